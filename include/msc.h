@@ -1,0 +1,176 @@
+/*
+ * msc.h -- C ABI of the MI355X Morse-Smale hot path (libmsc.so).
+ *
+ * Computes, for a scalar field sampled at the vertices of a 3D grid, the
+ * discrete gradient, its critical cells, and the 1-skeleton of the
+ * Morse-Smale complex, following Subhash, Pandey and Natarajan, "A GPU
+ * Parallel Algorithm for Computing Morse-Smale Complexes":
+ *   - gradient pairs, critical cells, index, V-paths: Section 2.2;
+ *   - gradient assignment per vertex lower star (the locally independent
+ *     rule of Robins, Wood and Sheppard cited in Section 1.1), first step of
+ *     Section 3;
+ *   - critical-cell compaction with block counts, prefix sum and stream
+ *     compaction: Section 3.5 ("Gradient pairs and critical points");
+ *   - saddle-extremum arcs by pointer jumping: Sections 3.4 and 3.5;
+ *   - 1-saddle/2-saddle reachability by frontier BFS: Sections 3.2 and 3.5;
+ *   - junction nodes, DAG minor, path counting by iterated sparse products:
+ *     Section 3.3 and Section 3.5 ("Gradient path counting").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Field layout.  `f` holds nx*ny*nz float32 values, x fastest: vertex
+ *   (x, y, z) has id v = x + nx*(y + ny*z).  Values must be finite.
+ * Vertex order.  u precedes v iff (f(u), id(u)) < (f(v), id(v)); -0.0 and
+ *   +0.0 compare equal (simulation of simplicity by vertex id).
+ * Cells.  A cell at refined coordinates (X, Y, Z), 0 <= X <= 2nx-2 etc., has
+ *   id 8*v(X>>1, Y>>1, Z>>1) + (X&1) + 2(Y&1) + 4(Z&1); its dimension
+ *   (= index when critical) is the number of odd coordinates.
+ * Gradient word.  One uint32 per vertex v; nibble k = a + 2b + 4c describes
+ *   the cell at refined (2x+a, 2y+b, 2z+c):
+ *     1..6  paired with the cell at refined offset +X, -X, +Y, -Y, +Z, -Z;
+ *     7     the cell does not exist (outside the grid);
+ *     8+d   critical, and its highest vertex is v + (d&1, d>>1&1, d>>2&1).
+ * Critical list.  Sorted by (index, cell id).  The rank of a critical cell is
+ *   its position among the critical cells of its index; ranks are the row and
+ *   column numbers of the arc matrices.
+ * Arc matrices.  CSR, rows ascending, columns ascending within a row, values
+ *   are numbers of gradient paths as exact unsigned 64-bit integers that
+ *   saturate at 2^64-1.  M10: 1-saddle x minimum.  M21: 2-saddle x 1-saddle.
+ *   M32: maximum x 2-saddle.  Each is also given transposed.  Paths from a
+ *   2-saddle that leave the grid through its boundary are dropped (Section
+ *   3.5: paths that do not terminate at a critical cell are discarded).
+ * Memory.  Every pointer argument is a device pointer unless documented as
+ *   host.  Inputs are read on the context's stream and only need to stay
+ *   valid until that stream passes the call.  Outputs documented as
+ *   context-owned stay valid until the next call on the same context.
+ * Streams and synchronisation.  All device work is ordered on the context's
+ *   stream.  Calls that size host-visible outputs (ms_critical, ms_connect,
+ *   ms_complex) synchronise that stream before they return.
+ * Errors.  Every entry point returns an ms_status; no C++ exception or abort
+ *   crosses the ABI.  ms_last_error gives a text for the last failing call.
+ *   A context is not thread-safe; use one context per host thread.
+ */
+#ifndef MSC_H
+#define MSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MS_OK = 0,
+    MS_ERR_INVALID_ARG = 1, /* null pointer, dims < 1 */
+    MS_ERR_NONFINITE = 2,   /* NaN or +-Inf in the field */
+    MS_ERR_TOO_LARGE = 3,   /* nx*ny*nz > 2^29 (cell ids are 32-bit) */
+    MS_ERR_CAPACITY = 4,    /* caller buffer too small; required sizes reported */
+    MS_ERR_OOM = 5,         /* device allocation failed */
+    MS_ERR_HIP = 6,         /* a HIP runtime call failed */
+    MS_ERR_INTERNAL = 7     /* an internal consistency check failed */
+} ms_status;
+
+/* Vertex counts along x, y, z; each >= 1. */
+typedef struct {
+    int64_t nx, ny, nz;
+} ms_dims;
+
+typedef struct ms_ctx ms_ctx;
+
+/* Creates a context bound to `stream` (a hipStream_t; NULL = the default
+ * stream) on the current device.  The context owns its workspace, which grows
+ * to the largest problem seen and is reused by later calls. */
+ms_status ms_ctx_create(ms_ctx** out, void* stream);
+void ms_ctx_destroy(ms_ctx* ctx);
+/* Rebinds the context to another stream (hipStream_t) of the same device. */
+ms_status ms_ctx_set_stream(ms_ctx* ctx, void* stream);
+/* Text describing the last non-OK status returned on this context. */
+const char* ms_last_error(const ms_ctx* ctx);
+
+/* Discrete gradient (Section 2.2 definitions; per-vertex lower-star pairing
+ * as cited in Section 1.1 and used in the first step of Section 3).
+ *   d_f    : device, nx*ny*nz float32, layout above.
+ *   d_grad : device, nx*ny*nz uint32, caller-owned; receives the gradient
+ *            words.
+ * Errors: MS_ERR_INVALID_ARG, MS_ERR_TOO_LARGE, MS_ERR_NONFINITE (d_grad is
+ * then unspecified).  Synchronises the stream (to report non-finite input). */
+ms_status ms_gradient(ms_ctx* ctx, const float* d_f, ms_dims dims, uint32_t* d_grad);
+
+/* Critical-cell list, structure of arrays, all device, caller-owned. */
+typedef struct {
+    uint32_t* id;      /* cell ids */
+    uint8_t* index;    /* index = dimension, 0..3 */
+    float* value;      /* f at the cell's highest vertex (bit copy) */
+    uint32_t* vmax;    /* id of the cell's highest vertex */
+    int64_t capacity;  /* entries available in each array */
+} ms_crit;
+
+/* Critical-cell extraction and compaction (Section 3.5, "Gradient pairs and
+ * critical points": marking, block counts, prefix sum, stream compaction).
+ *   d_f, d_grad : device inputs (d_grad as produced by ms_gradient).
+ *   out         : caller-owned arrays; may be NULL to query counts only.
+ *   h_count     : host, receives the number of critical cells per index.
+ * Output: the critical list sorted by (index, id) in out->[0, sum(h_count)).
+ * Errors: MS_ERR_CAPACITY when sum(h_count) > out->capacity (counts are
+ * written, outputs untouched; retry with larger arrays). */
+ms_status ms_critical(ms_ctx* ctx, const float* d_f, const uint32_t* d_grad, ms_dims dims,
+                      const ms_crit* out, int64_t h_count[4]);
+
+/* A CSR matrix in device memory, context-owned. */
+typedef struct {
+    int64_t nrows, ncols, nnz;
+    int64_t* rowptr;   /* nrows + 1 */
+    uint32_t* col;     /* nnz */
+    uint64_t* val;     /* nnz */
+} ms_csr;
+
+/* Counters of the connection phase (Section 5 reports the same kinds of
+ * statistics: junction counts, matrix sizes, product iterations). */
+typedef struct {
+    int64_t pj_rounds_vertex, pj_rounds_cube; /* pointer-jumping rounds */
+    int64_t bfs_levels, reachable;            /* BFS levels, reachable 1-2 pairs */
+    int64_t junctions;
+    int64_t nnz_a, nnz_b, nnz_bstar, nnz_d;   /* DAG-minor matrices (Section 3.3) */
+    int64_t spgemm_iters, nnz_astar, products;
+} ms_stats;
+
+typedef struct {
+    ms_csr m10, m10t;  /* 1-saddle x minimum, and minimum x 1-saddle */
+    ms_csr m21, m21t;  /* 2-saddle x 1-saddle, and 1-saddle x 2-saddle */
+    ms_csr m32, m32t;  /* maximum x 2-saddle, and 2-saddle x maximum */
+    int64_t n_saturated; /* entries of M21 equal to 2^64-1 (not an error) */
+    ms_stats stats;
+} ms_arcs;
+
+/* 1-skeleton (Sections 3.1-3.5): saddle-extremum arcs by pointer jumping;
+ * saddle-saddle arcs by frontier BFS, junction nodes, DAG minor and iterated
+ * sparse integer products.
+ *   d_grad       : device gradient words.
+ *   d_crit_id    : device, the critical cell ids sorted by (index, id), as
+ *                  written by ms_critical (sum(h_count) entries).
+ *   h_count      : host, critical counts per index.
+ *   out          : host struct; receives context-owned device matrices valid
+ *                  until the next call on this context.
+ * Errors: MS_ERR_INVALID_ARG, MS_ERR_OOM, MS_ERR_INTERNAL (e.g. a crit list
+ * that does not match the gradient). */
+ms_status ms_connect(ms_ctx* ctx, const uint32_t* d_grad, ms_dims dims, const uint32_t* d_crit_id,
+                     const int64_t h_count[4], ms_arcs* out);
+
+typedef struct {
+    uint32_t* grad;    /* device, nx*ny*nz gradient words, context-owned */
+    ms_crit crit;      /* context-owned critical list */
+    int64_t count[4];
+    ms_arcs arcs;      /* context-owned arc matrices */
+} ms_result;
+
+/* The whole hot path: ms_gradient, ms_critical and ms_connect on
+ * context-owned buffers.  d_f is a device field; all results stay on the
+ * device, owned by the context until its next call. */
+ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSC_H */

@@ -1,0 +1,105 @@
+// Shared definitions of the HIP path: grid indexing, cell-id arithmetic on
+// the refined grid, gradient-word decoding, launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace msc {
+
+// Gradient-word nibble codes (see include/msc.h).
+constexpr uint32_t NB_NONE = 7u;
+constexpr uint32_t NB_CRIT = 8u;
+
+// Label flag used by pointer jumping: set on a root (the low bits then hold
+// the rank of the extremum), clear on a plain successor pointer.
+constexpr uint32_t ROOT_FLAG = 0x80000000u;
+constexpr uint32_t EXIT_LABEL = 0xFFFFFFFFu;  // a (2,3) path that leaves the grid
+constexpr uint32_t NOT_JUNCTION = 0xFFFFFFFFu;
+
+// floor(n / d) for 0 <= n < 2^30 via one 64-bit multiply and shift
+// (Granlund-Montgomery: m = ceil(2^(30+l) / d), l = ceil(log2 d)).
+struct FastDiv {
+    uint64_t m;
+    uint32_t s;
+    uint32_t d;
+    static FastDiv make(uint32_t d) {
+        FastDiv r;
+        uint32_t l = 0;
+        while ((1ull << l) < d) l++;
+        r.s = 30 + l;
+        r.m = ((1ull << r.s) + d - 1) / d;
+        r.d = d;
+        return r;
+    }
+    __host__ __device__ inline uint32_t div(uint32_t n) const { return (uint32_t)(((uint64_t)n * m) >> s); }
+};
+
+struct Grid {
+    uint32_t n[3];       // vertex counts x, y, z
+    uint32_t stride[3];  // 1, nx, nx*ny
+    uint32_t nv;
+    FastDiv dx, dxy;
+    static Grid make(int64_t nx, int64_t ny, int64_t nz) {
+        Grid g;
+        g.n[0] = (uint32_t)nx; g.n[1] = (uint32_t)ny; g.n[2] = (uint32_t)nz;
+        g.stride[0] = 1; g.stride[1] = (uint32_t)nx; g.stride[2] = (uint32_t)(nx * ny);
+        g.nv = (uint32_t)(nx * ny * nz);
+        g.dx = FastDiv::make((uint32_t)nx);
+        g.dxy = FastDiv::make((uint32_t)(nx * ny));
+        return g;
+    }
+    __device__ inline void coords(uint32_t v, uint32_t c[3]) const {
+        uint32_t z = dxy.div(v);
+        uint32_t r = v - z * stride[2];
+        uint32_t y = dx.div(r);
+        c[0] = r - y * stride[1];
+        c[1] = y;
+        c[2] = z;
+    }
+};
+
+__device__ inline uint32_t nib_of(uint32_t word, uint32_t k) { return (word >> (4u * k)) & 15u; }
+
+// Cell one refined step from (w, k) along `axis` with sign `s` (+1 / -1).
+// Returns false when the step leaves the grid.  `c` holds the coordinates of
+// vertex w.
+__device__ inline bool cell_step(const Grid& g, uint32_t w, uint32_t k, const uint32_t c[3], int axis, int s,
+                                 uint32_t& w2, uint32_t& k2) {
+    uint32_t bit = 1u << axis;
+    if (k & bit) {
+        k2 = k & ~bit;
+        w2 = (s > 0) ? w + g.stride[axis] : w;
+        return true;
+    }
+    k2 = k | bit;
+    if (s > 0) {
+        if (c[axis] + 1 >= g.n[axis]) return false;
+        w2 = w;
+    } else {
+        if (c[axis] == 0) return false;
+        w2 = w - g.stride[axis];
+    }
+    return true;
+}
+
+// Saturating unsigned 64-bit arithmetic: every sum and product of path
+// counts equals min(true value, 2^64-1), whatever the evaluation order.
+__device__ inline uint64_t sat_add(uint64_t a, uint64_t b) {
+    uint64_t s = a + b;
+    return s < a ? ~0ull : s;
+}
+__device__ inline uint64_t sat_mul(uint64_t a, uint64_t b) {
+    if (__umul64hi(a, b) != 0) return ~0ull;
+    return a * b;
+}
+
+inline unsigned grid_blocks(uint64_t n, unsigned block) {
+    uint64_t b = (n + block - 1) / block;
+    if (b < 1) b = 1;
+    return (unsigned)b;
+}
+
+}  // namespace msc

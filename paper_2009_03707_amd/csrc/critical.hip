@@ -1,0 +1,142 @@
+// Critical-cell extraction and compaction (Section 3.5, "Gradient pairs and
+// critical points": mark unpaired cells, per-block counts, prefix sum over
+// the blocks, stream compaction into the critical-point list).
+//
+// Canonical order is (index, cell id), and cell ids are word-major
+// (8 * vertex + nibble), so the compaction walks the gradient words in memory
+// order.  Pass 1 counts the critical cells of each index per workgroup tile;
+// a device scan turns the counts into offsets; pass 2 re-reads the tile and
+// scatters each critical cell to its index segment in order (stable: the
+// workgroup-local ranks come from an exclusive scan, never from atomics).
+#include "prims.h"
+
+namespace msc {
+namespace {
+
+constexpr int CT = 256;          // threads
+constexpr int CWPT = 8;          // words per thread (contiguous)
+constexpr int CTILE = CT * CWPT; // words per tile
+
+// Per-index counts of the critical nibbles of one word, packed in four
+// 16-bit lanes (index = number of set bits of the nibble position).
+__device__ __forceinline__ uint64_t crit_counts(uint32_t w) {
+    uint32_t isc = (w >> 3) & 0x11111111u;  // bit 4k set <=> nibble k >= 8
+    uint64_t c0 = isc & 1u;
+    uint64_t c1 = (uint64_t)__builtin_popcount(isc & 0x00010110u);
+    uint64_t c2 = (uint64_t)__builtin_popcount(isc & 0x01101000u);
+    uint64_t c3 = (isc >> 28) & 1u;
+    return c0 | (c1 << 16) | (c2 << 32) | (c3 << 48);
+}
+
+__global__ __launch_bounds__(CT) void crit_count(const uint32_t* __restrict__ grad, uint64_t nv,
+                                                 uint64_t* __restrict__ blk) {
+    __shared__ uint64_t sc[CT / WAVE + 1];
+    uint64_t base = (uint64_t)blockIdx.x * CTILE + (uint64_t)threadIdx.x * CWPT;
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < CWPT; i++)
+        if (base + i < nv) s += crit_counts(grad[base + i]);
+    uint64_t tot;
+    block_excl_scan<uint64_t, CT>(s, sc, tot);
+    if (threadIdx.x == 0) {
+        // unpack into four per-index arrays laid out [index][block]
+        uint64_t nb = gridDim.x;
+        for (int k = 0; k < 4; k++) blk[(uint64_t)k * nb + blockIdx.x] = (tot >> (16 * k)) & 0xFFFFu;
+    }
+}
+
+// after the scan of the [index][block] counts: segment starts and totals
+__global__ void crit_totals(const uint64_t* __restrict__ excl, uint64_t nb, const uint64_t* __restrict__ blk,
+                            uint64_t* __restrict__ out /* [0..3] count, [4..7] segment start */) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint64_t start = 0;
+    for (int k = 0; k < 4; k++) {
+        // exclusive offsets are global over the concatenated [index][block]
+        // array; the count of index k is the difference of consecutive segment starts
+        uint64_t seg_begin = excl[(uint64_t)k * nb];
+        uint64_t seg_end = (k < 3) ? excl[(uint64_t)(k + 1) * nb] : excl[4 * nb - 1] + blk[4 * nb - 1];
+        out[k] = seg_end - seg_begin;
+        out[4 + k] = start;
+        start += out[k];
+    }
+}
+
+__global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f, const uint32_t* __restrict__ grad,
+                                                   Grid g, const uint64_t* __restrict__ excl,
+                                                   uint32_t* __restrict__ o_id, uint8_t* __restrict__ o_index,
+                                                   float* __restrict__ o_value, uint32_t* __restrict__ o_vmax) {
+    __shared__ uint64_t sc[CT / WAVE + 1];
+    const uint64_t nv = g.nv;
+    const uint64_t nb = gridDim.x;
+    uint64_t base = (uint64_t)blockIdx.x * CTILE + (uint64_t)threadIdx.x * CWPT;
+    uint32_t w[CWPT];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < CWPT; i++) {
+        w[i] = (base + i < nv) ? grad[base + i] : 0u;
+        s += crit_counts(w[i]);
+    }
+    uint64_t tot;
+    uint64_t ex = block_excl_scan<uint64_t, CT>(s, sc, tot);
+    if (tot == 0) return;
+    uint64_t pos[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) pos[k] = excl[(uint64_t)k * nb + blockIdx.x] + ((ex >> (16 * k)) & 0xFFFFu);
+#pragma unroll
+    for (int i = 0; i < CWPT; i++) {
+        uint32_t word = w[i];
+        if (((word >> 3) & 0x11111111u) == 0) continue;
+        uint32_t v = (uint32_t)(base + i);
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            uint32_t nib = nib_of(word, k);
+            if (nib < NB_CRIT) continue;
+            uint32_t idx = (uint32_t)__builtin_popcount(k);
+            uint32_t d = nib - NB_CRIT;
+            uint32_t vm = v + ((d & 1u) ? g.stride[0] : 0u) + ((d & 2u) ? g.stride[1] : 0u) +
+                          ((d & 4u) ? g.stride[2] : 0u);
+            uint64_t p = pos[idx]++;
+            o_id[p] = 8u * v + k;
+            o_index[p] = (uint8_t)idx;
+            o_value[p] = f[vm];
+            o_vmax[p] = vm;
+        }
+    }
+}
+
+}  // namespace
+
+size_t crit_tmp_elems(uint64_t nv) {
+    uint64_t nb = (nv + CTILE - 1) / CTILE;
+    return 2 * 4 * nb + 8 + scan_tmp_elems(4 * nb);
+}
+
+// Pass 1 + scan.  tmp layout: [4*nb counts][4*nb exclusive offsets][8 totals][scan tmp].
+// d_totals (8 uint64 inside tmp) receives per-index counts and segment starts.
+hipError_t launch_crit_count(const uint32_t* grad, const Grid& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s) {
+    uint64_t nb = (g.nv + CTILE - 1) / CTILE;
+    uint64_t* blk = tmp;
+    uint64_t* excl = tmp + 4 * nb;
+    uint64_t* tot = tmp + 8 * nb;
+    uint64_t* stmp = tmp + 8 * nb + 8;
+    hipLaunchKernelGGL(crit_count, dim3((unsigned)nb), dim3(CT), 0, s, grad, (uint64_t)g.nv, blk);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_excl_u64(blk, excl, 4 * nb, stmp, (uint64_t*)nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(crit_totals, dim3(1), dim3(64), 0, s, (const uint64_t*)excl, nb, (const uint64_t*)blk, tot);
+    *d_totals = tot;
+    return hipGetLastError();
+}
+
+// Pass 2: the exclusive offsets over [index][block] are global positions in
+// the (index, id)-sorted list because index segments are concatenated.
+hipError_t launch_crit_scatter(const float* f, const uint32_t* grad, const Grid& g, const uint64_t* tmp, uint32_t* id,
+                               uint8_t* index, float* value, uint32_t* vmax, hipStream_t s) {
+    uint64_t nb = (g.nv + CTILE - 1) / CTILE;
+    const uint64_t* excl = tmp + 4 * nb;
+    hipLaunchKernelGGL(crit_scatter, dim3((unsigned)nb), dim3(CT), 0, s, f, grad, g, excl, id, index, value, vmax);
+    return hipGetLastError();
+}
+
+}  // namespace msc

@@ -1,0 +1,77 @@
+// Host-side context of the C ABI: stream, grow-only named device buffers,
+// pinned host scratch for small readbacks, last-error text.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string.h>
+
+#include <map>
+#include <string>
+
+#include "../../include/msc.h"
+#include "common.h"
+
+struct ms_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    struct Buf {
+        void* p = nullptr;
+        size_t cap = 0;
+    };
+    std::map<std::string, Buf> bufs;
+    uint64_t* h_small = nullptr;  // pinned host scratch (64 words)
+};
+
+namespace msc {
+
+struct Fail {
+    ms_status st;
+};
+
+// Device buffer `name` of at least `count` elements of T (grows, never shrinks).
+template <typename T>
+T* buf(ms_ctx* c, const char* name, size_t count) {
+    size_t bytes = count * sizeof(T);
+    if (bytes == 0) bytes = sizeof(T);
+    ms_ctx::Buf& b = c->bufs[name];
+    if (b.cap < bytes) {
+        if (b.p) {
+            (void)hipStreamSynchronize(c->stream);
+            (void)hipFree(b.p);
+            b.p = nullptr;
+            b.cap = 0;
+        }
+        size_t want = bytes + bytes / 4 + 256;
+        if (hipMalloc(&b.p, want) != hipSuccess) {
+            (void)hipGetLastError();
+            c->err = std::string("device allocation of ") + std::to_string(want) + " bytes failed for " + name;
+            throw Fail{MS_ERR_OOM};
+        }
+        b.cap = want;
+    }
+    return (T*)b.p;
+}
+
+inline void check(ms_ctx* c, hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        c->err = std::string(what) + ": " + hipGetErrorString(e);
+        throw Fail{MS_ERR_HIP};
+    }
+}
+
+inline void fail(ms_ctx* c, ms_status st, const std::string& msg) {
+    c->err = msg;
+    throw Fail{st};
+}
+
+// Copies `n` uint64 words from device to the pinned scratch and waits.
+inline uint64_t* readback(ms_ctx* c, const uint64_t* d, size_t n) {
+    check(c, hipMemcpyAsync(c->h_small, d, n * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream), "readback");
+    check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    return c->h_small;
+}
+
+}  // namespace msc

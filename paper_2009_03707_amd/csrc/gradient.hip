@@ -1,0 +1,309 @@
+// Discrete gradient by per-vertex lower-star pairing.
+//
+// The paper assigns gradient pairs in a first, embarrassingly parallel step
+// (Section 3, first step; Section 3.5, "Gradient pairs and critical
+// points").  The pairing rule is the locally independent lower-star rule of
+// Robins, Wood and Sheppard that the paper cites (Section 1.1): the cells
+// whose highest vertex is x are paired among themselves by two priority
+// queues ordered by the cells' vertex values.
+//
+// MI355X design: one workgroup computes the gradient words of an
+// OX x OY x OZ block of vertices.  The field tile (with a one-vertex halo on
+// each side plus one extra vertex on the high side) is staged in LDS as
+// order-preserving integer keys; every vertex of the block and of its
+// high-side halo runs the lower-star pairing in registers with bitmask
+// queues; each cell's nibble is OR-ed into an LDS word tile (each nibble is
+// written by exactly one lower star), which is then stored coalesced.
+#include "common.h"
+
+namespace msc {
+namespace {
+
+constexpr int OX = 16, OY = 8, OZ = 4;           // output words per block
+constexpr int FX = OX + 3, FY = OY + 3, FZ = OZ + 3;  // staged field tile
+constexpr int NF = FX * FY * FZ;
+constexpr int NW = OX * OY * OZ;
+constexpr int PX = OX + 1, PY = OY + 1, PZ = OZ + 1;  // lower stars computed
+constexpr int NPLS = PX * PY * PZ;
+constexpr int THREADS = 256;
+constexpr uint32_t KEY_OUT = 0xFFFFFFFFu;  // vertex outside the grid
+constexpr uint32_t CENTER = 13;
+// edge cells of the star: offsets (+-1,0,0), (0,+-1,0), (0,0,+-1)
+constexpr uint32_t EDGES = (1u << 4) | (1u << 10) | (1u << 12) | (1u << 14) | (1u << 16) | (1u << 22);
+
+// Star cell j <-> offset (ox, oy, oz) in {-1,0,1}^3, j = (ox+1) + 3(oy+1) + 9(oz+1).
+__host__ __device__ constexpr int off_x(int j) { return j % 3 - 1; }
+__host__ __device__ constexpr int off_y(int j) { return (j / 3) % 3 - 1; }
+__host__ __device__ constexpr int off_z(int j) { return j / 9 - 1; }
+
+// Vertices of star cell j other than the centre: every d != 0 with d_i in {0, o_i}.
+__host__ __device__ constexpr uint32_t vert_mask(int j) {
+    uint32_t m = 0;
+    int ox = off_x(j), oy = off_y(j), oz = off_z(j);
+    for (int dz = 0; dz <= 1; dz++)
+        for (int dy = 0; dy <= 1; dy++)
+            for (int dx = 0; dx <= 1; dx++) {
+                int a = dx * ox, b = dy * oy, c = dz * oz;
+                if ((dx && !ox) || (dy && !oy) || (dz && !oz)) continue;
+                if (a == 0 && b == 0 && c == 0) continue;
+                m |= 1u << ((a + 1) + 3 * (b + 1) + 9 * (c + 1));
+            }
+    return m;
+}
+// Facets of star cell j that contain the centre: zero one nonzero offset.
+__host__ __device__ constexpr uint32_t facet_mask(int j) {
+    uint32_t m = 0;
+    if (off_x(j)) m |= 1u << (j - off_x(j));
+    if (off_y(j)) m |= 1u << (j - 3 * off_y(j));
+    if (off_z(j)) m |= 1u << (j - 9 * off_z(j));
+    return m;
+}
+// Cofacets of star cell j inside the star: set one zero offset to +-1.
+__host__ __device__ constexpr uint32_t cofacet_mask(int j) {
+    uint32_t m = 0;
+    if (!off_x(j)) m |= (1u << (j - 1)) | (1u << (j + 1));
+    if (!off_y(j)) m |= (1u << (j - 3)) | (1u << (j + 3));
+    if (!off_z(j)) m |= (1u << (j - 9)) | (1u << (j + 9));
+    return m;
+}
+// Destination of star cell j in the gradient words: word at centre +
+// (min(ox,0), min(oy,0), min(oz,0)), nibble |ox| + 2|oy| + 4|oz|.
+// Packed: bit0..2 = (ox<0, oy<0, oz<0) (also the critical corner), bits 3..5 = nibble.
+__host__ __device__ constexpr uint32_t dest_desc(int j) {
+    int ox = off_x(j), oy = off_y(j), oz = off_z(j);
+    uint32_t corner = (ox < 0 ? 1u : 0u) | (oy < 0 ? 2u : 0u) | (oz < 0 ? 4u : 0u);
+    uint32_t k = (ox ? 1u : 0u) | (oy ? 2u : 0u) | (oz ? 4u : 0u);
+    return corner | (k << 3);
+}
+
+struct Tables {
+    uint32_t fac[27], cof[27], desc[27];
+};
+
+__device__ __forceinline__ uint32_t float_key(uint32_t u) {
+    if (u == 0x80000000u) u = 0u;  // -0.0 == +0.0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+struct Star {
+    int lx, ly, lz;          // position in the block (0..OX etc.)
+    uint32_t* words;         // LDS word tile
+    const Tables* tab;
+    __device__ void emit(uint32_t j, uint32_t nib) const {
+        uint32_t d = tab->desc[j];
+        int wx = lx - (int)(d & 1u), wy = ly - (int)((d >> 1) & 1u), wz = lz - (int)((d >> 2) & 1u);
+        if ((unsigned)wx < (unsigned)OX && (unsigned)wy < (unsigned)OY && (unsigned)wz < (unsigned)OZ)
+            atomicOr(&words[wx + OX * (wy + OY * wz)], nib << (4u * (d >> 3)));
+    }
+    __device__ void emit_pair(uint32_t a, uint32_t b) const {  // a facet, b cofacet
+        int diff = (int)b - (int)a;
+        int ad = diff < 0 ? -diff : diff;
+        uint32_t axis = ad == 1 ? 0u : (ad == 3 ? 1u : 2u);
+        uint32_t neg = diff < 0 ? 1u : 0u;
+        emit(a, 1u + 2u * axis + neg);
+        emit(b, 1u + 2u * axis + (1u - neg));
+    }
+    __device__ void emit_crit(uint32_t j) const { emit(j, NB_CRIT + (tab->desc[j] & 7u)); }
+};
+
+__device__ __forceinline__ uint32_t ctz32(uint32_t x) { return (uint32_t)__builtin_ctz(x); }
+
+// argmin of the per-lane cell keys over the set bits of `m` (m != 0)
+__device__ __forceinline__ uint32_t argmin_key(uint32_t m, const uint32_t* kk, int tid) {
+    uint32_t best = 0, bk = 0xFFFFFFFFu;
+    while (m) {
+        uint32_t j = ctz32(m);
+        m &= m - 1;
+        uint32_t k = kk[j * THREADS + tid];
+        if (k < bk) { bk = k; best = j; }
+    }
+    return best;
+}
+
+// cofacets b of x (inside the lower star, unclassified) with exactly one
+// unclassified facet
+__device__ __forceinline__ uint32_t ready_cofacets(uint32_t x, uint32_t LS, uint32_t C, const Tables* tab) {
+    uint32_t out = 0;
+    uint32_t m = tab->cof[x] & LS & ~C;
+    while (m) {
+        uint32_t b = ctz32(m);
+        m &= m - 1;
+        if (__builtin_popcount(tab->fac[b] & LS & ~C) == 1) out |= 1u << b;
+    }
+    return out;
+}
+
+template <int J>
+struct Unroll {
+    template <typename F>
+    __device__ __forceinline__ static void run(F&& fn) {
+        Unroll<J - 1>::run(fn);
+        fn(std::integral_constant<int, J - 1>());
+    }
+};
+template <>
+struct Unroll<0> {
+    template <typename F>
+    __device__ __forceinline__ static void run(F&&) {}
+};
+
+__device__ void lower_star(const uint32_t* fk, int fidx, const Star& st, uint32_t* kk, int tid) {
+    uint32_t K[27];
+    Unroll<27>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int o = off_x(j) + FX * (off_y(j) + FY * off_z(j));
+        K[j] = fk[fidx + o];
+    });
+    const uint32_t kc = K[CENTER];
+    uint32_t lower = 0;
+    Unroll<27>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (j != (int)CENTER) {
+            bool lw = (j < (int)CENTER) ? (K[j] <= kc) : (K[j] < kc);
+            lower |= (lw ? 1u : 0u) << j;
+        }
+    });
+    // cells of the lower star: all their non-centre vertices are lower
+    uint32_t LS = 1u << CENTER;
+    Unroll<27>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (j != (int)CENTER) {
+            constexpr uint32_t vm = vert_mask(j);
+            LS |= ((vm & ~lower) == 0 ? 1u : 0u) << j;
+        }
+    });
+    if ((LS & EDGES) == 0) {  // no lower neighbour: a minimum
+        st.emit_crit(CENTER);
+        return;
+    }
+    // rank of every neighbour in the vertex order (ties broken by id, which
+    // among the neighbours of one vertex is the order of the star index)
+    uint32_t rk[27];
+    Unroll<27>::run([&](auto jc) { rk[decltype(jc)::value] = 0; });
+    Unroll<27>::run([&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        if constexpr (b != (int)CENTER) {
+            Unroll<b>::run([&](auto ac) {
+                constexpr int a = decltype(ac)::value;
+                if constexpr (a != (int)CENTER) {
+                    bool c = K[a] <= K[b];  // a precedes b
+                    rk[b] += c ? 1u : 0u;
+                    rk[a] += c ? 0u : 1u;
+                }
+            });
+        }
+    });
+    // cell keys: bit set of the ranks of the cell's other vertices; comparing
+    // them as integers is the lexicographic comparison of the descending
+    // vertex lists with a proper prefix smaller
+    Unroll<27>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (j != (int)CENTER) {
+            uint32_t key = 0;
+            Unroll<27>::run([&](auto vc) {
+                constexpr int v = decltype(vc)::value;
+                if constexpr (((vert_mask(j) >> v) & 1u) != 0) key |= 1u << rk[v];
+            });
+            kk[j * THREADS + tid] = key;
+        }
+    });
+    const Tables* tab = st.tab;
+    uint32_t C = 1u << CENTER;  // classified cells
+    uint32_t E = LS & EDGES;
+    uint32_t delta = argmin_key(E, kk, tid);
+    st.emit_pair(CENTER, delta);
+    C |= 1u << delta;
+    uint32_t PZ = E & ~(1u << delta);
+    uint32_t PO = ready_cofacets(delta, LS, C, tab);
+    for (;;) {
+        while (PO) {
+            uint32_t a = argmin_key(PO, kk, tid);
+            PO &= ~(1u << a);
+            if (C & (1u << a)) continue;
+            uint32_t uf = tab->fac[a] & LS & ~C;
+            if (!uf) {
+                PZ |= 1u << a;
+                continue;
+            }
+            uint32_t p = ctz32(uf);
+            st.emit_pair(p, a);
+            C |= (1u << a) | (1u << p);
+            PZ &= ~(1u << p);
+            PO |= ready_cofacets(a, LS, C, tab) | ready_cofacets(p, LS, C, tab);
+        }
+        PZ &= ~C;
+        if (!PZ) break;
+        uint32_t g = argmin_key(PZ, kk, tid);
+        PZ &= ~(1u << g);
+        st.emit_crit(g);
+        C |= 1u << g;
+        PO |= ready_cofacets(g, LS, C, tab);
+    }
+}
+
+__global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restrict__ f, Grid g, uint32_t ntx,
+                                                           uint32_t nty, uint32_t* __restrict__ grad,
+                                                           int* __restrict__ err) {
+    __shared__ uint32_t fk[NF];
+    __shared__ uint32_t words[NW];
+    __shared__ uint32_t kk[27 * THREADS];
+    __shared__ Tables tab;
+    const int tid = threadIdx.x;
+    const uint32_t t = blockIdx.x;
+    const uint32_t tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
+    const int x0 = (int)(tx * OX), y0 = (int)(ty * OY), z0 = (int)(tz * OZ);
+    const int nx = (int)g.n[0], ny = (int)g.n[1], nz = (int)g.n[2];
+
+    if (tid < 27) {
+        tab.fac[tid] = facet_mask(tid);
+        tab.cof[tid] = cofacet_mask(tid);
+        tab.desc[tid] = dest_desc(tid);
+    }
+    bool bad = false;
+    for (int i = tid; i < NF; i += THREADS) {
+        int fx = i % FX, fy = (i / FX) % FY, fz = i / (FX * FY);
+        int x = x0 - 1 + fx, y = y0 - 1 + fy, z = z0 - 1 + fz;
+        uint32_t key = KEY_OUT;
+        if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
+            uint32_t u = __float_as_uint(f[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * (size_t)z)]);
+            if ((u & 0x7F800000u) == 0x7F800000u) bad = true;
+            key = float_key(u);
+        }
+        fk[i] = key;
+    }
+    if (bad) atomicOr(err, 1);
+    for (int i = tid; i < NW; i += THREADS) words[i] = 0u;
+    __syncthreads();
+
+    for (int i = tid; i < NPLS; i += THREADS) {
+        int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
+        int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+        if (x >= nx || y >= ny || z >= nz) continue;
+        Star st{lx, ly, lz, words, &tab};
+        int fidx = (lx + 1) + FX * ((ly + 1) + FY * (lz + 1));
+        lower_star(fk, fidx, st, kk, tid);
+    }
+    __syncthreads();
+
+    for (int i = tid; i < NW; i += THREADS) {
+        int wx = i % OX, wy = (i / OX) % OY, wz = i / (OX * OY);
+        int x = x0 + wx, y = y0 + wy, z = z0 + wz;
+        if (x >= nx || y >= ny || z >= nz) continue;
+        uint32_t w = words[i];
+        if (x == nx - 1) w |= 0x70707070u;  // cells with an odd X beyond the grid
+        if (y == ny - 1) w |= 0x77007700u;
+        if (z == nz - 1) w |= 0x77770000u;
+        grad[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * (size_t)z)] = w;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_gradient(const float* f, const Grid& g, uint32_t* grad, int* err, hipStream_t s) {
+    uint32_t ntx = (g.n[0] + OX - 1) / OX, nty = (g.n[1] + OY - 1) / OY, ntz = (g.n[2] + OZ - 1) / OZ;
+    uint64_t nb = (uint64_t)ntx * nty * ntz;
+    hipLaunchKernelGGL(grad_lowerstar, dim3((unsigned)nb), dim3(THREADS), 0, s, f, g, ntx, nty, grad, err);
+    return hipGetLastError();
+}
+
+}  // namespace msc

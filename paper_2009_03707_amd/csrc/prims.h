@@ -1,0 +1,69 @@
+// Wave64 / workgroup scan helpers and device-wide primitives (prefix sum,
+// stable radix sort, run-length merge) used by the compaction steps.
+#pragma once
+
+#include "common.h"
+
+namespace msc {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (WAVE - 1)); }
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T t = __shfl_up(x, d, WAVE);
+        if (lane >= d) x += t;
+    }
+    return x;
+}
+
+// Exclusive scan over a workgroup of NT threads (multiple of 64).  `scratch`
+// is LDS of at least NT/64 + 1 elements.  Returns the exclusive prefix;
+// `total` receives the workgroup sum.
+template <typename T, int NT>
+__device__ __forceinline__ T block_excl_scan(T x, T* scratch, T& total) {
+    constexpr int NWAVE = NT / WAVE;
+    const int lane = lane_id();
+    const int w = (int)threadIdx.x / WAVE;
+    T inc = wave_incl_scan(x);
+    __syncthreads();
+    if (lane == WAVE - 1) scratch[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int i = 0; i < NWAVE; i++) {
+            T v = scratch[i];
+            scratch[i] = run;
+            run += v;
+        }
+        scratch[NWAVE] = run;
+    }
+    __syncthreads();
+    total = scratch[NWAVE];
+    return inc - x + scratch[w];
+}
+
+// Device-wide exclusive prefix sum of n uint64 values (out may equal in);
+// writes the total to *d_total when non-null.  `tmp` needs
+// scan_tmp_elems(n) uint64 elements.
+size_t scan_tmp_elems(uint64_t n);
+hipError_t scan_excl_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, uint64_t* d_total,
+                         hipStream_t s);
+// Same for uint32 inputs producing uint64 prefixes.
+hipError_t scan_excl_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, uint64_t* d_total,
+                                hipStream_t s);
+
+// Stable LSD radix sort of (key, payload) pairs on the low `bits` bits of the
+// keys.  Buffers: keys/vals in (a), alternate (b); the result lands in (a) or
+// (b) -- `*result_in_b` tells which.  `tmp` needs radix_tmp_elems(n) uint64.
+size_t radix_tmp_elems(uint64_t n);
+hipError_t radix_sort_u64(uint64_t* keys_a, uint32_t* vals_a, uint64_t* keys_b, uint32_t* vals_b, uint64_t n,
+                          int bits, uint64_t* tmp, bool* result_in_b, hipStream_t s);
+hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, uint64_t n,
+                          int bits, uint64_t* tmp, bool* result_in_b, hipStream_t s);
+
+}  // namespace msc

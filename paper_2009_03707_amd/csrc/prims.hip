@@ -1,0 +1,206 @@
+// Device-wide prefix sum and stable LSD radix sort (the "prefix scan" and
+// "stream compaction" primitives of Section 2.3, written for wave64).
+#include "prims.h"
+
+namespace msc {
+namespace {
+
+constexpr int ST = 256;            // scan threads per workgroup
+constexpr int SI = 8;              // scan items per thread
+constexpr int STILE = ST * SI;
+
+template <typename TIn>
+__global__ __launch_bounds__(ST) void scan_reduce(const TIn* __restrict__ in, uint64_t n, uint64_t* __restrict__ part) {
+    __shared__ uint64_t sc[ST / WAVE + 1];
+    uint64_t base = (uint64_t)blockIdx.x * STILE;
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SI; i++) {
+        uint64_t j = base + (uint64_t)i * ST + threadIdx.x;
+        if (j < n) s += (uint64_t)in[j];
+    }
+    uint64_t tot;
+    block_excl_scan<uint64_t, ST>(s, sc, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// exclusive scan of one tile; adds `offset` (device, may be null); writes the
+// tile total to *total when non-null (single-tile case)
+template <typename TIn>
+__global__ __launch_bounds__(ST) void scan_tile(const TIn* __restrict__ in, uint64_t* __restrict__ out, uint64_t n,
+                                                const uint64_t* __restrict__ offsets, uint64_t* __restrict__ total) {
+    __shared__ uint64_t sc[ST / WAVE + 1];
+    uint64_t base = (uint64_t)blockIdx.x * STILE + (uint64_t)threadIdx.x * SI;
+    uint64_t v[SI];
+    uint64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < SI; i++) {
+        uint64_t j = base + i;
+        v[i] = j < n ? (uint64_t)in[j] : 0;
+        s += v[i];
+    }
+    uint64_t tot;
+    uint64_t ex = block_excl_scan<uint64_t, ST>(s, sc, tot);
+    if (offsets) ex += offsets[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < SI; i++) {
+        uint64_t j = base + i;
+        if (j < n) out[j] = ex;
+        ex += v[i];
+    }
+    if (total && threadIdx.x == 0) *total = tot;
+}
+
+template <typename TIn>
+hipError_t scan_impl(const TIn* in, uint64_t* out, uint64_t n, uint64_t* tmp, uint64_t* d_total, hipStream_t s) {
+    if (n <= (uint64_t)STILE) {
+        hipLaunchKernelGGL(scan_tile<TIn>, dim3(1), dim3(ST), 0, s, in, out, n, (const uint64_t*)nullptr, d_total);
+        return hipGetLastError();
+    }
+    uint64_t nb = (n + STILE - 1) / STILE;
+    hipLaunchKernelGGL(scan_reduce<TIn>, dim3((unsigned)nb), dim3(ST), 0, s, in, n, tmp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_impl<uint64_t>(tmp, tmp, nb, tmp + nb, d_total, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_tile<TIn>, dim3((unsigned)nb), dim3(ST), 0, s, in, out, n, (const uint64_t*)tmp,
+                       (uint64_t*)nullptr);
+    return hipGetLastError();
+}
+
+// ---- radix sort -----------------------------------------------------------
+
+constexpr int RT = 256;           // threads
+constexpr int RR = 16;            // rounds of RT keys per tile
+constexpr int RTILE = RT * RR;
+constexpr int RWAVES = RT / WAVE;
+
+template <typename K>
+__global__ __launch_bounds__(RT) void radix_hist(const K* __restrict__ keys, uint64_t n, int shift, uint64_t nblk,
+                                                 uint64_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t base = (uint64_t)blockIdx.x * RTILE;
+    for (int r = 0; r < RR; r++) {
+        uint64_t j = base + (uint64_t)r * RT + threadIdx.x;
+        if (j < n) atomicAdd(&h[(uint32_t)(keys[j] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+template <typename K>
+__global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                                    K* __restrict__ okeys, uint32_t* __restrict__ ovals, uint64_t n,
+                                                    int shift, uint64_t nblk, const uint64_t* __restrict__ offs) {
+    __shared__ uint64_t base_of[256];
+    __shared__ uint32_t wcnt[RWAVES][256];
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
+    base_of[tid] = offs[(uint64_t)tid * nblk + blockIdx.x];
+    const uint64_t lt = (1ull << lane) - 1ull;
+    uint64_t tbase = (uint64_t)blockIdx.x * RTILE;
+    for (int r = 0; r < RR; r++) {
+        for (int i = tid; i < RWAVES * 256; i += RT) (&wcnt[0][0])[i] = 0;
+        __syncthreads();
+        uint64_t j = tbase + (uint64_t)r * RT + tid;
+        bool valid = j < n;
+        K key = valid ? keys[j] : (K)0;
+        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            uint64_t bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        uint32_t wrank = (uint32_t)__popcll(peers & lt);
+        if (valid && wrank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint64_t pos = base_of[d] + wrank;
+            for (int q = 0; q < w; q++) pos += wcnt[q][d];
+            okeys[pos] = key;
+            ovals[pos] = vals[j];
+        }
+        __syncthreads();
+        {
+            uint32_t add = 0;
+            for (int q = 0; q < RWAVES; q++) add += wcnt[q][tid];
+            base_of[tid] += add;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename K>
+hipError_t radix_impl(K* ka, uint32_t* va, K* kb, uint32_t* vb, uint64_t n, int bits, uint64_t* tmp, bool* in_b,
+                      hipStream_t s) {
+    *in_b = false;
+    if (n <= 1 || bits <= 0) return hipSuccess;
+    uint64_t nblk = (n + RTILE - 1) / RTILE;
+    uint64_t* hist = tmp;
+    uint64_t* stmp = tmp + 256 * nblk;
+    K* src_k = ka; uint32_t* src_v = va; K* dst_k = kb; uint32_t* dst_v = vb;
+    for (int sh = 0; sh < bits; sh += 8) {
+        hipLaunchKernelGGL(radix_hist<K>, dim3((unsigned)nblk), dim3(RT), 0, s, src_k, n, sh, nblk, hist);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        e = scan_impl<uint64_t>(hist, hist, 256 * nblk, stmp, (uint64_t*)nullptr, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(radix_scatter<K>, dim3((unsigned)nblk), dim3(RT), 0, s, src_k, src_v, dst_k, dst_v, n, sh,
+                           nblk, (const uint64_t*)hist);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        K* tk = src_k; src_k = dst_k; dst_k = tk;
+        uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
+        *in_b = !*in_b;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+size_t scan_tmp_elems(uint64_t n) {
+    size_t t = 1;
+    while (n > (uint64_t)STILE) {
+        n = (n + STILE - 1) / STILE;
+        t += n;
+    }
+    return t + 1;
+}
+
+hipError_t scan_excl_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, uint64_t* d_total,
+                         hipStream_t s) {
+    if (n == 0) {
+        if (d_total) return hipMemsetAsync(d_total, 0, sizeof(uint64_t), s);
+        return hipSuccess;
+    }
+    return scan_impl<uint64_t>(in, out, n, tmp, d_total, s);
+}
+
+hipError_t scan_excl_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, uint64_t* tmp, uint64_t* d_total,
+                                hipStream_t s) {
+    if (n == 0) {
+        if (d_total) return hipMemsetAsync(d_total, 0, sizeof(uint64_t), s);
+        return hipSuccess;
+    }
+    return scan_impl<uint32_t>(in, out, n, tmp, d_total, s);
+}
+
+size_t radix_tmp_elems(uint64_t n) {
+    uint64_t nblk = (n + RTILE - 1) / RTILE;
+    if (nblk < 1) nblk = 1;
+    return 256 * nblk + scan_tmp_elems(256 * nblk);
+}
+
+hipError_t radix_sort_u64(uint64_t* ka, uint32_t* va, uint64_t* kb, uint32_t* vb, uint64_t n, int bits,
+                          uint64_t* tmp, bool* in_b, hipStream_t s) {
+    return radix_impl<uint64_t>(ka, va, kb, vb, n, bits, tmp, in_b, s);
+}
+
+hipError_t radix_sort_u32(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, uint64_t n, int bits,
+                          uint64_t* tmp, bool* in_b, hipStream_t s) {
+    return radix_impl<uint32_t>(ka, va, kb, vb, n, bits, tmp, in_b, s);
+}
+
+}  // namespace msc

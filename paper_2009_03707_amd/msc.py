@@ -1,0 +1,267 @@
+"""Thin Python binding of libmsc.so (include/msc.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  PyTorch supplies device memory (tensors) and the stream
+(``torch.cuda.current_stream()``).  If the library is not built, or there is
+no GPU, calls raise instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsc.so")
+
+MS_OK, MS_ERR_INVALID_ARG, MS_ERR_NONFINITE, MS_ERR_TOO_LARGE, MS_ERR_CAPACITY, MS_ERR_OOM, MS_ERR_HIP, \
+    MS_ERR_INTERNAL = range(8)
+
+EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_error", "ms_gradient",
+            "ms_critical", "ms_connect", "ms_complex"]
+
+
+class MscError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libmsc status {status}: {msg}")
+        self.status = status
+
+
+class Dims(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("nz", C.c_int64)]
+
+
+class Crit(C.Structure):
+    _fields_ = [("id", C.c_void_p), ("index", C.c_void_p), ("value", C.c_void_p), ("vmax", C.c_void_p),
+                ("capacity", C.c_int64)]
+
+
+class Csr(C.Structure):
+    _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64),
+                ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("pj_rounds_vertex", "pj_rounds_cube", "bfs_levels", "reachable",
+                                         "junctions", "nnz_a", "nnz_b", "nnz_bstar", "nnz_d", "spgemm_iters",
+                                         "nnz_astar", "products")]
+
+
+class Arcs(C.Structure):
+    _fields_ = [("m10", Csr), ("m10t", Csr), ("m21", Csr), ("m21t", Csr), ("m32", Csr), ("m32t", Csr),
+                ("n_saturated", C.c_int64), ("stats", Stats)]
+
+
+class Result(C.Structure):
+    _fields_ = [("grad", C.c_void_p), ("crit", Crit), ("count", C.c_int64 * 4), ("arcs", Arcs)]
+
+
+_LIB = None
+
+
+def lib():
+    """Loads libmsc.so; raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        vp, i64 = C.c_void_p, C.c_int64
+        L.ms_ctx_create.argtypes = [C.POINTER(vp), vp]
+        L.ms_ctx_destroy.argtypes = [vp]
+        L.ms_ctx_destroy.restype = None
+        L.ms_ctx_set_stream.argtypes = [vp, vp]
+        L.ms_last_error.argtypes = [vp]
+        L.ms_last_error.restype = C.c_char_p
+        L.ms_gradient.argtypes = [vp, vp, Dims, vp]
+        L.ms_critical.argtypes = [vp, vp, vp, Dims, C.POINTER(Crit), C.POINTER(i64)]
+        L.ms_connect.argtypes = [vp, vp, Dims, vp, C.POINTER(i64), C.POINTER(Arcs)]
+        L.ms_complex.argtypes = [vp, vp, Dims, C.POINTER(Result)]
+        for n in EXPORTED:
+            getattr(L, n)
+        _LIB = L
+    return _LIB
+
+
+_hip = None
+
+
+def _hip_rt():
+    global _hip
+    if _hip is None:
+        h = C.CDLL("libamdhip64.so")
+        h.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        h.hipMemcpyAsync.restype = C.c_int
+        _hip = h
+    return _hip
+
+
+def _dims(f: torch.Tensor) -> Dims:
+    if f.dim() != 3:
+        raise ValueError("field must be a 3D tensor of shape (nz, ny, nx)")
+    nz, ny, nx = f.shape
+    return Dims(nx, ny, nz)
+
+
+def _check_field(f: torch.Tensor):
+    if not f.is_cuda or f.dtype != torch.float32 or not f.is_contiguous():
+        raise ValueError("field must be a contiguous float32 CUDA/HIP tensor")
+
+
+def _stream_handle():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One ms_ctx bound to the current torch stream of the current device."""
+
+    def __init__(self):
+        self._h = C.c_void_p()
+        st = lib().ms_ctx_create(C.byref(self._h), _stream_handle())
+        if st != MS_OK:
+            raise MscError(st, "ms_ctx_create failed")
+
+    def close(self):
+        if self._h:
+            lib().ms_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        lib().ms_ctx_set_stream(self._h, _stream_handle())
+
+    def _raise(self, st, what):
+        if st != MS_OK:
+            msg = lib().ms_last_error(self._h)
+            raise MscError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    # -- entry points -------------------------------------------------------
+    def gradient(self, f: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        _check_field(f)
+        self._sync_stream()
+        g = out if out is not None else torch.empty(f.shape, dtype=torch.int32, device=f.device)
+        st = lib().ms_gradient(self._h, C.c_void_p(f.data_ptr()), _dims(f), C.c_void_p(g.data_ptr()))
+        self._raise(st, "ms_gradient")
+        return g
+
+    def critical(self, f: torch.Tensor, grad: torch.Tensor):
+        """Returns (id int32[N], index uint8[N], value float32[N], vmax int32[N],
+        counts list[4]); ids and vertex ids are uint32 values stored in int32."""
+        _check_field(f)
+        self._sync_stream()
+        cnt = (C.c_int64 * 4)()
+        st = lib().ms_critical(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(grad.data_ptr()), _dims(f), None, cnt)
+        self._raise(st, "ms_critical (count)")
+        n = sum(cnt)
+        dev = f.device
+        ids = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        idx = torch.empty(max(n, 1), dtype=torch.uint8, device=dev)
+        val = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+        vm = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+        cr = Crit(ids.data_ptr(), idx.data_ptr(), val.data_ptr(), vm.data_ptr(), n)
+        st = lib().ms_critical(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(grad.data_ptr()), _dims(f),
+                               C.byref(cr), cnt)
+        self._raise(st, "ms_critical")
+        return ids[:n], idx[:n], val[:n], vm[:n], list(cnt)
+
+    def connect(self, grad: torch.Tensor, dims, crit_id: torch.Tensor, counts) -> "Arcs":
+        self._sync_stream()
+        cnt = (C.c_int64 * 4)(*[int(c) for c in counts])
+        arcs = Arcs()
+        st = lib().ms_connect(self._h, C.c_void_p(grad.data_ptr()), Dims(*dims),
+                              C.c_void_p(crit_id.data_ptr() if crit_id.numel() else 0), cnt, C.byref(arcs))
+        self._raise(st, "ms_connect")
+        return arcs
+
+    def complex_raw(self, f: torch.Tensor) -> Result:
+        """ms_complex; the returned structure points at context-owned device
+        buffers valid until the next call on this context."""
+        _check_field(f)
+        self._sync_stream()
+        res = Result()
+        st = lib().ms_complex(self._h, C.c_void_p(f.data_ptr()), _dims(f), C.byref(res))
+        self._raise(st, "ms_complex")
+        return res
+
+
+# -- copying context-owned outputs into torch tensors ---------------------------
+
+def _copy_dev(ptr: int, nbytes: int, dtype, count: int, device) -> torch.Tensor:
+    t = torch.empty(max(count, 1), dtype=dtype, device=device)
+    if nbytes > 0:
+        rc = _hip_rt().hipMemcpyAsync(C.c_void_p(t.data_ptr()), C.c_void_p(ptr), nbytes, 3, _stream_handle())
+        if rc != 0:
+            raise MscError(MS_ERR_HIP, f"hipMemcpyAsync failed ({rc})")
+    return t[:count]
+
+
+@dataclass
+class CsrT:
+    nrows: int
+    ncols: int
+    rowptr: torch.Tensor  # int64[nrows+1]
+    col: torch.Tensor     # int32 (uint32 values)
+    val: torch.Tensor     # int64 (uint64 bit patterns)
+
+
+def csr_to_torch(m: Csr, device) -> CsrT:
+    rp = _copy_dev(m.rowptr or 0, 8 * (m.nrows + 1) if m.rowptr else 0, torch.int64, m.nrows + 1, device)
+    if not m.rowptr:
+        rp.zero_()
+    col = _copy_dev(m.col or 0, 4 * m.nnz, torch.int32, m.nnz, device)
+    val = _copy_dev(m.val or 0, 8 * m.nnz, torch.int64, m.nnz, device)
+    return CsrT(m.nrows, m.ncols, rp, col, val)
+
+
+@dataclass
+class Complex:
+    grad: torch.Tensor
+    crit_id: torch.Tensor
+    crit_index: torch.Tensor
+    crit_value: torch.Tensor
+    crit_vmax: torch.Tensor
+    count: list
+    m10: CsrT
+    m10t: CsrT
+    m21: CsrT
+    m21t: CsrT
+    m32: CsrT
+    m32t: CsrT
+    n_saturated: int
+    stats: dict
+
+
+def complex_(f: torch.Tensor, ctx: Context | None = None) -> Complex:
+    """Runs the whole hot path and copies the results into torch tensors."""
+    own = ctx is None
+    ctx = ctx or Context()
+    try:
+        r = ctx.complex_raw(f)
+        dev = f.device
+        n = sum(r.count)
+        nv = f.numel()
+        out = Complex(
+            grad=_copy_dev(r.grad, 4 * nv, torch.int32, nv, dev).view(f.shape),
+            crit_id=_copy_dev(r.crit.id, 4 * n, torch.int32, n, dev),
+            crit_index=_copy_dev(r.crit.index, n, torch.uint8, n, dev),
+            crit_value=_copy_dev(r.crit.value, 4 * n, torch.float32, n, dev),
+            crit_vmax=_copy_dev(r.crit.vmax, 4 * n, torch.int32, n, dev),
+            count=list(r.count),
+            m10=csr_to_torch(r.arcs.m10, dev), m10t=csr_to_torch(r.arcs.m10t, dev),
+            m21=csr_to_torch(r.arcs.m21, dev), m21t=csr_to_torch(r.arcs.m21t, dev),
+            m32=csr_to_torch(r.arcs.m32, dev), m32t=csr_to_torch(r.arcs.m32t, dev),
+            n_saturated=int(r.arcs.n_saturated),
+            stats={k: int(getattr(r.arcs.stats, k)) for k, _ in Stats._fields_},
+        )
+        torch.cuda.current_stream().synchronize()
+        return out
+    finally:
+        if own:
+            ctx.close()

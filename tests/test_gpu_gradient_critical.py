@@ -1,0 +1,96 @@
+"""GPU parity of the gradient and critical-cell steps against the oracle:
+bit-exact gradient words and critical lists (integer / bit-copy outputs)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2009_03707_amd import fields
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2009_03707_amd import msc
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = msc.Context()
+    yield c
+    c.close()
+
+
+def _small_cases():
+    rng = np.random.default_rng(12345)
+    cases = []
+    for i in range(40):
+        dims = tuple(int(v) for v in rng.integers(1, 24, size=3))
+        levels = int(rng.choice([0, 0, 2, 3, 8]))
+        cases.append((dims, 100 + i, levels))
+    # degenerate shapes and tile edges (tile is 16 x 8 x 4 words)
+    for dims in [(1, 1, 1), (2, 1, 1), (1, 1, 9), (17, 9, 5), (16, 8, 4), (33, 1, 1), (1, 40, 3), (31, 17, 9)]:
+        cases.append((dims, 7, 0))
+        cases.append((dims, 8, 2))
+    return cases
+
+
+def _check(ctx, f):
+    from gpu_util import to_dev, u32
+    g_ref = O.gradient(f)
+    cr = O.critical(f, g_ref)
+    fd = to_dev(f)
+    g = ctx.gradient(fd)
+    np.testing.assert_array_equal(u32(g).reshape(f.shape), g_ref)
+    ids, idx, val, vm, cnt = ctx.critical(fd, g)
+    assert cnt == cr.count.tolist()
+    np.testing.assert_array_equal(u32(ids), cr.id)
+    np.testing.assert_array_equal(idx.cpu().numpy(), cr.index)
+    np.testing.assert_array_equal(val.cpu().numpy().view(np.uint32), cr.value.view(np.uint32))
+    np.testing.assert_array_equal(u32(vm), cr.vmax)
+
+
+@pytest.mark.parametrize("dims,seed,levels", _small_cases())
+def test_random_fields_bit_exact(ctx, dims, seed, levels):
+    _check(ctx, fields.random_field(dims, seed=seed, levels=levels))
+
+
+@pytest.mark.parametrize("name", ["sine32", "grf40x33x29", "blob48", "signed_zero"])
+def test_structured_fields_bit_exact(ctx, name):
+    if name == "sine32":
+        f = fields.sine_field(32)
+    elif name == "grf40x33x29":
+        f = fields.grf_field((40, 33, 29), seed=5)
+    elif name == "blob48":
+        f = fields.blob_field((48, 48, 48), nblobs=2, seed=0)
+    else:
+        rng = np.random.default_rng(3)
+        f = rng.choice(np.array([0.0, -0.0, 1.0, -1.0, 1e-40, -1e-40], np.float32), size=(9, 10, 11))
+    _check(ctx, f)
+
+
+def test_nonfinite_is_reported(ctx):
+    from paper_2009_03707_amd import msc
+    from gpu_util import to_dev
+    f = fields.random_field((5, 6, 7), seed=1)
+    f[3, 2, 1] = np.nan
+    with pytest.raises(msc.MscError) as e:
+        ctx.gradient(to_dev(f))
+    assert e.value.status == msc.MS_ERR_NONFINITE
+
+
+def test_capacity_error_then_retry(ctx):
+    import ctypes as C
+    from paper_2009_03707_amd import msc
+    from gpu_util import to_dev, u32
+    f = fields.random_field((12, 11, 10), seed=2)
+    fd = to_dev(f)
+    g = ctx.gradient(fd)
+    L = msc.lib()
+    cnt = (C.c_int64 * 4)()
+    small = torch.empty(4, dtype=torch.int32, device="cuda")
+    cr = msc.Crit(small.data_ptr(), small.data_ptr(), small.data_ptr(), small.data_ptr(), 1)
+    st = L.ms_critical(ctx._h, C.c_void_p(fd.data_ptr()), C.c_void_p(g.data_ptr()), msc._dims(fd), C.byref(cr), cnt)
+    assert st == msc.MS_ERR_CAPACITY
+    assert sum(cnt) == int(O.critical(f, O.gradient(f)).count.sum())
+    ids = ctx.critical(fd, g)[0]
+    assert len(ids) == sum(cnt)

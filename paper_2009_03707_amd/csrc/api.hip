@@ -161,6 +161,13 @@ ms_status ms_connect(ms_ctx* ctx, const uint32_t* d_grad, ms_dims dims, const ui
         total += h_count[k];
     }
     if (total > 0 && !d_crit_id) fail(ctx, MS_ERR_INVALID_ARG, "null critical list");
+    // the list must hold exactly the critical cells of the gradient: compare
+    // the counts here; the labelling pass checks each entry
+    int64_t have[4];
+    ms_status st = MS_OK;
+    critical_impl(ctx, nullptr, d_grad, g, nullptr, have, nullptr, &st);
+    for (int k = 0; k < 4; k++)
+        if (have[k] != h_count[k]) fail(ctx, MS_ERR_INVALID_ARG, "critical counts do not match the gradient");
     connect_impl(ctx, d_grad, g, d_crit_id, h_count, out);
     API_END
 }

@@ -1,8 +1,389 @@
-// placeholder, replaced below
+// Host orchestration of the 1-skeleton (ms_connect): saddle-extremum arcs by
+// pointer jumping, then saddle-saddle arcs by BFS, junctions, DAG minor and
+// iterated sparse products (Sections 3.2-3.5).  Every loop whose length
+// depends on the data has a bound that turns a malformed input into an
+// error instead of an endless loop.
 #include "ctx.h"
+#include "prims.h"
+
 namespace msc {
-void connect_impl(ms_ctx* c, const uint32_t*, const Grid&, const uint32_t*, const int64_t*, ms_arcs* out) {
+
+hipError_t launch_pj_init(const uint32_t* grad, const Grid& g, uint32_t* Pv, uint32_t* Pc, int* err, hipStream_t s);
+hipError_t launch_label(const uint32_t* crit, const int64_t cnt[4], const uint32_t* grad, const Grid& g, uint32_t* Pv,
+                        uint32_t* Pc, uint32_t* label, int* err, hipStream_t s);
+hipError_t launch_pj_round(uint32_t* P, uint32_t n, int* changed, hipStream_t s);
+hipError_t launch_m10(bool fill, const uint32_t* s1, uint64_t S1, const Grid& g, const uint32_t* Pv, uint32_t* cnt,
+                      const uint64_t* rowptr, uint32_t* col, uint64_t* val, int* err, hipStream_t s);
+hipError_t launch_m32t(bool fill, const uint32_t* s2, uint64_t S2, const Grid& g, const uint32_t* Pc, uint32_t* cnt,
+                       const uint64_t* rowptr, uint32_t* col, uint64_t* val, int* err, hipStream_t s);
+int bit_width(uint64_t v);
+hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, uint32_t* rows, hipStream_t s);
+hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s);
+hipError_t launch_hist(const uint32_t* keys, uint64_t n, uint32_t* h, hipStream_t s);
+hipError_t launch_gather_t(const uint32_t* perm, const uint32_t* rows, const uint64_t* val, uint32_t* ocol,
+                           uint64_t* oval, uint64_t n, hipStream_t s);
+hipError_t launch_make_keys(const uint32_t* row, const uint32_t* col, uint64_t n, int cb, uint64_t* keys,
+                            uint32_t* idx, hipStream_t s);
+hipError_t launch_heads(const uint64_t* keys, uint64_t n, uint32_t* h, hipStream_t s);
+hipError_t launch_merge_runs(const uint64_t* keys, const uint32_t* perm, const uint64_t* val, uint64_t n,
+                             const uint64_t* pos, int cb, uint32_t* orow, uint32_t* ocol, uint64_t* oval,
+                             hipStream_t s);
+hipError_t launch_esc_count(const uint32_t* xcol, uint64_t nx, const uint64_t* yrowptr, uint32_t* pc, hipStream_t s);
+hipError_t launch_esc_expand(const uint32_t* xrow, const uint32_t* xcol, const uint64_t* xval, uint64_t nx,
+                             const uint64_t* poff, const uint64_t* yrowptr, const uint32_t* ycol, const uint64_t* yval,
+                             uint32_t* prow, uint32_t* pcol, uint64_t* pval, hipStream_t s);
+hipError_t launch_count_sat(const uint64_t* v, uint64_t n, unsigned long long* out, hipStream_t s);
+hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Grid& g,
+                             uint32_t* vis, uint32_t* next, unsigned long long* next_count, uint32_t* label,
+                             uint32_t* jlist, unsigned long long* jcount, hipStream_t s);
+hipError_t launch_minor_trace(const uint32_t* s1, uint64_t S1, const uint32_t* jlist, uint64_t J, const uint32_t* grad,
+                              const Grid& g, const uint32_t* label, uint64_t max_steps, uint64_t S2, uint8_t* out_t,
+                              uint32_t* out_id, int* err, hipStream_t s);
+hipError_t launch_minor_rows(bool fill, const uint8_t* out_t, const uint32_t* out_id, uint64_t S1, uint64_t NS,
+                             uint32_t* cj, uint32_t* cs, const uint64_t* rpA, uint32_t* colA, uint64_t* valA,
+                             const uint64_t* rpD, uint32_t* colD, uint64_t* valD, const uint64_t* rpB, uint32_t* colB,
+                             uint64_t* valB, const uint64_t* rpBs, uint32_t* colBs, uint64_t* valBs, hipStream_t s);
+
+namespace {
+
+struct Coo {
+    uint32_t* row = nullptr;
+    uint32_t* col = nullptr;
+    uint64_t* val = nullptr;
+    uint64_t n = 0;
+};
+
+std::string nm(const char* a, const char* b) { return std::string(a) + "." + b; }
+
+// named buffer set for a COO of capacity n
+Coo coo_buf(ms_ctx* c, const char* name, uint64_t n) {
+    Coo o;
+    o.row = buf<uint32_t>(c, nm(name, "row").c_str(), n);
+    o.col = buf<uint32_t>(c, nm(name, "col").c_str(), n);
+    o.val = buf<uint64_t>(c, nm(name, "val").c_str(), n);
+    o.n = n;
+    return o;
+}
+
+ms_csr csr_buf(ms_ctx* c, const char* name, uint64_t nrows, uint64_t ncols, uint64_t nnz) {
+    ms_csr m;
+    m.nrows = (int64_t)nrows;
+    m.ncols = (int64_t)ncols;
+    m.nnz = (int64_t)nnz;
+    m.rowptr = (int64_t*)buf<uint64_t>(c, nm(name, "rowptr").c_str(), nrows + 1);
+    m.col = buf<uint32_t>(c, nm(name, "col").c_str(), nnz);
+    m.val = buf<uint64_t>(c, nm(name, "val").c_str(), nnz);
+    return m;
+}
+
+uint64_t read_u64(ms_ctx* c, const uint64_t* d) { return readback(c, d, 1)[0]; }
+
+void check_err_flag(ms_ctx* c, int* d_err, const char* stage) {
+    uint64_t* slot = buf<uint64_t>(c, "err_slot", 1);
+    check(c, hipMemsetAsync(slot, 0, sizeof(uint64_t), c->stream), "memset");
+    check(c, hipMemcpyAsync(slot, d_err, sizeof(int), hipMemcpyDeviceToDevice, c->stream), "copy");
+    uint64_t v = read_u64(c, slot);
+    if (v) fail(c, MS_ERR_INTERNAL, std::string("consistency check failed in ") + stage + " (flag " + std::to_string(v) + ")");
+}
+
+// Row counts (u32) -> rowptr (exclusive scan, total in rowptr[n]); returns nnz.
+uint64_t counts_to_rowptr(ms_ctx* c, const uint32_t* cnt, uint64_t n, uint64_t* rowptr) {
+    uint64_t* tmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(n) + 1);
+    check(c, scan_excl_u32_to_u64(cnt, rowptr, n, tmp, rowptr + n, c->stream), "scan");
+    return read_u64(c, rowptr + n);
+}
+
+// Transpose of a CSR (stable radix sort by column; rows of the output come out
+// with ascending columns because input entries are in row-major order).
+void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out) {
+    uint64_t nnz = (uint64_t)in.nnz;
+    out = csr_buf(c, name, (uint64_t)in.ncols, (uint64_t)in.nrows, nnz);
+    uint32_t* h = buf<uint32_t>(c, "tr.hist", (uint64_t)in.ncols + 1);
+    check(c, hipMemsetAsync(h, 0, sizeof(uint32_t) * ((uint64_t)in.ncols + 1), c->stream), "memset");
+    if (nnz == 0) {
+        check(c, hipMemsetAsync(out.rowptr, 0, sizeof(int64_t) * ((uint64_t)in.ncols + 1), c->stream), "memset");
+        return;
+    }
+    uint32_t* rows = buf<uint32_t>(c, "tr.rows", nnz);
+    uint32_t* ka = buf<uint32_t>(c, "tr.ka", nnz);
+    uint32_t* kb = buf<uint32_t>(c, "tr.kb", nnz);
+    uint32_t* va = buf<uint32_t>(c, "tr.va", nnz);
+    uint32_t* vb = buf<uint32_t>(c, "tr.vb", nnz);
+    uint64_t* tmp = buf<uint64_t>(c, "tr.tmp", radix_tmp_elems(nnz));
+    check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, rows, c->stream), "expand rows");
+    check(c, hipMemcpyAsync(ka, in.col, sizeof(uint32_t) * nnz, hipMemcpyDeviceToDevice, c->stream), "copy");
+    check(c, launch_iota(va, nnz, c->stream), "iota");
+    check(c, launch_hist(ka, nnz, h, c->stream), "hist");
+    bool in_b = false;
+    check(c, radix_sort_u32(ka, va, kb, vb, nnz, bit_width((uint64_t)in.ncols - 1), tmp, &in_b, c->stream), "sort");
+    const uint32_t* perm = in_b ? vb : va;
+    check(c, launch_gather_t(perm, rows, in.val, out.col, out.val, nnz, c->stream), "gather");
+    uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems((uint64_t)in.ncols) + 1);
+    check(c, scan_excl_u32_to_u64(h, (uint64_t*)out.rowptr, (uint64_t)in.ncols, stmp,
+                                  (uint64_t*)out.rowptr + in.ncols, c->stream),
+          "scan");
+}
+
+// Sort a COO by (row, col) and merge repeats; result in buffer set `name`.
+Coo sort_merge(ms_ctx* c, const Coo& in, uint64_t nrows, uint64_t ncols, const char* name) {
+    Coo out;
+    if (in.n == 0) {
+        out = coo_buf(c, name, 1);
+        out.n = 0;
+        return out;
+    }
+    uint64_t n = in.n;
+    if (n >= (1ull << 32)) fail(c, MS_ERR_TOO_LARGE, "more than 2^32 sparse entries in one product");
+    int cb = bit_width(ncols - 1), rb = bit_width(nrows - 1);
+    uint64_t* ka = buf<uint64_t>(c, "sm.ka", n);
+    uint64_t* kb = buf<uint64_t>(c, "sm.kb", n);
+    uint32_t* va = buf<uint32_t>(c, "sm.va", n);
+    uint32_t* vb = buf<uint32_t>(c, "sm.vb", n);
+    uint64_t* tmp = buf<uint64_t>(c, "sm.tmp", radix_tmp_elems(n));
+    check(c, launch_make_keys(in.row, in.col, n, cb, ka, va, c->stream), "keys");
+    bool in_b = false;
+    check(c, radix_sort_u64(ka, va, kb, vb, n, cb + rb, tmp, &in_b, c->stream), "sort");
+    const uint64_t* keys = in_b ? kb : ka;
+    const uint32_t* perm = in_b ? vb : va;
+    uint32_t* heads = buf<uint32_t>(c, "sm.heads", n);
+    uint64_t* pos = buf<uint64_t>(c, "sm.pos", n + 1);
+    check(c, launch_heads(keys, n, heads, c->stream), "heads");
+    uint64_t m = counts_to_rowptr(c, heads, n, pos);
+    out = coo_buf(c, name, m);
+    out.n = m;
+    check(c, launch_merge_runs(keys, perm, in.val, n, pos, cb, out.row, out.col, out.val, c->stream), "merge");
+    return out;
+}
+
+// Products X*Y (X as COO, Y as CSR) written at offset `at` of the product
+// buffer set "prod" (capacity for `reserve_extra` more entries is kept);
+// returns the number of products written.
+uint64_t esc_expand(ms_ctx* c, const Coo& x, const ms_csr& y, uint64_t at, Coo& prod, uint64_t reserve_extra) {
+    uint64_t t = 0;
+    if (x.n > 0) {
+        uint32_t* pc = buf<uint32_t>(c, "esc.pc", x.n);
+        uint64_t* poff = buf<uint64_t>(c, "esc.poff", x.n + 1);
+        check(c, launch_esc_count(x.col, x.n, (const uint64_t*)y.rowptr, pc, c->stream), "esc count");
+        t = counts_to_rowptr(c, pc, x.n, poff);
+        prod.row = buf_keep<uint32_t>(c, "prod.row", at + t + reserve_extra, at);
+        prod.col = buf_keep<uint32_t>(c, "prod.col", at + t + reserve_extra, at);
+        prod.val = buf_keep<uint64_t>(c, "prod.val", at + t + reserve_extra, at);
+        if (t)
+            check(c, launch_esc_expand(x.row, x.col, x.val, x.n, poff, (const uint64_t*)y.rowptr, y.col, y.val,
+                                       prod.row + at, prod.col + at, prod.val + at, c->stream),
+                  "esc expand");
+    } else {
+        prod.row = buf_keep<uint32_t>(c, "prod.row", at + reserve_extra, at);
+        prod.col = buf_keep<uint32_t>(c, "prod.col", at + reserve_extra, at);
+        prod.val = buf_keep<uint64_t>(c, "prod.val", at + reserve_extra, at);
+    }
+    prod.n = at + t;
+    return t;
+}
+
+void coo_to_csr(ms_ctx* c, const Coo& in, uint64_t nrows, uint64_t ncols, const char* name, ms_csr& out) {
+    out = csr_buf(c, name, nrows, ncols, in.n);
+    uint32_t* h = buf<uint32_t>(c, "cc.hist", nrows + 1);
+    check(c, hipMemsetAsync(h, 0, sizeof(uint32_t) * (nrows + 1), c->stream), "memset");
+    check(c, launch_hist(in.row, in.n, h, c->stream), "hist");
+    uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(nrows) + 1);
+    check(c, scan_excl_u32_to_u64(h, (uint64_t*)out.rowptr, nrows, stmp, (uint64_t*)out.rowptr + nrows, c->stream),
+          "scan");
+    if (in.n) {
+        check(c, hipMemcpyAsync(out.col, in.col, 4 * in.n, hipMemcpyDeviceToDevice, c->stream), "copy");
+        check(c, hipMemcpyAsync(out.val, in.val, 8 * in.n, hipMemcpyDeviceToDevice, c->stream), "copy");
+    }
+}
+
+Coo csr_as_coo(ms_ctx* c, const ms_csr& m, const char* rows_name) {
+    Coo o;
+    o.n = (uint64_t)m.nnz;
+    o.row = buf<uint32_t>(c, rows_name, o.n);
+    o.col = m.col;
+    o.val = m.val;
+    check(c, launch_expand_rows((const uint64_t*)m.rowptr, (uint64_t)m.nrows, o.row, c->stream), "expand rows");
+    return o;
+}
+
+}  // namespace
+
+void connect_impl(ms_ctx* c, const uint32_t* grad, const Grid& g, const uint32_t* crit, const int64_t cnt[4],
+                  ms_arcs* out) {
     memset(out, 0, sizeof(*out));
-    fail(c, MS_ERR_INTERNAL, "connect not built yet");
+    hipStream_t s = c->stream;
+    const uint64_t S0 = (uint64_t)cnt[0], S1 = (uint64_t)cnt[1], S2 = (uint64_t)cnt[2], S3 = (uint64_t)cnt[3];
+    const uint32_t* s1 = crit + S0;
+    const uint32_t* s2 = crit + S0 + S1;
+    int* d_err = buf<int>(c, "cn_err", 1);
+    check(c, hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
+    ms_stats& st = out->stats;
+
+    // ---- saddle-extremum arcs ------------------------------------------------
+    uint32_t* Pv = buf<uint32_t>(c, "pv", g.nv);
+    uint32_t* Pc = buf<uint32_t>(c, "pc", g.nv);
+    uint32_t* label = buf<uint32_t>(c, "cell_label", (uint64_t)8 * g.nv);
+    check(c, launch_pj_init(grad, g, Pv, Pc, d_err, s), "pj init");
+    check(c, launch_label(crit, cnt, grad, g, Pv, Pc, label, d_err, s), "label");
+    check_err_flag(c, d_err, "critical list labelling");
+    int* d_chg = buf<int>(c, "pj_changed", 1);
+    for (int which = 0; which < 2; which++) {
+        uint32_t* P = which == 0 ? Pv : Pc;
+        int64_t rounds = 0;
+        for (;;) {
+            check(c, hipMemsetAsync(d_chg, 0, sizeof(int), s), "memset");
+            check(c, launch_pj_round(P, g.nv, d_chg, s), "pj round");
+            rounds++;
+            uint64_t* slot = buf<uint64_t>(c, "pj_slot", 1);
+            check(c, hipMemsetAsync(slot, 0, sizeof(uint64_t), s), "memset");
+            check(c, hipMemcpyAsync(slot, d_chg, sizeof(int), hipMemcpyDeviceToDevice, s), "copy");
+            if (!read_u64(c, slot)) break;
+            if (rounds > 64) fail(c, MS_ERR_INTERNAL, "pointer jumping did not converge (cycle in the gradient)");
+        }
+        (which == 0 ? st.pj_rounds_vertex : st.pj_rounds_cube) = rounds;
+    }
+    {
+        uint32_t* rc = buf<uint32_t>(c, "rowcnt", S1 > S2 ? S1 : S2);
+        // M10
+        ms_csr& m10 = out->m10;
+        uint64_t* rp = buf<uint64_t>(c, "m10.rowptr", S1 + 1);
+        check(c, launch_m10(false, s1, S1, g, Pv, rc, nullptr, nullptr, nullptr, d_err, s), "m10 count");
+        uint64_t nnz = counts_to_rowptr(c, rc, S1, rp);
+        m10 = csr_buf(c, "m10", S1, S0, nnz);
+        check(c, launch_m10(true, s1, S1, g, Pv, nullptr, (const uint64_t*)m10.rowptr, m10.col, m10.val, d_err, s),
+              "m10 fill");
+        // M32 transposed (rows 2-saddles)
+        ms_csr& m32t = out->m32t;
+        uint64_t* rp2 = buf<uint64_t>(c, "m32t.rowptr", S2 + 1);
+        check(c, launch_m32t(false, s2, S2, g, Pc, rc, nullptr, nullptr, nullptr, d_err, s), "m32t count");
+        uint64_t nnz2 = counts_to_rowptr(c, rc, S2, rp2);
+        m32t = csr_buf(c, "m32t", S2, S3, nnz2);
+        check(c, launch_m32t(true, s2, S2, g, Pc, nullptr, (const uint64_t*)m32t.rowptr, m32t.col, m32t.val, d_err, s),
+              "m32t fill");
+        check_err_flag(c, d_err, "saddle-extremum arcs");
+        transpose(c, m10, "m10t", out->m10t);
+        transpose(c, m32t, "m32", out->m32);
+    }
+
+    // ---- saddle-saddle reachability (frontier BFS) --------------------------
+    uint64_t nvis = ((uint64_t)g.nv + 3) / 4;
+    uint32_t* vis = buf<uint32_t>(c, "visited", nvis);
+    check(c, hipMemsetAsync(vis, 0, 4 * nvis, s), "memset");
+    unsigned long long* d_cnt = (unsigned long long*)buf<uint64_t>(c, "bfs_counts", 2);  // [0] next, [1] junctions
+    check(c, hipMemsetAsync(d_cnt, 0, 16, s), "memset");
+    uint64_t ncur = S1, J = 0, reach = 0;
+    int64_t levels = 0;
+    const uint64_t max_nodes = (uint64_t)3 * g.nv + 1;
+    if (S1 > 0) {
+        uint32_t* fa = buf<uint32_t>(c, "front_a", ncur);
+        check(c, hipMemcpyAsync(fa, s1, 4 * ncur, hipMemcpyDeviceToDevice, s), "copy");
+        bool level0 = true;
+        const char* cur_name = "front_a";
+        const char* nxt_name = "front_b";
+        while (ncur > 0) {
+            uint32_t* cur = buf<uint32_t>(c, cur_name, ncur);
+            uint32_t* nxt = buf<uint32_t>(c, nxt_name, 4 * ncur);
+            uint32_t* jlist = buf_keep<uint32_t>(c, "jlist", J + ncur + 1, J);
+            check(c, hipMemsetAsync(d_cnt, 0, 8, s), "memset");
+            check(c, launch_bfs_expand(cur, ncur, level0, grad, g, vis, nxt, d_cnt, label, jlist, d_cnt + 1, s),
+                  "bfs expand");
+            uint64_t* h = readback(c, (const uint64_t*)d_cnt, 2);
+            uint64_t nn = h[0];
+            J = h[1];
+            reach += level0 ? 0 : ncur;
+            ncur = nn;
+            levels++;
+            level0 = false;
+            std::swap(cur_name, nxt_name);
+            if ((uint64_t)levels > max_nodes) fail(c, MS_ERR_INTERNAL, "BFS did not terminate");
+        }
+    }
+    st.bfs_levels = levels;
+    st.reachable = (int64_t)reach;
+    st.junctions = (int64_t)J;
+
+    // ---- DAG minor ----------------------------------------------------------
+    const uint64_t NS = S1 + J;
+    uint32_t* jlist = buf<uint32_t>(c, "jlist", J + 1);
+    uint8_t* out_t = buf<uint8_t>(c, "minor_t", 4 * NS);
+    uint32_t* out_id = buf<uint32_t>(c, "minor_id", 4 * NS);
+    check(c, launch_minor_trace(s1, S1, jlist, J, grad, g, label, max_nodes, S2, out_t, out_id, d_err, s), "minor trace");
+    uint32_t* cj = buf<uint32_t>(c, "minor_cj", NS);
+    uint32_t* cs = buf<uint32_t>(c, "minor_cs", NS);
+    check(c, launch_minor_rows(false, out_t, out_id, S1, NS, cj, cs, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s),
+          "minor rows");
+    check_err_flag(c, d_err, "DAG minor tracing");
+    uint64_t* rpA = buf<uint64_t>(c, "A.rowptr", S1 + 1);
+    uint64_t* rpD = buf<uint64_t>(c, "D.rowptr", S1 + 1);
+    uint64_t* rpB = buf<uint64_t>(c, "B.rowptr", J + 1);
+    uint64_t* rpBs = buf<uint64_t>(c, "Bs.rowptr", J + 1);
+    uint64_t nA = counts_to_rowptr(c, cj, S1, rpA);
+    uint64_t nD = counts_to_rowptr(c, cs, S1, rpD);
+    uint64_t nB = counts_to_rowptr(c, cj + S1, J, rpB);
+    uint64_t nBs = counts_to_rowptr(c, cs + S1, J, rpBs);
+    ms_csr A = csr_buf(c, "A", S1, J, nA), D = csr_buf(c, "D", S1, S2, nD);
+    ms_csr B = csr_buf(c, "B", J, J, nB), Bs = csr_buf(c, "Bs", J, S2, nBs);
+    check(c, launch_minor_rows(true, out_t, out_id, S1, NS, nullptr, nullptr, (const uint64_t*)A.rowptr, A.col, A.val,
+                               (const uint64_t*)D.rowptr, D.col, D.val, (const uint64_t*)B.rowptr, B.col, B.val,
+                               (const uint64_t*)Bs.rowptr, Bs.col, Bs.val, s),
+          "minor fill");
+    st.nnz_a = (int64_t)nA;
+    st.nnz_b = (int64_t)nB;
+    st.nnz_bstar = (int64_t)nBs;
+    st.nnz_d = (int64_t)nD;
+
+    // ---- path counting: A* = sum_k A B^k ; P = D + A* B* ---------------------
+    // Each iteration adds the current frontier of 1-saddle -> junction path
+    // counts to the accumulation list and advances it by one level of the
+    // minor (frontier <- frontier * B) until the product is empty.
+    Coo fr = csr_as_coo(c, A, "A.rows");
+    uint64_t astar_n = 0;
+    int64_t iters = 0;
+    uint64_t products = 0;
+    Coo acc;
+    while (fr.n > 0) {
+        acc.row = buf_keep<uint32_t>(c, "acc.row", astar_n + fr.n, astar_n);
+        acc.col = buf_keep<uint32_t>(c, "acc.col", astar_n + fr.n, astar_n);
+        acc.val = buf_keep<uint64_t>(c, "acc.val", astar_n + fr.n, astar_n);
+        check(c, hipMemcpyAsync(acc.row + astar_n, fr.row, 4 * fr.n, hipMemcpyDeviceToDevice, s), "copy");
+        check(c, hipMemcpyAsync(acc.col + astar_n, fr.col, 4 * fr.n, hipMemcpyDeviceToDevice, s), "copy");
+        check(c, hipMemcpyAsync(acc.val + astar_n, fr.val, 8 * fr.n, hipMemcpyDeviceToDevice, s), "copy");
+        astar_n += fr.n;
+        Coo prod;
+        uint64_t t = esc_expand(c, fr, B, 0, prod, 0);
+        products += t;
+        iters++;
+        if ((uint64_t)iters > J + 2) fail(c, MS_ERR_INTERNAL, "path counting did not terminate (cycle in the minor)");
+        if (t == 0) break;
+        // alternate between two named result sets so the input stays intact
+        fr = sort_merge(c, prod, S1, J, (iters & 1) ? "front1" : "front2");
+    }
+    st.spgemm_iters = iters;
+    Coo astar;
+    if (astar_n) {
+        acc.n = astar_n;
+        astar = sort_merge(c, acc, S1, J, "astar");
+    }
+    st.nnz_astar = (int64_t)astar.n;
+    // P products: A* B* followed by the entries of D
+    Coo prod;
+    uint64_t t = esc_expand(c, astar, Bs, 0, prod, nD);
+    products += t;
+    st.products = (int64_t)products;
+    if (nD) {
+        Coo dcoo = csr_as_coo(c, D, "D.rows");
+        check(c, hipMemcpyAsync(prod.row + t, dcoo.row, 4 * nD, hipMemcpyDeviceToDevice, s), "copy");
+        check(c, hipMemcpyAsync(prod.col + t, dcoo.col, 4 * nD, hipMemcpyDeviceToDevice, s), "copy");
+        check(c, hipMemcpyAsync(prod.val + t, dcoo.val, 8 * nD, hipMemcpyDeviceToDevice, s), "copy");
+    }
+    prod.n = t + nD;
+    Coo P = sort_merge(c, prod, S1, S2, "P");
+    coo_to_csr(c, P, S1, S2, "m21t", out->m21t);
+    transpose(c, out->m21t, "m21", out->m21);
+    unsigned long long* d_sat = (unsigned long long*)buf<uint64_t>(c, "sat_count", 1);
+    check(c, hipMemsetAsync(d_sat, 0, 8, s), "memset");
+    check(c, launch_count_sat(out->m21t.val, (uint64_t)out->m21t.nnz, d_sat, s), "count saturated");
+    out->n_saturated = (int64_t)read_u64(c, (const uint64_t*)d_sat);
 }
-}
+
+}  // namespace msc

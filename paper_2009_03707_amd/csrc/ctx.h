@@ -55,6 +55,29 @@ T* buf(ms_ctx* c, const char* name, size_t count) {
     return (T*)b.p;
 }
 
+// Like buf(), but a growth keeps the first `used` elements.
+template <typename T>
+T* buf_keep(ms_ctx* c, const char* name, size_t count, size_t used) {
+    size_t bytes = (count ? count : 1) * sizeof(T);
+    ms_ctx::Buf& b = c->bufs[name];
+    if (b.cap >= bytes) return (T*)b.p;
+    size_t want = bytes + bytes / 2 + 256;
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        c->err = std::string("device allocation of ") + std::to_string(want) + " bytes failed for " + name;
+        throw Fail{MS_ERR_OOM};
+    }
+    if (b.p) {
+        if (used) (void)hipMemcpyAsync(p, b.p, used * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(b.p);
+    }
+    b.p = p;
+    b.cap = want;
+    return (T*)p;
+}
+
 inline void check(ms_ctx* c, hipError_t e, const char* what) {
     if (e != hipSuccess) {
         c->err = std::string(what) + ": " + hipGetErrorString(e);

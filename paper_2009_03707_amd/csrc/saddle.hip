@@ -1,0 +1,298 @@
+// 1-saddle / 2-saddle connections (Sections 3.1-3.3 and 3.5).
+//
+// The DAG of 1-2 gradient pairs has a node for every 1-saddle and every edge
+// paired with a quad.  From a node e, each cofacet quad Q other than the quad
+// e is paired with leads to a 2-saddle (Q critical) or to the edge Q is
+// paired with; a quad paired with a cube leads nowhere.  Traversals run
+// against the direction of the discrete gradient (ascending from the
+// 1-saddles), so they cannot cycle (Section 3.5).
+//
+// Reachability (Section 3.2): frontier BFS from all 1-saddles; a node is
+// expanded by one lane, which tests-and-sets a visited bit for each target
+// edge and appends the new ones to the next frontier with one atomic per
+// wave (the order inside a frontier does not matter, only the visited set).
+// The same lane counts the node's out-degree and, for reachable non-saddle
+// nodes, marks junctions (out-degree > 1, Section 3.3) and numbers them.
+//
+// DAG minor (Section 3.3, "DAG minor construction"): every (source, out-edge)
+// pair -- sources are the 1-saddles and junctions -- is traced by one lane
+// until it reaches a junction or a 2-saddle; paths that end elsewhere are
+// dropped (Section 3.5).  Because a simple path never splits, a lane keeps
+// walking in registers instead of compacting after each step.  Each lane
+// writes to a fixed slot (4 per source), so the minor is assembled in source
+// order without any sort.
+#include "prims.h"
+
+namespace msc {
+namespace {
+
+constexpr int BT = 256;
+constexpr uint8_t T_NONE = 0, T_JUNC = 1, T_S2 = 2;
+
+struct CellRef {
+    uint32_t w, k;
+};
+
+// V(e): the quad an edge is paired with, if any.
+__device__ __forceinline__ bool paired_quad(const Grid& g, uint32_t w, uint32_t k, uint32_t ne, const uint32_t c[3],
+                                            uint32_t axis_e, CellRef& v) {
+    if (ne < 1 || ne > 6) return false;
+    uint32_t da = (ne - 1u) >> 1;
+    if (da == axis_e) return false;  // paired with a vertex
+    int s = ((ne - 1u) & 1u) ? -1 : 1;
+    return cell_step(g, w, k, c, (int)da, s, v.w, v.k);
+}
+
+// If quad (qw, qk) is paired with one of its edges, that edge; otherwise false.
+__device__ __forceinline__ bool quad_edge_partner(const Grid& g, uint32_t qw, uint32_t qk, uint32_t nq, CellRef& e) {
+    if (nq < 1 || nq > 6) return false;
+    uint32_t dq = (nq - 1u) >> 1;
+    if (!((qk >> dq) & 1u)) return false;  // partner is a cube
+    e.k = qk & ~(1u << dq);
+    e.w = ((nq - 1u) & 1u) ? qw : qw + g.stride[dq];
+    return true;
+}
+
+__global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ cur, uint64_t ncur, int level0,
+                                                   const uint32_t* __restrict__ grad, Grid g,
+                                                   uint32_t* __restrict__ vis, uint32_t* __restrict__ next,
+                                                   unsigned long long* __restrict__ next_count,
+                                                   uint32_t* __restrict__ label, uint32_t* __restrict__ jlist,
+                                                   unsigned long long* __restrict__ jcount) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    bool valid = i < ncur;
+    uint32_t t[4];
+    uint32_t nt = 0, outdeg = 0;
+    uint32_t e = 0;
+    if (valid) {
+        e = cur[i];
+        uint32_t w = e >> 3, k = e & 7u;
+        uint32_t a = (uint32_t)__builtin_ctz(k);
+        uint32_t c[3];
+        g.coords(w, c);
+        CellRef v;
+        bool hv = paired_quad(g, w, k, nib_of(grad[w], k), c, a, v);
+        for (uint32_t b = 0; b < 3; b++) {
+            if (b == a) continue;
+            for (int s = -1; s <= 1; s += 2) {
+                CellRef q;
+                if (!cell_step(g, w, k, c, (int)b, s, q.w, q.k)) continue;
+                if (hv && q.w == v.w && q.k == v.k) continue;
+                uint32_t nq = nib_of(grad[q.w], q.k);
+                if (nq >= NB_CRIT) {
+                    outdeg++;
+                    continue;
+                }
+                CellRef e2;
+                if (!quad_edge_partner(g, q.w, q.k, nq, e2)) continue;
+                outdeg++;
+                uint32_t bit = 1u << (8u * (e2.w & 3u) + e2.k);
+                uint32_t old = atomicOr(&vis[e2.w >> 2], bit);
+                if (!(old & bit)) t[nt++] = 8u * e2.w + e2.k;
+            }
+        }
+    }
+    // append the newly visited edges, one atomic per wave
+    uint32_t incl = wave_incl_scan(nt);
+    uint32_t tot = __shfl(incl, WAVE - 1, WAVE);
+    unsigned long long base = 0;
+    if (tot) {
+        if (lane_id() == WAVE - 1) base = atomicAdd(next_count, (unsigned long long)tot);
+        base = __shfl(base, WAVE - 1, WAVE);
+    }
+    uint64_t o = base + incl - nt;
+    for (uint32_t q = 0; q < nt; q++) next[o + q] = t[q];
+    // junctions among reachable non-saddle nodes
+    uint32_t isj = (valid && !level0 && outdeg > 1) ? 1u : 0u;
+    uint32_t jin = wave_incl_scan(isj);
+    uint32_t jtot = __shfl(jin, WAVE - 1, WAVE);
+    unsigned long long jb = 0;
+    if (jtot) {
+        if (lane_id() == WAVE - 1) jb = atomicAdd(jcount, (unsigned long long)jtot);
+        jb = __shfl(jb, WAVE - 1, WAVE);
+    }
+    if (valid && !level0) {
+        if (isj) {
+            uint32_t jid = (uint32_t)(jb + jin - 1u);
+            label[e] = jid;
+            jlist[jid] = e;
+        } else {
+            label[e] = NOT_JUNCTION;
+        }
+    }
+}
+
+// Trace the simple path leaving source `src` through its out-edge `slot`.
+__global__ __launch_bounds__(BT) void k_minor_trace(const uint32_t* __restrict__ s1, uint64_t S1,
+                                                    const uint32_t* __restrict__ jlist, uint64_t J,
+                                                    const uint32_t* __restrict__ grad, Grid g,
+                                                    const uint32_t* __restrict__ label, uint64_t max_steps,
+                                                    uint64_t S2, uint8_t* __restrict__ out_t,
+                                                    uint32_t* __restrict__ out_id, int* __restrict__ err) {
+    uint64_t lane = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    uint64_t si = lane >> 2;
+    if (si >= S1 + J) return;
+    uint32_t slot = (uint32_t)(lane & 3u);
+    uint32_t e = si < S1 ? s1[si] : jlist[si - S1];
+    uint32_t w = e >> 3, k = e & 7u;
+    uint32_t a = (uint32_t)__builtin_ctz(k);
+    uint32_t c[3];
+    g.coords(w, c);
+    CellRef v;
+    bool hv = paired_quad(g, w, k, nib_of(grad[w], k), c, a, v);
+    uint32_t b0 = a == 0 ? 1u : 0u, b1 = a == 2 ? 1u : 2u;
+    uint32_t b = (slot >> 1) ? b1 : b0;
+    int s = (slot & 1u) ? 1 : -1;
+    uint8_t typ = T_NONE;
+    uint32_t id = 0;
+    CellRef q;
+    if (cell_step(g, w, k, c, (int)b, s, q.w, q.k) && !(hv && q.w == v.w && q.k == v.k)) {
+        for (uint64_t step = 0;; step++) {
+            if (step > max_steps) {
+                atomicOr(err, 8);
+                break;
+            }
+            uint32_t nq = nib_of(grad[q.w], q.k);
+            if (nq >= NB_CRIT) {
+                typ = T_S2;
+                id = label[8u * q.w + q.k];
+                break;
+            }
+            CellRef e2;
+            if (!quad_edge_partner(g, q.w, q.k, nq, e2)) break;  // paired with a cube: dead end
+            uint32_t lab = label[8u * e2.w + e2.k];
+            if (lab != NOT_JUNCTION) {
+                typ = T_JUNC;
+                id = lab;
+                break;
+            }
+            // e2 has out-degree <= 1 and is paired with q: find its only out-edge
+            uint32_t a2 = (uint32_t)__builtin_ctz(e2.k);
+            uint32_t c2[3];
+            g.coords(e2.w, c2);
+            bool found = false;
+            for (uint32_t bb = 0; bb < 3 && !found; bb++) {
+                if (bb == a2) continue;
+                for (int ss = -1; ss <= 1 && !found; ss += 2) {
+                    CellRef q2;
+                    if (!cell_step(g, e2.w, e2.k, c2, (int)bb, ss, q2.w, q2.k)) continue;
+                    if (q2.w == q.w && q2.k == q.k) continue;
+                    uint32_t n2 = nib_of(grad[q2.w], q2.k);
+                    CellRef tmp;
+                    if (n2 >= NB_CRIT || quad_edge_partner(g, q2.w, q2.k, n2, tmp)) {
+                        q = q2;
+                        found = true;
+                    }
+                }
+            }
+            if (!found) break;  // dead end
+        }
+    }
+    if ((typ == T_S2 && id >= S2) || (typ == T_JUNC && id >= J)) {
+        atomicOr(err, 16);  // a label that was never assigned
+        typ = T_NONE;
+    }
+    out_t[lane] = typ;
+    out_id[lane] = id;
+}
+
+// Per source: distinct junction targets and distinct 2-saddle targets with
+// multiplicities (at most four paths leave a source).
+template <bool FILL>
+__global__ __launch_bounds__(BT) void k_minor_rows(const uint8_t* __restrict__ out_t,
+                                                   const uint32_t* __restrict__ out_id, uint64_t S1, uint64_t NS,
+                                                   uint32_t* __restrict__ cj, uint32_t* __restrict__ cs,
+                                                   const uint64_t* __restrict__ rpA, uint32_t* __restrict__ colA,
+                                                   uint64_t* __restrict__ valA, const uint64_t* __restrict__ rpD,
+                                                   uint32_t* __restrict__ colD, uint64_t* __restrict__ valD,
+                                                   const uint64_t* __restrict__ rpB, uint32_t* __restrict__ colB,
+                                                   uint64_t* __restrict__ valB, const uint64_t* __restrict__ rpBs,
+                                                   uint32_t* __restrict__ colBs, uint64_t* __restrict__ valBs) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= NS) return;
+    uint32_t jv[4], sv[4];
+    uint64_t jm[4], sm[4];
+    uint32_t nj = 0, ns = 0;
+    for (int q = 0; q < 4; q++) {
+        uint8_t t = out_t[4 * i + q];
+        uint32_t id = out_id[4 * i + q];
+        uint32_t* v = t == T_JUNC ? jv : sv;
+        uint64_t* m = t == T_JUNC ? jm : sm;
+        uint32_t& n = t == T_JUNC ? nj : ns;
+        if (t == T_NONE) continue;
+        // insert keeping ascending order and merging repeats
+        uint32_t p = 0;
+        while (p < n && v[p] < id) p++;
+        if (p < n && v[p] == id) {
+            m[p] += 1;
+            continue;
+        }
+        for (uint32_t r = n; r > p; r--) {
+            v[r] = v[r - 1];
+            m[r] = m[r - 1];
+        }
+        v[p] = id;
+        m[p] = 1;
+        n++;
+    }
+    if (!FILL) {
+        cj[i] = nj;
+        cs[i] = ns;
+        return;
+    }
+    uint32_t *cJ, *cS;
+    uint64_t *vJ, *vS;
+    uint64_t oJ, oS;
+    if (i < S1) {
+        cJ = colA; vJ = valA; oJ = rpA[i];
+        cS = colD; vS = valD; oS = rpD[i];
+    } else {
+        cJ = colB; vJ = valB; oJ = rpB[i - S1];
+        cS = colBs; vS = valBs; oS = rpBs[i - S1];
+    }
+    for (uint32_t q = 0; q < nj; q++) {
+        cJ[oJ + q] = jv[q];
+        vJ[oJ + q] = jm[q];
+    }
+    for (uint32_t q = 0; q < ns; q++) {
+        cS[oS + q] = sv[q];
+        vS[oS + q] = sm[q];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Grid& g,
+                             uint32_t* vis, uint32_t* next, unsigned long long* next_count, uint32_t* label,
+                             uint32_t* jlist, unsigned long long* jcount, hipStream_t s) {
+    if (ncur == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_blocks(ncur, BT)), dim3(BT), 0, s, cur, ncur, level0 ? 1 : 0, grad, g,
+                       vis, next, next_count, label, jlist, jcount);
+    return hipGetLastError();
+}
+
+hipError_t launch_minor_trace(const uint32_t* s1, uint64_t S1, const uint32_t* jlist, uint64_t J, const uint32_t* grad,
+                              const Grid& g, const uint32_t* label, uint64_t max_steps, uint64_t S2, uint8_t* out_t,
+                              uint32_t* out_id, int* err, hipStream_t s) {
+    uint64_t lanes = 4 * (S1 + J);
+    if (lanes == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_minor_trace, dim3(grid_blocks(lanes, BT)), dim3(BT), 0, s, s1, S1, jlist, J, grad, g, label,
+                       max_steps, S2, out_t, out_id, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_minor_rows(bool fill, const uint8_t* out_t, const uint32_t* out_id, uint64_t S1, uint64_t NS,
+                             uint32_t* cj, uint32_t* cs, const uint64_t* rpA, uint32_t* colA, uint64_t* valA,
+                             const uint64_t* rpD, uint32_t* colD, uint64_t* valD, const uint64_t* rpB, uint32_t* colB,
+                             uint64_t* valB, const uint64_t* rpBs, uint32_t* colBs, uint64_t* valBs, hipStream_t s) {
+    if (NS == 0) return hipSuccess;
+    if (fill)
+        hipLaunchKernelGGL(k_minor_rows<true>, dim3(grid_blocks(NS, BT)), dim3(BT), 0, s, out_t, out_id, S1, NS, cj, cs,
+                           rpA, colA, valA, rpD, colD, valD, rpB, colB, valB, rpBs, colBs, valBs);
+    else
+        hipLaunchKernelGGL(k_minor_rows<false>, dim3(grid_blocks(NS, BT)), dim3(BT), 0, s, out_t, out_id, S1, NS, cj,
+                           cs, rpA, colA, valA, rpD, colD, valD, rpB, colB, valB, rpBs, colBs, valBs);
+    return hipGetLastError();
+}
+
+}  // namespace msc

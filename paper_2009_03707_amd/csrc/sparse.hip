@@ -1,0 +1,179 @@
+// Sparse integer matrices for the path-counting step (Section 3.3, "Path
+// counting via matrix operations"; Section 3.5, "Gradient path counting").
+//
+// The paper uses cuSPARSE in floating point; here every kernel is
+// hand-written and the arithmetic is unsigned 64-bit saturating, which is
+// exact up to 2^64-1 and independent of the order of additions.  Products
+// are formed expand-sort-compress: each nonzero A(i,k) is expanded against
+// row k of B, the (row, column) keys are radix-sorted (stable), and runs of
+// equal keys are merged by saturating addition.
+#include "prims.h"
+
+namespace msc {
+namespace {
+
+constexpr int BT = 256;
+
+__global__ __launch_bounds__(BT) void k_expand_rows(const uint64_t* __restrict__ rowptr, uint64_t nrows,
+                                                    uint32_t* __restrict__ rows) {
+    uint64_t r = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (r >= nrows) return;
+    for (uint64_t p = rowptr[r]; p < rowptr[r + 1]; p++) rows[p] = (uint32_t)r;
+}
+
+__global__ __launch_bounds__(BT) void k_iota(uint32_t* __restrict__ a, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i < n) a[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(BT) void k_hist(const uint32_t* __restrict__ keys, uint64_t n, uint32_t* __restrict__ h) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i < n) atomicAdd(&h[keys[i]], 1u);
+}
+
+__global__ __launch_bounds__(BT) void k_gather_t(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ rows,
+                                                 const uint64_t* __restrict__ val, uint32_t* __restrict__ ocol,
+                                                 uint64_t* __restrict__ oval, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n) return;
+    uint32_t p = perm[i];
+    ocol[i] = rows[p];
+    oval[i] = val[p];
+}
+
+__global__ __launch_bounds__(BT) void k_make_keys(const uint32_t* __restrict__ row, const uint32_t* __restrict__ col,
+                                                  uint64_t n, int cb, uint64_t* __restrict__ keys,
+                                                  uint32_t* __restrict__ idx) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = ((uint64_t)row[i] << cb) | (uint64_t)col[i];
+    idx[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(BT) void k_heads(const uint64_t* __restrict__ keys, uint64_t n, uint32_t* __restrict__ h) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n) return;
+    h[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(BT) void k_merge_runs(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ perm,
+                                                   const uint64_t* __restrict__ val, uint64_t n,
+                                                   const uint64_t* __restrict__ pos, int cb,
+                                                   uint32_t* __restrict__ orow, uint32_t* __restrict__ ocol,
+                                                   uint64_t* __restrict__ oval) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n) return;
+    uint64_t k = keys[i];
+    if (i > 0 && keys[i - 1] == k) return;
+    uint64_t s = val[perm[i]];
+    for (uint64_t j = i + 1; j < n && keys[j] == k; j++) s = sat_add(s, val[perm[j]]);
+    uint64_t o = pos[i];
+    orow[o] = (uint32_t)(k >> cb);
+    ocol[o] = (uint32_t)(k & ((1ull << cb) - 1ull));
+    oval[o] = s;
+}
+
+// number of products of each nonzero X(i,k) with row k of Y
+__global__ __launch_bounds__(BT) void k_esc_count(const uint32_t* __restrict__ xcol, uint64_t nx,
+                                                  const uint64_t* __restrict__ yrowptr, uint32_t* __restrict__ pc) {
+    uint64_t e = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (e >= nx) return;
+    uint32_t k = xcol[e];
+    pc[e] = (uint32_t)(yrowptr[k + 1] - yrowptr[k]);
+}
+
+__global__ __launch_bounds__(BT) void k_esc_expand(const uint32_t* __restrict__ xrow, const uint32_t* __restrict__ xcol,
+                                                   const uint64_t* __restrict__ xval, uint64_t nx,
+                                                   const uint64_t* __restrict__ poff,
+                                                   const uint64_t* __restrict__ yrowptr,
+                                                   const uint32_t* __restrict__ ycol,
+                                                   const uint64_t* __restrict__ yval, uint32_t* __restrict__ prow,
+                                                   uint32_t* __restrict__ pcol, uint64_t* __restrict__ pval) {
+    uint64_t e = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (e >= nx) return;
+    uint32_t k = xcol[e], r = xrow[e];
+    uint64_t a = xval[e];
+    uint64_t o = poff[e];
+    for (uint64_t q = yrowptr[k]; q < yrowptr[k + 1]; q++, o++) {
+        prow[o] = r;
+        pcol[o] = ycol[q];
+        pval[o] = sat_mul(a, yval[q]);
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_count_sat(const uint64_t* __restrict__ v, uint64_t n,
+                                                  unsigned long long* __restrict__ out) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    bool s = i < n && v[i] == ~0ull;
+    uint64_t b = __ballot(s);
+    if (lane_id() == 0 && b) atomicAdd(out, (unsigned long long)__popcll(b));
+}
+
+}  // namespace
+
+int bit_width(uint64_t v) {
+    int b = 0;
+    while (b < 64 && (v >> b) != 0) b++;
+    return b < 1 ? 1 : b;
+}
+
+hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, uint32_t* rows, hipStream_t s) {
+    if (nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand_rows, dim3(grid_blocks(nrows, BT)), dim3(BT), 0, s, rowptr, nrows, rows);
+    return hipGetLastError();
+}
+hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, a, n);
+    return hipGetLastError();
+}
+hipError_t launch_hist(const uint32_t* keys, uint64_t n, uint32_t* h, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hist, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, keys, n, h);
+    return hipGetLastError();
+}
+hipError_t launch_gather_t(const uint32_t* perm, const uint32_t* rows, const uint64_t* val, uint32_t* ocol,
+                           uint64_t* oval, uint64_t n, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_t, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, perm, rows, val, ocol, oval, n);
+    return hipGetLastError();
+}
+hipError_t launch_make_keys(const uint32_t* row, const uint32_t* col, uint64_t n, int cb, uint64_t* keys,
+                            uint32_t* idx, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_make_keys, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, row, col, n, cb, keys, idx);
+    return hipGetLastError();
+}
+hipError_t launch_heads(const uint64_t* keys, uint64_t n, uint32_t* h, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_heads, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, keys, n, h);
+    return hipGetLastError();
+}
+hipError_t launch_merge_runs(const uint64_t* keys, const uint32_t* perm, const uint64_t* val, uint64_t n,
+                             const uint64_t* pos, int cb, uint32_t* orow, uint32_t* ocol, uint64_t* oval,
+                             hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge_runs, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, keys, perm, val, n, pos, cb, orow, ocol,
+                       oval);
+    return hipGetLastError();
+}
+hipError_t launch_esc_count(const uint32_t* xcol, uint64_t nx, const uint64_t* yrowptr, uint32_t* pc, hipStream_t s) {
+    if (nx == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_esc_count, dim3(grid_blocks(nx, BT)), dim3(BT), 0, s, xcol, nx, yrowptr, pc);
+    return hipGetLastError();
+}
+hipError_t launch_esc_expand(const uint32_t* xrow, const uint32_t* xcol, const uint64_t* xval, uint64_t nx,
+                             const uint64_t* poff, const uint64_t* yrowptr, const uint32_t* ycol, const uint64_t* yval,
+                             uint32_t* prow, uint32_t* pcol, uint64_t* pval, hipStream_t s) {
+    if (nx == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_esc_expand, dim3(grid_blocks(nx, BT)), dim3(BT), 0, s, xrow, xcol, xval, nx, poff, yrowptr,
+                       ycol, yval, prow, pcol, pval);
+    return hipGetLastError();
+}
+hipError_t launch_count_sat(const uint64_t* v, uint64_t n, unsigned long long* out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_sat, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, v, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace msc

@@ -88,6 +88,31 @@ ms_status ms_ctx_set_stream(ms_ctx* ctx, void* stream);
 /* Text describing the last non-OK status returned on this context. */
 const char* ms_last_error(const ms_ctx* ctx);
 
+/* Context options (ms_ctx_set_option). */
+enum {
+    MS_OPT_PATH_SCHEDULE = 1, /* how A* = sum_k A B^k is evaluated (Section 3.3) */
+    /* Tuning of the ready schedule's column merges; results never depend on
+     * them.  A column with at most MERGE_LIGHT inputs (0..32, default 32)
+     * and at most 8 input lists is merged by one thread; other columns are
+     * merged by a workgroup in chunks of MERGE_CHUNK entries (1..4096,
+     * default 4096). */
+    MS_OPT_MERGE_LIGHT = 2,
+    MS_OPT_MERGE_CHUNK = 3
+};
+enum {
+    /* Default.  A* is the solution of A* = A + A* B; its columns are formed by
+     * sparse products restricted to the junctions whose minor predecessors
+     * are complete (a ready frontier in topological order), so every
+     * (1-saddle, junction) pair is produced once.  Falls back to
+     * MS_PATHS_POWER by itself when a column has more than 64 inputs. */
+    MS_PATHS_READY = 0,
+    /* The paper's iteration: A* accumulates the frontier A, advanced by
+     * A <- A B until the product is empty, then P = D + A* B*. */
+    MS_PATHS_POWER = 1
+};
+/* Sets an option; MS_ERR_INVALID_ARG for an unknown option or value. */
+ms_status ms_ctx_set_option(ms_ctx* ctx, int option, int64_t value);
+
 /* Discrete gradient (Section 2.2 definitions; per-vertex lower-star pairing
  * as cited in Section 1.1 and used in the first step of Section 3).
  *   d_f    : device, nx*ny*nz float32, layout above.
@@ -163,6 +188,27 @@ typedef struct {
     int64_t count[4];
     ms_arcs arcs;      /* context-owned arc matrices */
 } ms_result;
+
+/* Per-stage device time of ms_complex calls, accumulated while timing is
+ * enabled (the paper breaks its runtime down the same way, Section 5,
+ * Figure 10).  Times come from HIP events recorded on the context's stream:
+ * gradient_ms brackets exactly the gradient kernel; the other stages bracket
+ * their kernels and the host round trips between them. */
+typedef struct {
+    double gradient_ms;  /* gradient kernel */
+    double critical_ms;  /* critical counts, scan, compaction */
+    double extrema_ms;   /* pointer jumping, M10 / M32 and transposes */
+    double bfs_ms;       /* saddle-saddle reachability */
+    double minor_ms;     /* junction numbering, DAG minor, minor matrices */
+    double paths_ms;     /* iterated products, P, M21 and transpose */
+    double total_ms;     /* whole ms_complex */
+    int64_t calls;
+} ms_timing;
+
+/* Enables (1) or disables (0) timing; enabling resets the accumulators. */
+ms_status ms_ctx_set_timing(ms_ctx* ctx, int enable);
+/* Copies the accumulated timing into *out (host). */
+ms_status ms_ctx_get_timing(ms_ctx* ctx, ms_timing* out);
 
 /* The whole hot path: ms_gradient, ms_critical and ms_connect on
  * context-owned buffers.  d_f is a device field; all results stay on the

@@ -114,6 +114,8 @@ void ms_ctx_destroy(ms_ctx* ctx) {
     for (auto& kv : ctx->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
     if (ctx->h_small) (void)hipHostFree(ctx->h_small);
+    for (auto& e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -124,6 +126,49 @@ ms_status ms_ctx_set_stream(ms_ctx* ctx, void* stream) {
 }
 
 const char* ms_last_error(const ms_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ms_status ms_ctx_set_option(ms_ctx* ctx, int option, int64_t value) {
+    if (!ctx) return MS_ERR_INVALID_ARG;
+    if (option == MS_OPT_PATH_SCHEDULE && (value == MS_PATHS_READY || value == MS_PATHS_POWER)) {
+        ctx->path_schedule = (int)value;
+        return MS_OK;
+    }
+    if (option == MS_OPT_MERGE_LIGHT && value >= 0 && value <= 32) {
+        ctx->merge_light = (uint32_t)value;
+        return MS_OK;
+    }
+    if (option == MS_OPT_MERGE_CHUNK && value >= 1 && value <= 4096) {
+        ctx->merge_chunk = (uint32_t)value;
+        return MS_OK;
+    }
+    ctx->err = "unknown option or value";
+    return MS_ERR_INVALID_ARG;
+}
+
+ms_status ms_ctx_set_timing(ms_ctx* ctx, int enable) {
+    API_BEGIN
+    if (enable) {
+        for (auto& e : ctx->ev)
+            if (!e) check(ctx, hipEventCreate(&e), "event create");
+    }
+    ctx->timing = enable != 0;
+    for (double& a : ctx->acc_ms) a = 0;
+    ctx->calls = 0;
+    API_END
+}
+
+ms_status ms_ctx_get_timing(ms_ctx* ctx, ms_timing* out) {
+    if (!ctx || !out) return MS_ERR_INVALID_ARG;
+    out->gradient_ms = ctx->acc_ms[0];
+    out->critical_ms = ctx->acc_ms[1];
+    out->extrema_ms = ctx->acc_ms[2];
+    out->bfs_ms = ctx->acc_ms[3];
+    out->minor_ms = ctx->acc_ms[4];
+    out->paths_ms = ctx->acc_ms[5];
+    out->total_ms = ctx->acc_ms[6];
+    out->calls = ctx->calls;
+    return MS_OK;
+}
 
 ms_status ms_gradient(ms_ctx* ctx, const float* d_f, ms_dims dims, uint32_t* d_grad) {
     API_BEGIN
@@ -179,7 +224,10 @@ ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out
     memset(out, 0, sizeof(*out));
     uint32_t* grad = buf<uint32_t>(ctx, "cx_grad", g.nv);
     int* d_err = buf<int>(ctx, "err_flag", 4);
-    gradient_impl(ctx, d_f, g, grad, d_err);
+    check(ctx, hipMemsetAsync(d_err, 0, sizeof(int), ctx->stream), "clear error flag");
+    mark(ctx, 0);
+    check(ctx, launch_gradient(d_f, g, grad, d_err, ctx->stream), "gradient kernel launch");
+    mark(ctx, 1);
     int64_t cnt[4];
     ms_status st = MS_OK;
     critical_impl(ctx, d_f, grad, g, nullptr, cnt, d_err, &st);
@@ -198,7 +246,21 @@ ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out
     out->grad = grad;
     out->crit = cr;
     for (int k = 0; k < 4; k++) out->count[k] = cnt[k];
+    mark(ctx, 2);
     connect_impl(ctx, grad, g, cr.id, cnt, &out->arcs);
+    mark(ctx, 6);
+    if (ctx->timing) {
+        check(ctx, hipEventSynchronize(ctx->ev[6]), "event synchronize");
+        for (int i = 0; i < 6; i++) {
+            float ms = 0;
+            check(ctx, hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]), "event elapsed");
+            ctx->acc_ms[i] += ms;
+        }
+        float tot = 0;
+        check(ctx, hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[6]), "event elapsed");
+        ctx->acc_ms[6] += tot;
+        ctx->calls++;
+    }
     API_END
 }
 

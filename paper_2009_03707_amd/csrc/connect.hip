@@ -4,7 +4,7 @@
 // depends on the data has a bound that turns a malformed input into an
 // error instead of an endless loop.
 #include "ctx.h"
-#include "prims.h"
+#include "paths.h"
 
 namespace msc {
 
@@ -34,8 +34,8 @@ hipError_t launch_esc_expand(const uint32_t* xrow, const uint32_t* xcol, const u
                              uint32_t* prow, uint32_t* pcol, uint64_t* pval, hipStream_t s);
 hipError_t launch_count_sat(const uint64_t* v, uint64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Grid& g,
-                             uint32_t* vis, uint32_t* next, unsigned long long* next_count, uint32_t* label,
-                             uint32_t* jlist, unsigned long long* jcount, hipStream_t s);
+                             uint32_t* vis, uint32_t* next, unsigned long long* counts, uint32_t* label,
+                             uint32_t* jlist, hipStream_t s);
 hipError_t launch_minor_trace(const uint32_t* s1, uint64_t S1, const uint32_t* jlist, uint64_t J, const uint32_t* grad,
                               const Grid& g, const uint32_t* label, uint64_t max_steps, uint64_t S2, uint8_t* out_t,
                               uint32_t* out_id, int* err, hipStream_t s);
@@ -205,134 +205,14 @@ Coo csr_as_coo(ms_ctx* c, const ms_csr& m, const char* rows_name) {
     return o;
 }
 
-}  // namespace
-
-void connect_impl(ms_ctx* c, const uint32_t* grad, const Grid& g, const uint32_t* crit, const int64_t cnt[4],
-                  ms_arcs* out) {
-    memset(out, 0, sizeof(*out));
+// Path counting as the paper iterates it (Section 3.3): A* accumulates the
+// frontier A, which is advanced by A <- A*B until the product is empty; then
+// P = D + A* B*.  Products are expand-sort-compress.  Writes M21 and M21t.
+void paths_power(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, const ms_csr& D, uint64_t S1,
+                 uint64_t S2, uint64_t J, ms_arcs* out) {
     hipStream_t s = c->stream;
-    const uint64_t S0 = (uint64_t)cnt[0], S1 = (uint64_t)cnt[1], S2 = (uint64_t)cnt[2], S3 = (uint64_t)cnt[3];
-    const uint32_t* s1 = crit + S0;
-    const uint32_t* s2 = crit + S0 + S1;
-    int* d_err = buf<int>(c, "cn_err", 1);
-    check(c, hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
     ms_stats& st = out->stats;
-
-    // ---- saddle-extremum arcs ------------------------------------------------
-    uint32_t* Pv = buf<uint32_t>(c, "pv", g.nv);
-    uint32_t* Pc = buf<uint32_t>(c, "pc", g.nv);
-    uint32_t* label = buf<uint32_t>(c, "cell_label", (uint64_t)8 * g.nv);
-    check(c, launch_pj_init(grad, g, Pv, Pc, d_err, s), "pj init");
-    check(c, launch_label(crit, cnt, grad, g, Pv, Pc, label, d_err, s), "label");
-    check_err_flag(c, d_err, "critical list labelling");
-    int* d_chg = buf<int>(c, "pj_changed", 1);
-    for (int which = 0; which < 2; which++) {
-        uint32_t* P = which == 0 ? Pv : Pc;
-        int64_t rounds = 0;
-        for (;;) {
-            check(c, hipMemsetAsync(d_chg, 0, sizeof(int), s), "memset");
-            check(c, launch_pj_round(P, g.nv, d_chg, s), "pj round");
-            rounds++;
-            uint64_t* slot = buf<uint64_t>(c, "pj_slot", 1);
-            check(c, hipMemsetAsync(slot, 0, sizeof(uint64_t), s), "memset");
-            check(c, hipMemcpyAsync(slot, d_chg, sizeof(int), hipMemcpyDeviceToDevice, s), "copy");
-            if (!read_u64(c, slot)) break;
-            if (rounds > 64) fail(c, MS_ERR_INTERNAL, "pointer jumping did not converge (cycle in the gradient)");
-        }
-        (which == 0 ? st.pj_rounds_vertex : st.pj_rounds_cube) = rounds;
-    }
-    {
-        uint32_t* rc = buf<uint32_t>(c, "rowcnt", S1 > S2 ? S1 : S2);
-        // M10
-        ms_csr& m10 = out->m10;
-        uint64_t* rp = buf<uint64_t>(c, "m10.rowptr", S1 + 1);
-        check(c, launch_m10(false, s1, S1, g, Pv, rc, nullptr, nullptr, nullptr, d_err, s), "m10 count");
-        uint64_t nnz = counts_to_rowptr(c, rc, S1, rp);
-        m10 = csr_buf(c, "m10", S1, S0, nnz);
-        check(c, launch_m10(true, s1, S1, g, Pv, nullptr, (const uint64_t*)m10.rowptr, m10.col, m10.val, d_err, s),
-              "m10 fill");
-        // M32 transposed (rows 2-saddles)
-        ms_csr& m32t = out->m32t;
-        uint64_t* rp2 = buf<uint64_t>(c, "m32t.rowptr", S2 + 1);
-        check(c, launch_m32t(false, s2, S2, g, Pc, rc, nullptr, nullptr, nullptr, d_err, s), "m32t count");
-        uint64_t nnz2 = counts_to_rowptr(c, rc, S2, rp2);
-        m32t = csr_buf(c, "m32t", S2, S3, nnz2);
-        check(c, launch_m32t(true, s2, S2, g, Pc, nullptr, (const uint64_t*)m32t.rowptr, m32t.col, m32t.val, d_err, s),
-              "m32t fill");
-        check_err_flag(c, d_err, "saddle-extremum arcs");
-        transpose(c, m10, "m10t", out->m10t);
-        transpose(c, m32t, "m32", out->m32);
-    }
-
-    // ---- saddle-saddle reachability (frontier BFS) --------------------------
-    uint64_t nvis = ((uint64_t)g.nv + 3) / 4;
-    uint32_t* vis = buf<uint32_t>(c, "visited", nvis);
-    check(c, hipMemsetAsync(vis, 0, 4 * nvis, s), "memset");
-    unsigned long long* d_cnt = (unsigned long long*)buf<uint64_t>(c, "bfs_counts", 2);  // [0] next, [1] junctions
-    check(c, hipMemsetAsync(d_cnt, 0, 16, s), "memset");
-    uint64_t ncur = S1, J = 0, reach = 0;
-    int64_t levels = 0;
-    const uint64_t max_nodes = (uint64_t)3 * g.nv + 1;
-    if (S1 > 0) {
-        uint32_t* fa = buf<uint32_t>(c, "front_a", ncur);
-        check(c, hipMemcpyAsync(fa, s1, 4 * ncur, hipMemcpyDeviceToDevice, s), "copy");
-        bool level0 = true;
-        const char* cur_name = "front_a";
-        const char* nxt_name = "front_b";
-        while (ncur > 0) {
-            uint32_t* cur = buf<uint32_t>(c, cur_name, ncur);
-            uint32_t* nxt = buf<uint32_t>(c, nxt_name, 4 * ncur);
-            uint32_t* jlist = buf_keep<uint32_t>(c, "jlist", J + ncur + 1, J);
-            check(c, hipMemsetAsync(d_cnt, 0, 8, s), "memset");
-            check(c, launch_bfs_expand(cur, ncur, level0, grad, g, vis, nxt, d_cnt, label, jlist, d_cnt + 1, s),
-                  "bfs expand");
-            uint64_t* h = readback(c, (const uint64_t*)d_cnt, 2);
-            uint64_t nn = h[0];
-            J = h[1];
-            reach += level0 ? 0 : ncur;
-            ncur = nn;
-            levels++;
-            level0 = false;
-            std::swap(cur_name, nxt_name);
-            if ((uint64_t)levels > max_nodes) fail(c, MS_ERR_INTERNAL, "BFS did not terminate");
-        }
-    }
-    st.bfs_levels = levels;
-    st.reachable = (int64_t)reach;
-    st.junctions = (int64_t)J;
-
-    // ---- DAG minor ----------------------------------------------------------
-    const uint64_t NS = S1 + J;
-    uint32_t* jlist = buf<uint32_t>(c, "jlist", J + 1);
-    uint8_t* out_t = buf<uint8_t>(c, "minor_t", 4 * NS);
-    uint32_t* out_id = buf<uint32_t>(c, "minor_id", 4 * NS);
-    check(c, launch_minor_trace(s1, S1, jlist, J, grad, g, label, max_nodes, S2, out_t, out_id, d_err, s), "minor trace");
-    uint32_t* cj = buf<uint32_t>(c, "minor_cj", NS);
-    uint32_t* cs = buf<uint32_t>(c, "minor_cs", NS);
-    check(c, launch_minor_rows(false, out_t, out_id, S1, NS, cj, cs, nullptr, nullptr, nullptr, nullptr, nullptr,
-                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s),
-          "minor rows");
-    check_err_flag(c, d_err, "DAG minor tracing");
-    uint64_t* rpA = buf<uint64_t>(c, "A.rowptr", S1 + 1);
-    uint64_t* rpD = buf<uint64_t>(c, "D.rowptr", S1 + 1);
-    uint64_t* rpB = buf<uint64_t>(c, "B.rowptr", J + 1);
-    uint64_t* rpBs = buf<uint64_t>(c, "Bs.rowptr", J + 1);
-    uint64_t nA = counts_to_rowptr(c, cj, S1, rpA);
-    uint64_t nD = counts_to_rowptr(c, cs, S1, rpD);
-    uint64_t nB = counts_to_rowptr(c, cj + S1, J, rpB);
-    uint64_t nBs = counts_to_rowptr(c, cs + S1, J, rpBs);
-    ms_csr A = csr_buf(c, "A", S1, J, nA), D = csr_buf(c, "D", S1, S2, nD);
-    ms_csr B = csr_buf(c, "B", J, J, nB), Bs = csr_buf(c, "Bs", J, S2, nBs);
-    check(c, launch_minor_rows(true, out_t, out_id, S1, NS, nullptr, nullptr, (const uint64_t*)A.rowptr, A.col, A.val,
-                               (const uint64_t*)D.rowptr, D.col, D.val, (const uint64_t*)B.rowptr, B.col, B.val,
-                               (const uint64_t*)Bs.rowptr, Bs.col, Bs.val, s),
-          "minor fill");
-    st.nnz_a = (int64_t)nA;
-    st.nnz_b = (int64_t)nB;
-    st.nnz_bstar = (int64_t)nBs;
-    st.nnz_d = (int64_t)nD;
-
-    // ---- path counting: A* = sum_k A B^k ; P = D + A* B* ---------------------
+    const uint64_t nD = (uint64_t)D.nnz;
     // Each iteration adds the current frontier of 1-saddle -> junction path
     // counts to the accumulation list and advances it by one level of the
     // minor (frontier <- frontier * B) until the product is empty.
@@ -380,6 +260,227 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Grid& g, const uint32_t
     Coo P = sort_merge(c, prod, S1, S2, "P");
     coo_to_csr(c, P, S1, S2, "m21t", out->m21t);
     transpose(c, out->m21t, "m21", out->m21);
+}
+
+// Path counting by column merges in topological order of the junction DAG
+// (see paths.hip).  Returns false when some column has more than 256
+// inputs; the caller then uses paths_power (the partial results here are
+// discarded).
+bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, const ms_csr& D, uint64_t S1,
+                 uint64_t S2, uint64_t J, ms_arcs* out, int* d_err) {
+    hipStream_t s = c->stream;
+    ms_stats& st = out->stats;
+    ms_csr At, Bt, Bst, Dt;
+    transpose(c, A, "At", At);     // junction x 1-saddle
+    transpose(c, B, "Bt", Bt);     // junction x predecessor junction
+    transpose(c, Bs, "Bst", Bst);  // 2-saddle x junction
+    transpose(c, D, "Dt", Dt);     // 2-saddle x 1-saddle
+    const uint64_t nmax = (J > S2 ? J : S2) + 1;
+    uint32_t* indeg = buf<uint32_t>(c, "pr.indeg", J);
+    uint32_t* ready[2] = {buf<uint32_t>(c, "pr.ready0", J), buf<uint32_t>(c, "pr.ready1", J)};
+    uint64_t* aoff = buf<uint64_t>(c, "pr.aoff", J);
+    uint32_t* alen = buf<uint32_t>(c, "pr.alen", J);
+    uint64_t* ub = buf<uint64_t>(c, "pr.ub", nmax + 1);
+    uint8_t* flag = buf<uint8_t>(c, "pr.flag", nmax);
+    uint32_t* heavy = buf<uint32_t>(c, "pr.heavy", nmax);
+    unsigned long long* d_n = (unsigned long long*)buf<uint64_t>(c, "pr.counts", 2);  // [0] ready, [1] heavy
+    uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(nmax) + 1);
+    check(c, hipMemsetAsync(d_n, 0, 16, s), "memset");
+    check(c, launch_ready_init((const uint64_t*)Bt.rowptr, J, indeg, ready[0], d_n, s), "ready init");
+    uint64_t r = J ? readback(c, (const uint64_t*)d_n, 1)[0] : 0;
+    uint64_t used = 0, processed = 0;
+    int64_t levels = 0;
+    uint32_t* arow = buf_keep<uint32_t>(c, "astar.row", 1, 0);
+    uint64_t* aval = buf_keep<uint64_t>(c, "astar.val", 1, 0);
+    int cur = 0;
+    while (r > 0) {
+        MergeLaunch m{ready[cur], r, (const uint64_t*)At.rowptr, At.col, At.val, (const uint64_t*)Bt.rowptr, Bt.col,
+                      Bt.val, aoff, alen, arow, aval, c->merge_light, c->merge_chunk};
+        check(c, hipMemsetAsync(d_n + 1, 0, 8, s), "memset");
+        check(c, launch_merge_classify(m, ub, flag, heavy, d_n + 1, d_err, aoff, alen, s), "merge classify");
+        check(c, scan_excl_u64(ub, ub, r, stmp, ub + r, s), "scan");
+        uint64_t t = read_u64(c, ub + r);
+        arow = buf_keep<uint32_t>(c, "astar.row", used + t, used);
+        aval = buf_keep<uint64_t>(c, "astar.val", used + t, used);
+        m.arow = arow;
+        m.aval = aval;
+        check(c, launch_merge(m, flag, heavy, d_n + 1, ub, used, arow, aval, nullptr, aoff, alen, s), "merge");
+        used += t;
+        processed += r;
+        levels++;
+        check(c, hipMemsetAsync(d_n, 0, 8, s), "memset");
+        check(c, launch_release(ready[cur], r, (const uint64_t*)B.rowptr, B.col, indeg, ready[1 - cur], d_n, d_err, s),
+              "release");
+        r = readback(c, (const uint64_t*)d_n, 1)[0];
+        cur = 1 - cur;
+        if ((uint64_t)levels > J + 1) fail(c, MS_ERR_INTERNAL, "path counting did not terminate");
+    }
+    if (processed != J) fail(c, MS_ERR_INTERNAL, "the junction graph has a cycle");
+    // P columns: M21 rows are 2-saddles with their 1-saddle path counts
+    MergeLaunch mp{nullptr, S2, (const uint64_t*)Dt.rowptr, Dt.col, Dt.val, (const uint64_t*)Bst.rowptr, Bst.col,
+                   Bst.val, aoff, alen, arow, aval, c->merge_light, c->merge_chunk};
+    check(c, hipMemsetAsync(d_n + 1, 0, 8, s), "memset");
+    check(c, launch_merge_classify(mp, ub, flag, heavy, d_n + 1, d_err, nullptr, nullptr, s), "merge classify");
+    check(c, scan_excl_u64(ub, ub, S2, stmp, ub + S2, s), "scan");
+    uint64_t tp = S2 ? read_u64(c, ub + S2) : 0;
+    uint32_t* prow = buf<uint32_t>(c, "pt.row", tp);
+    uint64_t* pval = buf<uint64_t>(c, "pt.val", tp);
+    uint32_t* pcnt = buf<uint32_t>(c, "pt.cnt", S2 + 1);
+    check(c, launch_merge(mp, flag, heavy, d_n + 1, ub, 0, prow, pval, pcnt, nullptr, nullptr, s), "merge");
+    uint64_t* slot = buf<uint64_t>(c, "err_slot", 1);
+    check(c, hipMemsetAsync(slot, 0, sizeof(uint64_t), s), "memset");
+    check(c, hipMemcpyAsync(slot, d_err, sizeof(int), hipMemcpyDeviceToDevice, s), "copy");
+    uint64_t ev = read_u64(c, slot);
+    if (ev & 32) {  // a column with more than 256 inputs: use the power iteration
+        check(c, hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
+        return false;
+    }
+    if (ev) fail(c, MS_ERR_INTERNAL, "consistency check failed in path counting (flag " + std::to_string(ev) + ")");
+    uint64_t* rp = buf<uint64_t>(c, "m21.rowptr", S2 + 1);
+    uint64_t nP = counts_to_rowptr(c, pcnt, S2, rp);
+    ms_csr m21 = csr_buf(c, "m21", S2, S1, nP);
+    check(c, launch_compact(ub, (const uint64_t*)m21.rowptr, S2, nP, prow, pval, m21.col, m21.val, s), "compact");
+    out->m21 = m21;
+    transpose(c, out->m21, "m21t", out->m21t);
+    st.spgemm_iters = levels;
+    st.nnz_astar = (int64_t)used;
+    st.products = (int64_t)(used + tp);
+    return true;
+}
+}  // namespace
+
+void connect_impl(ms_ctx* c, const uint32_t* grad, const Grid& g, const uint32_t* crit, const int64_t cnt[4],
+                  ms_arcs* out) {
+    memset(out, 0, sizeof(*out));
+    hipStream_t s = c->stream;
+    const uint64_t S0 = (uint64_t)cnt[0], S1 = (uint64_t)cnt[1], S2 = (uint64_t)cnt[2], S3 = (uint64_t)cnt[3];
+    const uint32_t* s1 = crit + S0;
+    const uint32_t* s2 = crit + S0 + S1;
+    int* d_err = buf<int>(c, "cn_err", 1);
+    check(c, hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
+    ms_stats& st = out->stats;
+
+    // ---- saddle-extremum arcs ------------------------------------------------
+    uint32_t* Pv = buf<uint32_t>(c, "pv", g.nv);
+    uint32_t* Pc = buf<uint32_t>(c, "pc", g.nv);
+    uint32_t* label = buf<uint32_t>(c, "cell_label", (uint64_t)8 * g.nv);
+    check(c, launch_pj_init(grad, g, Pv, Pc, d_err, s), "pj init");
+    check(c, launch_label(crit, cnt, grad, g, Pv, Pc, label, d_err, s), "label");
+    check_err_flag(c, d_err, "critical list labelling");
+    int* d_chg = (int*)buf<uint64_t>(c, "pj_changed", 32);  // 64 flag words
+    for (int which = 0; which < 2; which++) {
+        uint32_t* P = which == 0 ? Pv : Pc;
+        int64_t rounds = 0;
+        for (;;) {
+            check(c, hipMemsetAsync(d_chg, 0, 64 * sizeof(int), s), "memset");
+            check(c, launch_pj_round(P, g.nv, d_chg, s), "pj round");
+            rounds++;
+            const uint64_t* h = readback(c, (const uint64_t*)d_chg, 32);
+            bool any = false;
+            for (int i = 0; i < 32; i++) any = any || h[i] != 0;
+            if (!any) break;
+            if (rounds > 64) fail(c, MS_ERR_INTERNAL, "pointer jumping did not converge (cycle in the gradient)");
+        }
+        (which == 0 ? st.pj_rounds_vertex : st.pj_rounds_cube) = rounds;
+    }
+    {
+        uint32_t* rc = buf<uint32_t>(c, "rowcnt", S1 > S2 ? S1 : S2);
+        // M10
+        ms_csr& m10 = out->m10;
+        uint64_t* rp = buf<uint64_t>(c, "m10.rowptr", S1 + 1);
+        check(c, launch_m10(false, s1, S1, g, Pv, rc, nullptr, nullptr, nullptr, d_err, s), "m10 count");
+        uint64_t nnz = counts_to_rowptr(c, rc, S1, rp);
+        m10 = csr_buf(c, "m10", S1, S0, nnz);
+        check(c, launch_m10(true, s1, S1, g, Pv, nullptr, (const uint64_t*)m10.rowptr, m10.col, m10.val, d_err, s),
+              "m10 fill");
+        // M32 transposed (rows 2-saddles)
+        ms_csr& m32t = out->m32t;
+        uint64_t* rp2 = buf<uint64_t>(c, "m32t.rowptr", S2 + 1);
+        check(c, launch_m32t(false, s2, S2, g, Pc, rc, nullptr, nullptr, nullptr, d_err, s), "m32t count");
+        uint64_t nnz2 = counts_to_rowptr(c, rc, S2, rp2);
+        m32t = csr_buf(c, "m32t", S2, S3, nnz2);
+        check(c, launch_m32t(true, s2, S2, g, Pc, nullptr, (const uint64_t*)m32t.rowptr, m32t.col, m32t.val, d_err, s),
+              "m32t fill");
+        check_err_flag(c, d_err, "saddle-extremum arcs");
+        transpose(c, m10, "m10t", out->m10t);
+        transpose(c, m32t, "m32", out->m32);
+    }
+
+    mark(c, 3);
+    // ---- saddle-saddle reachability (frontier BFS) --------------------------
+    uint64_t nvis = ((uint64_t)g.nv + 3) / 4;
+    uint32_t* vis = buf<uint32_t>(c, "visited", nvis);
+    check(c, hipMemsetAsync(vis, 0, 4 * nvis, s), "memset");
+    // packed per-level counter: low 32 bits next frontier, high 32 bits junctions so far
+    unsigned long long* d_cnt = (unsigned long long*)buf<uint64_t>(c, "bfs_counts", 1);
+    uint64_t ncur = S1, J = 0, reach = 0;
+    int64_t levels = 0;
+    const uint64_t max_nodes = (uint64_t)3 * g.nv + 1;
+    if (S1 > 0) {
+        uint32_t* fa = buf<uint32_t>(c, "front_a", ncur);
+        check(c, hipMemcpyAsync(fa, s1, 4 * ncur, hipMemcpyDeviceToDevice, s), "copy");
+        bool level0 = true;
+        const char* cur_name = "front_a";
+        const char* nxt_name = "front_b";
+        while (ncur > 0) {
+            uint32_t* cur = buf<uint32_t>(c, cur_name, ncur);
+            uint32_t* nxt = buf<uint32_t>(c, nxt_name, 4 * ncur);
+            uint32_t* jlist = buf_keep<uint32_t>(c, "jlist", J + ncur + 1, J);
+            uint64_t init = J << 32;
+            check(c, hipMemcpyAsync(d_cnt, &init, 8, hipMemcpyHostToDevice, s), "counter init");
+            check(c, launch_bfs_expand(cur, ncur, level0, grad, g, vis, nxt, d_cnt, label, jlist, s), "bfs expand");
+            uint64_t h = readback(c, (const uint64_t*)d_cnt, 1)[0];
+            uint64_t nn = h & 0xFFFFFFFFull;
+            J = h >> 32;
+            reach += level0 ? 0 : ncur;
+            ncur = nn;
+            levels++;
+            level0 = false;
+            std::swap(cur_name, nxt_name);
+            if ((uint64_t)levels > max_nodes) fail(c, MS_ERR_INTERNAL, "BFS did not terminate");
+        }
+    }
+    st.bfs_levels = levels;
+    st.reachable = (int64_t)reach;
+    st.junctions = (int64_t)J;
+
+    mark(c, 4);
+    // ---- DAG minor ----------------------------------------------------------
+    const uint64_t NS = S1 + J;
+    uint32_t* jlist = buf<uint32_t>(c, "jlist", J + 1);
+    uint8_t* out_t = buf<uint8_t>(c, "minor_t", 4 * NS);
+    uint32_t* out_id = buf<uint32_t>(c, "minor_id", 4 * NS);
+    check(c, launch_minor_trace(s1, S1, jlist, J, grad, g, label, max_nodes, S2, out_t, out_id, d_err, s), "minor trace");
+    uint32_t* cj = buf<uint32_t>(c, "minor_cj", NS);
+    uint32_t* cs = buf<uint32_t>(c, "minor_cs", NS);
+    check(c, launch_minor_rows(false, out_t, out_id, S1, NS, cj, cs, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, s),
+          "minor rows");
+    check_err_flag(c, d_err, "DAG minor tracing");
+    uint64_t* rpA = buf<uint64_t>(c, "A.rowptr", S1 + 1);
+    uint64_t* rpD = buf<uint64_t>(c, "D.rowptr", S1 + 1);
+    uint64_t* rpB = buf<uint64_t>(c, "B.rowptr", J + 1);
+    uint64_t* rpBs = buf<uint64_t>(c, "Bs.rowptr", J + 1);
+    uint64_t nA = counts_to_rowptr(c, cj, S1, rpA);
+    uint64_t nD = counts_to_rowptr(c, cs, S1, rpD);
+    uint64_t nB = counts_to_rowptr(c, cj + S1, J, rpB);
+    uint64_t nBs = counts_to_rowptr(c, cs + S1, J, rpBs);
+    ms_csr A = csr_buf(c, "A", S1, J, nA), D = csr_buf(c, "D", S1, S2, nD);
+    ms_csr B = csr_buf(c, "B", J, J, nB), Bs = csr_buf(c, "Bs", J, S2, nBs);
+    check(c, launch_minor_rows(true, out_t, out_id, S1, NS, nullptr, nullptr, (const uint64_t*)A.rowptr, A.col, A.val,
+                               (const uint64_t*)D.rowptr, D.col, D.val, (const uint64_t*)B.rowptr, B.col, B.val,
+                               (const uint64_t*)Bs.rowptr, Bs.col, Bs.val, s),
+          "minor fill");
+    st.nnz_a = (int64_t)nA;
+    st.nnz_b = (int64_t)nB;
+    st.nnz_bstar = (int64_t)nBs;
+    st.nnz_d = (int64_t)nD;
+
+    mark(c, 5);
+    // ---- path counting --------------------------------------------------------
+    bool done = false;
+    if (c->path_schedule == MS_PATHS_READY) done = paths_ready(c, A, B, Bs, D, S1, S2, J, out, d_err);
+    if (!done) paths_power(c, A, B, Bs, D, S1, S2, J, out);
     unsigned long long* d_sat = (unsigned long long*)buf<uint64_t>(c, "sat_count", 1);
     check(c, hipMemsetAsync(d_sat, 0, 8, s), "memset");
     check(c, launch_count_sat(out->m21t.val, (uint64_t)out->m21t.nnz, d_sat, s), "count saturated");

@@ -23,6 +23,14 @@ struct ms_ctx {
     };
     std::map<std::string, Buf> bufs;
     uint64_t* h_small = nullptr;  // pinned host scratch (64 words)
+    // stage timing (events at stage boundaries of ms_complex)
+    bool timing = false;
+    hipEvent_t ev[8] = {};
+    double acc_ms[8] = {};
+    int64_t calls = 0;
+    int path_schedule = MS_PATHS_READY;
+    uint32_t merge_light = 32;   // see MS_OPT_MERGE_LIGHT
+    uint32_t merge_chunk = 4096; // see MS_OPT_MERGE_CHUNK
 };
 
 namespace msc {
@@ -95,6 +103,11 @@ inline uint64_t* readback(ms_ctx* c, const uint64_t* d, size_t n) {
     check(c, hipMemcpyAsync(c->h_small, d, n * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream), "readback");
     check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     return c->h_small;
+}
+
+// Records boundary event i of ms_complex on the context stream (timing only).
+inline void mark(ms_ctx* c, int i) {
+    if (c->timing) check(c, hipEventRecord(c->ev[i], c->stream), "event record");
 }
 
 }  // namespace msc

@@ -88,9 +88,12 @@ __global__ __launch_bounds__(BT) void k_label(const uint32_t* __restrict__ crit,
     else if (idx == 2) label[id] = rank;
 }
 
+// One jump for every unfinished pointer.  `changed` holds 64 words; a
+// workgroup with an unfinished pointer stores 1 into one of them (spread so
+// that the stores do not queue on a single address).
 __global__ __launch_bounds__(BT) void k_pj_round(uint32_t* __restrict__ P, uint32_t n, int* __restrict__ changed) {
     uint32_t i = blockIdx.x * BT + threadIdx.x;
-    bool active = false;
+    int active = 0;
     if (i < n) {
         uint32_t p = P[i];
         if (!(p & ROOT_FLAG)) {
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(BT) void k_pj_round(uint32_t* __restrict__ P, uint3
             active = !(q & ROOT_FLAG);
         }
     }
-    if (__any(active) && lane_id() == 0) atomicOr(changed, 1);
+    if (__syncthreads_or(active) && threadIdx.x == 0) changed[blockIdx.x & 63u] = 1;
 }
 
 // M10 rows: the two vertices of each 1-saddle lead to their minima.

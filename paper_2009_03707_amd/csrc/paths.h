@@ -1,0 +1,47 @@
+// Launchers of the column-merge path counting (paths.hip).
+#pragma once
+
+#include "prims.h"
+
+namespace msc {
+
+// Output column c of a merge is the sorted union of its base list (row c of
+// the base CSR) and the A* columns of its predecessors (row c of the
+// predecessor CSR: junction ids and multiplicities).
+struct MergeLaunch {
+    const uint32_t* cols;  // output columns to form (null: 0..n-1)
+    uint64_t n;
+    const uint64_t* brp;
+    const uint32_t* bcol;
+    const uint64_t* bval;
+    const uint64_t* prp;
+    const uint32_t* pcol;
+    const uint64_t* pval;
+    const uint64_t* aoff;  // A* column offsets / lengths / storage
+    const uint32_t* alen;
+    const uint32_t* arow;
+    const uint64_t* aval;
+    uint32_t light_ub;  // columns with at most this many inputs (and <= 8 lists) merge in one thread
+    uint32_t chunk;     // other columns merge in chunks of this many entries (1..4096)
+};
+
+// Upper bound (input entries) per output column into ub, and the queue of
+// columns that need a workgroup (heavy / nheavy).  Columns with more than 256
+// inputs set bit 32 of *err and are given an empty range.
+hipError_t launch_merge_classify(const MergeLaunch& m, uint64_t* ub, uint8_t* heavy_flag, uint32_t* heavy,
+                                 unsigned long long* nheavy, int* err, uint64_t* col_off, uint32_t* col_len,
+                                 hipStream_t s);
+// Forms every output column i at out_base + off[i] (off: exclusive scan of
+// ub).  Writes its length to cnt[i] and/or to (col_off, col_len)[column].
+hipError_t launch_merge(const MergeLaunch& m, const uint8_t* heavy_flag, const uint32_t* heavy,
+                        const unsigned long long* nheavy, const uint64_t* off, uint64_t out_base, uint32_t* orow,
+                        uint64_t* oval, uint32_t* cnt, uint64_t* col_off, uint32_t* col_len, hipStream_t s);
+// Copies column i from src_off[i] to dst_off[i] (dst_off: n + 1 entries).
+hipError_t launch_compact(const uint64_t* src_off, const uint64_t* dst_off, uint64_t n, uint64_t total,
+                          const uint32_t* srow, const uint64_t* sval, uint32_t* drow, uint64_t* dval, hipStream_t s);
+hipError_t launch_ready_init(const uint64_t* prp, uint64_t J, uint32_t* indeg, uint32_t* ready,
+                             unsigned long long* nready, hipStream_t s);
+hipError_t launch_release(const uint32_t* ready, uint64_t n, const uint64_t* brp, const uint32_t* bcol,
+                          uint32_t* indeg, uint32_t* next, unsigned long long* nnext, int* err, hipStream_t s);
+
+}  // namespace msc

@@ -56,9 +56,8 @@ __device__ __forceinline__ bool quad_edge_partner(const Grid& g, uint32_t qw, ui
 __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ cur, uint64_t ncur, int level0,
                                                    const uint32_t* __restrict__ grad, Grid g,
                                                    uint32_t* __restrict__ vis, uint32_t* __restrict__ next,
-                                                   unsigned long long* __restrict__ next_count,
-                                                   uint32_t* __restrict__ label, uint32_t* __restrict__ jlist,
-                                                   unsigned long long* __restrict__ jcount) {
+                                                   unsigned long long* __restrict__ counts,
+                                                   uint32_t* __restrict__ label, uint32_t* __restrict__ jlist) {
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
     bool valid = i < ncur;
     uint32_t t[4];
@@ -92,28 +91,22 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
             }
         }
     }
-    // append the newly visited edges, one atomic per wave
-    uint32_t incl = wave_incl_scan(nt);
-    uint32_t tot = __shfl(incl, WAVE - 1, WAVE);
-    unsigned long long base = 0;
-    if (tot) {
-        if (lane_id() == WAVE - 1) base = atomicAdd(next_count, (unsigned long long)tot);
-        base = __shfl(base, WAVE - 1, WAVE);
-    }
-    uint64_t o = base + incl - nt;
-    for (uint32_t q = 0; q < nt; q++) next[o + q] = t[q];
-    // junctions among reachable non-saddle nodes
+    // append the newly visited edges and number the junctions with one
+    // atomic per workgroup on a packed counter (low 32 bits: frontier,
+    // high 32 bits: junctions)
+    __shared__ unsigned long long sc[BT / WAVE + 1];
+    __shared__ unsigned long long base;
     uint32_t isj = (valid && !level0 && outdeg > 1) ? 1u : 0u;
-    uint32_t jin = wave_incl_scan(isj);
-    uint32_t jtot = __shfl(jin, WAVE - 1, WAVE);
-    unsigned long long jb = 0;
-    if (jtot) {
-        if (lane_id() == WAVE - 1) jb = atomicAdd(jcount, (unsigned long long)jtot);
-        jb = __shfl(jb, WAVE - 1, WAVE);
-    }
+    unsigned long long packed = (unsigned long long)nt | ((unsigned long long)isj << 32);
+    unsigned long long tot;
+    unsigned long long ex = block_excl_scan<unsigned long long, BT>(packed, sc, tot);
+    if (threadIdx.x == 0) base = tot ? atomicAdd(counts, tot) : 0ull;
+    __syncthreads();
+    uint64_t o = (base & 0xFFFFFFFFull) + (ex & 0xFFFFFFFFull);
+    for (uint32_t q = 0; q < nt; q++) next[o + q] = t[q];
     if (valid && !level0) {
         if (isj) {
-            uint32_t jid = (uint32_t)(jb + jin - 1u);
+            uint32_t jid = (uint32_t)((base >> 32) + (ex >> 32));
             label[e] = jid;
             jlist[jid] = e;
         } else {
@@ -263,11 +256,11 @@ __global__ __launch_bounds__(BT) void k_minor_rows(const uint8_t* __restrict__ o
 }  // namespace
 
 hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Grid& g,
-                             uint32_t* vis, uint32_t* next, unsigned long long* next_count, uint32_t* label,
-                             uint32_t* jlist, unsigned long long* jcount, hipStream_t s) {
+                             uint32_t* vis, uint32_t* next, unsigned long long* counts, uint32_t* label,
+                             uint32_t* jlist, hipStream_t s) {
     if (ncur == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bfs_expand, dim3(grid_blocks(ncur, BT)), dim3(BT), 0, s, cur, ncur, level0 ? 1 : 0, grad, g,
-                       vis, next, next_count, label, jlist, jcount);
+                       vis, next, counts, label, jlist);
     return hipGetLastError();
 }
 

@@ -20,7 +20,11 @@ MS_OK, MS_ERR_INVALID_ARG, MS_ERR_NONFINITE, MS_ERR_TOO_LARGE, MS_ERR_CAPACITY, 
     MS_ERR_INTERNAL = range(8)
 
 EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_error", "ms_gradient",
-            "ms_critical", "ms_connect", "ms_complex"]
+            "ms_critical", "ms_connect", "ms_complex", "ms_ctx_set_timing", "ms_ctx_get_timing",
+            "ms_ctx_set_option"]
+
+MS_OPT_PATH_SCHEDULE, MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK = 1, 2, 3
+MS_PATHS_READY, MS_PATHS_POWER = 0, 1
 
 
 class MscError(RuntimeError):
@@ -54,6 +58,11 @@ class Arcs(C.Structure):
                 ("n_saturated", C.c_int64), ("stats", Stats)]
 
 
+class Timing(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("gradient_ms", "critical_ms", "extrema_ms", "bfs_ms", "minor_ms",
+                                          "paths_ms", "total_ms")] + [("calls", C.c_int64)]
+
+
 class Result(C.Structure):
     _fields_ = [("grad", C.c_void_p), ("crit", Crit), ("count", C.c_int64 * 4), ("arcs", Arcs)]
 
@@ -79,6 +88,9 @@ def lib():
         L.ms_critical.argtypes = [vp, vp, vp, Dims, C.POINTER(Crit), C.POINTER(i64)]
         L.ms_connect.argtypes = [vp, vp, Dims, vp, C.POINTER(i64), C.POINTER(Arcs)]
         L.ms_complex.argtypes = [vp, vp, Dims, C.POINTER(Result)]
+        L.ms_ctx_set_timing.argtypes = [vp, C.c_int]
+        L.ms_ctx_get_timing.argtypes = [vp, C.POINTER(Timing)]
+        L.ms_ctx_set_option.argtypes = [vp, C.c_int, C.c_int64]
         for n in EXPORTED:
             getattr(L, n)
         _LIB = L
@@ -141,6 +153,21 @@ class Context:
         if st != MS_OK:
             msg = lib().ms_last_error(self._h)
             raise MscError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def set_path_schedule(self, schedule: int):
+        """MS_PATHS_READY (default) or MS_PATHS_POWER (the paper's iteration)."""
+        self._raise(lib().ms_ctx_set_option(self._h, MS_OPT_PATH_SCHEDULE, int(schedule)), "ms_ctx_set_option")
+
+    def set_option(self, option: int, value: int):
+        self._raise(lib().ms_ctx_set_option(self._h, int(option), int(value)), "ms_ctx_set_option")
+
+    def set_timing(self, on: bool):
+        self._raise(lib().ms_ctx_set_timing(self._h, 1 if on else 0), "ms_ctx_set_timing")
+
+    def timing(self) -> dict:
+        t = Timing()
+        self._raise(lib().ms_ctx_get_timing(self._h, C.byref(t)), "ms_ctx_get_timing")
+        return {k: getattr(t, k) for k, _ in Timing._fields_}
 
     # -- entry points -------------------------------------------------------
     def gradient(self, f: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

@@ -11,12 +11,20 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=["ready", "power", "ready-chunked"])
+def ctx(request):
+    """Both path-counting schedules: the default ready frontier and the
+    paper's power iteration; "ready-chunked" sends every column through the
+    workgroup merge with tiny chunks, so that chunk splitting is exercised on
+    small fields."""
     from paper_2009_03707_amd import msc
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c = msc.Context()
+    c.set_path_schedule(msc.MS_PATHS_POWER if request.param == "power" else msc.MS_PATHS_READY)
+    if request.param == "ready-chunked":
+        c.set_option(msc.MS_OPT_MERGE_LIGHT, 0)
+        c.set_option(msc.MS_OPT_MERGE_CHUNK, 3)
     yield c
     c.close()
 
@@ -74,7 +82,7 @@ def test_random_fields(ctx, kind, dims, seed, levels):
     check_complex(ctx, fields.random_field(dims, seed=seed, levels=levels))
 
 
-@pytest.mark.parametrize("name", ["sine32", "grf48", "blob64", "monotone", "constant"])
+@pytest.mark.parametrize("name", ["sine32", "grf48", "blob64", "blob72dense", "monotone", "constant"])
 def test_structured_fields(ctx, name):
     if name == "sine32":
         f = fields.sine_field(32)
@@ -82,6 +90,8 @@ def test_structured_fields(ctx, name):
         f = fields.grf_field((48, 44, 40), seed=2)
     elif name == "blob64":
         f = fields.blob_field((64, 64, 64), nblobs=4, seed=0)
+    elif name == "blob72dense":
+        f = fields.blob_field((72, 70, 66), nblobs=12, seed=5)
     elif name == "monotone":
         f = np.arange(30 * 20 * 10, dtype=np.float32).reshape(10, 20, 30)
     else:

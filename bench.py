@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="blobs512")
-    ap.add_argument("--cpu-sample", type=int, default=112, help="side of the oracle crop (0 = skip)")
+    ap.add_argument("--cpu-sample", type=int, default=160, help="side of the oracle crop (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the hot path is measured on a single MI355X "

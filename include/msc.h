@@ -215,6 +215,24 @@ ms_status ms_ctx_get_timing(ms_ctx* ctx, ms_timing* out);
  * device, owned by the context until its next call. */
 ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out);
 
+/* Batched hot path: nfields fields of any (non-cubic, uneven) dims in one
+ * launch per phase.  The fields are processed as one complex over their
+ * concatenation -- cells of different fields are never adjacent, so every
+ * arc matrix is block diagonal -- and each field's part is then copied out
+ * with local ids and ranks: outs[f] is byte-identical to ms_complex on field
+ * f alone (stats excepted: they describe the whole batch).  The iteration
+ * counts of the data-dependent loops (BFS levels, pointer-jumping rounds,
+ * path-counting levels) are the maximum over the fields, not the sum.
+ *   nfields : 1..1024.
+ *   d_f     : host array of nfields device pointers to float32 fields.
+ *   dims    : host array of nfields dims.
+ *   outs    : host array of nfields results; every pointer is
+ *             context-owned and valid until the next call on the context.
+ * Errors: as ms_complex, plus MS_ERR_TOO_LARGE when the fields together have
+ * more than 2^29 vertices (split the batch). */
+ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f, const ms_dims* dims,
+                           ms_result* outs);
+
 #ifdef __cplusplus
 }
 #endif

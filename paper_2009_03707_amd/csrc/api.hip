@@ -3,17 +3,45 @@
 // context's stream and converts failures into ms_status codes.
 #include <string.h>
 
+#include <vector>
+
 #include "ctx.h"
 #include "prims.h"
 
 namespace msc {
-hipError_t launch_gradient(const float* f, const Grid& g, uint32_t* grad, int* err, hipStream_t s);
+uint32_t gradient_tiles(const Grid& g);
+hipError_t launch_gradient(const float* f0, const float* const* fptr, const Geo& geo, const uint32_t* tile_off,
+                           uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s);
 size_t crit_tmp_elems(uint64_t nv);
-hipError_t launch_crit_count(const uint32_t* grad, const Grid& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s);
-hipError_t launch_crit_scatter(const float* f, const uint32_t* grad, const Grid& g, const uint64_t* tmp, uint32_t* id,
-                               uint8_t* index, float* value, uint32_t* vmax, hipStream_t s);
-void connect_impl(ms_ctx* c, const uint32_t* grad, const Grid& g, const uint32_t* crit_id, const int64_t count[4],
+hipError_t launch_crit_count(const uint32_t* grad, const Geo& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s);
+hipError_t launch_crit_scatter(const float* f0, const float* const* fptr, const uint32_t* grad, const Geo& g,
+                               const uint64_t* tmp, uint32_t* id, uint8_t* index, float* value, uint32_t* vmax,
+                               hipStream_t s);
+void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t* crit_id, const int64_t count[4],
                   ms_arcs* out);
+
+hipError_t launch_gather_u64(const uint64_t* src, const uint64_t* idx, uint64_t n, uint64_t* dst, hipStream_t s);
+hipError_t launch_crit_field_counts(const uint32_t* id, uint64_t n, const Geo& geo, unsigned long long* cnt,
+                                    hipStream_t s);
+hipError_t launch_crit_split(const uint32_t* id, const uint8_t* index, const float* value, const uint32_t* vmax,
+                             uint64_t n, const Geo& geo, const uint64_t* seg, const uint64_t* fk_before,
+                             const uint64_t* fk_start, uint32_t* o_id, uint8_t* o_index, float* o_value,
+                             uint32_t* o_vmax, hipStream_t s);
+hipError_t launch_csr_split(const uint64_t* rowptr, uint64_t nrows, const uint32_t* col, uint64_t nnz,
+                            const uint64_t* roff, const uint64_t* coff, const uint64_t* eoff, uint32_t nf,
+                            uint64_t* orp, uint32_t* ocol, hipStream_t s);
+hipError_t launch_sat_per_field(const uint64_t* val, uint64_t nnz, const uint64_t* eoff, uint32_t nf,
+                                unsigned long long* out, hipStream_t s);
+
+Geo single(const Grid& g) {
+    Geo geo;
+    geo.grids = nullptr;
+    geo.voff = nullptr;
+    geo.nf = 1;
+    geo.nv = g.nv;
+    geo.g0 = g;
+    return geo;
+}
 
 Grid check_dims(ms_ctx* c, ms_dims d) {
     if (d.nx < 1 || d.ny < 1 || d.nz < 1) fail(c, MS_ERR_INVALID_ARG, "every dimension must be >= 1");
@@ -26,12 +54,13 @@ Grid check_dims(ms_ctx* c, ms_dims d) {
 // gradient + non-finite flag (flag left on the device at *d_err)
 void gradient_impl(ms_ctx* c, const float* f, const Grid& g, uint32_t* grad, int* d_err) {
     check(c, hipMemsetAsync(d_err, 0, sizeof(int), c->stream), "clear error flag");
-    check(c, launch_gradient(f, g, grad, d_err, c->stream), "gradient kernel launch");
+    check(c, launch_gradient(f, nullptr, single(g), nullptr, gradient_tiles(g), grad, d_err, c->stream),
+          "gradient kernel launch");
 }
 
 // counts per index (host) after pass 1; optional scatter into `out`
-void critical_impl(ms_ctx* c, const float* f, const uint32_t* grad, const Grid& g, const ms_crit* out,
-                   int64_t h_count[4], const int* d_err, ms_status* nonfinite) {
+void critical_impl(ms_ctx* c, const float* f, const float* const* fptr, const uint32_t* grad, const Geo& g,
+                   const ms_crit* out, int64_t h_count[4], const int* d_err, ms_status* nonfinite) {
     uint64_t* tmp = buf<uint64_t>(c, "crit_tmp", crit_tmp_elems(g.nv) + 1);
     uint64_t* d_tot = nullptr;
     check(c, launch_crit_count(grad, g, tmp, &d_tot, c->stream), "critical count launch");
@@ -60,7 +89,7 @@ void critical_impl(ms_ctx* c, const float* f, const uint32_t* grad, const Grid& 
     }
     if (total == 0) return;
     if (!out->id || !out->index || !out->value || !out->vmax) fail(c, MS_ERR_INVALID_ARG, "null critical output array");
-    check(c, launch_crit_scatter(f, grad, g, tmp, out->id, out->index, out->value, out->vmax, c->stream),
+    check(c, launch_crit_scatter(f, fptr, grad, g, tmp, out->id, out->index, out->value, out->vmax, c->stream),
           "critical scatter launch");
 }
 
@@ -99,7 +128,7 @@ ms_status ms_ctx_create(ms_ctx** out, void* stream) {
         delete c;
         return MS_ERR_HIP;
     }
-    if (hipHostMalloc((void**)&c->h_small, 64 * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->h_small, HOST_SCRATCH_WORDS * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
         return MS_ERR_OOM;
@@ -190,7 +219,7 @@ ms_status ms_critical(ms_ctx* ctx, const float* d_f, const uint32_t* d_grad, ms_
     Grid g = check_dims(ctx, dims);
     if (!d_f || !d_grad || !h_count) fail(ctx, MS_ERR_INVALID_ARG, "null argument");
     ms_status st = MS_OK;
-    critical_impl(ctx, d_f, d_grad, g, out, h_count, nullptr, &st);
+    critical_impl(ctx, d_f, nullptr, d_grad, single(g), out, h_count, nullptr, &st);
     if (st == MS_ERR_CAPACITY) fail(ctx, st, "critical output capacity too small");
     API_END
 }
@@ -210,11 +239,25 @@ ms_status ms_connect(ms_ctx* ctx, const uint32_t* d_grad, ms_dims dims, const ui
     // the counts here; the labelling pass checks each entry
     int64_t have[4];
     ms_status st = MS_OK;
-    critical_impl(ctx, nullptr, d_grad, g, nullptr, have, nullptr, &st);
+    critical_impl(ctx, nullptr, nullptr, d_grad, single(g), nullptr, have, nullptr, &st);
     for (int k = 0; k < 4; k++)
         if (have[k] != h_count[k]) fail(ctx, MS_ERR_INVALID_ARG, "critical counts do not match the gradient");
-    connect_impl(ctx, d_grad, g, d_crit_id, h_count, out);
+    connect_impl(ctx, d_grad, single(g), d_crit_id, h_count, out);
     API_END
+}
+
+static void accumulate_timing(ms_ctx* ctx) {
+    if (!ctx->timing) return;
+    check(ctx, hipEventSynchronize(ctx->ev[6]), "event synchronize");
+    for (int i = 0; i < 6; i++) {
+        float ms = 0;
+        check(ctx, hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]), "event elapsed");
+        ctx->acc_ms[i] += ms;
+    }
+    float tot = 0;
+    check(ctx, hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[6]), "event elapsed");
+    ctx->acc_ms[6] += tot;
+    ctx->calls++;
 }
 
 ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out) {
@@ -226,11 +269,12 @@ ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out
     int* d_err = buf<int>(ctx, "err_flag", 4);
     check(ctx, hipMemsetAsync(d_err, 0, sizeof(int), ctx->stream), "clear error flag");
     mark(ctx, 0);
-    check(ctx, launch_gradient(d_f, g, grad, d_err, ctx->stream), "gradient kernel launch");
+    check(ctx, launch_gradient(d_f, nullptr, single(g), nullptr, gradient_tiles(g), grad, d_err, ctx->stream),
+          "gradient kernel launch");
     mark(ctx, 1);
     int64_t cnt[4];
     ms_status st = MS_OK;
-    critical_impl(ctx, d_f, grad, g, nullptr, cnt, d_err, &st);
+    critical_impl(ctx, d_f, nullptr, grad, single(g), nullptr, cnt, d_err, &st);
     if (st == MS_ERR_NONFINITE) fail(ctx, st, "the field contains NaN or infinite values");
     int64_t total = cnt[0] + cnt[1] + cnt[2] + cnt[3];
     ms_crit cr;
@@ -240,27 +284,177 @@ ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out
     cr.vmax = buf<uint32_t>(ctx, "cx_crit_vmax", total);
     cr.capacity = total;
     if (total > 0)
-        check(ctx, launch_crit_scatter(d_f, grad, g, buf<uint64_t>(ctx, "crit_tmp", 1), cr.id, cr.index, cr.value,
-                                       cr.vmax, ctx->stream),
+        check(ctx, launch_crit_scatter(d_f, nullptr, grad, single(g), buf<uint64_t>(ctx, "crit_tmp", 1), cr.id,
+                                       cr.index, cr.value, cr.vmax, ctx->stream),
               "critical scatter launch");
     out->grad = grad;
     out->crit = cr;
     for (int k = 0; k < 4; k++) out->count[k] = cnt[k];
     mark(ctx, 2);
-    connect_impl(ctx, grad, g, cr.id, cnt, &out->arcs);
+    connect_impl(ctx, grad, single(g), cr.id, cnt, &out->arcs);
     mark(ctx, 6);
-    if (ctx->timing) {
-        check(ctx, hipEventSynchronize(ctx->ev[6]), "event synchronize");
-        for (int i = 0; i < 6; i++) {
-            float ms = 0;
-            check(ctx, hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]), "event elapsed");
-            ctx->acc_ms[i] += ms;
-        }
-        float tot = 0;
-        check(ctx, hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[6]), "event elapsed");
-        ctx->acc_ms[6] += tot;
-        ctx->calls++;
+    accumulate_timing(ctx);
+    API_END
+}
+
+ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f, const ms_dims* dims,
+                           ms_result* outs) {
+    API_BEGIN
+    if (nfields < 1 || nfields > 1024 || !d_f || !dims || !outs)
+        fail(ctx, MS_ERR_INVALID_ARG, "need 1..1024 fields and non-null arrays");
+    hipStream_t s = ctx->stream;
+    const uint32_t nf = (uint32_t)nfields;
+    std::vector<Grid> grids(nf);
+    std::vector<uint32_t> voff(nf + 1), toff(nf + 1);
+    uint64_t total = 0, tiles = 0;
+    for (uint32_t f = 0; f < nf; f++) {
+        grids[f] = check_dims(ctx, dims[f]);
+        if (!d_f[f]) fail(ctx, MS_ERR_INVALID_ARG, "null field pointer");
+        voff[f] = (uint32_t)total;
+        toff[f] = (uint32_t)tiles;
+        total += grids[f].nv;
+        tiles += gradient_tiles(grids[f]);
+        if (total > ((uint64_t)1 << 29)) fail(ctx, MS_ERR_TOO_LARGE, "the batch has more than 2^29 vertices");
     }
+    voff[nf] = (uint32_t)total;
+    toff[nf] = (uint32_t)tiles;
+    // field tables on the device
+    Grid* d_grids = buf<Grid>(ctx, "bx.grids", nf);
+    uint32_t* d_voff = buf<uint32_t>(ctx, "bx.voff", nf + 1);
+    uint32_t* d_toff = buf<uint32_t>(ctx, "bx.toff", nf + 1);
+    const float** d_fptr = buf<const float*>(ctx, "bx.fptr", nf);
+    check(ctx, hipMemcpyAsync(d_grids, grids.data(), sizeof(Grid) * nf, hipMemcpyHostToDevice, s), "table copy");
+    check(ctx, hipMemcpyAsync(d_voff, voff.data(), 4 * (nf + 1), hipMemcpyHostToDevice, s), "table copy");
+    check(ctx, hipMemcpyAsync(d_toff, toff.data(), 4 * (nf + 1), hipMemcpyHostToDevice, s), "table copy");
+    check(ctx, hipMemcpyAsync(d_fptr, d_f, sizeof(float*) * nf, hipMemcpyHostToDevice, s), "table copy");
+    Geo geo;
+    geo.grids = d_grids;
+    geo.voff = d_voff;
+    geo.nf = nf;
+    geo.nv = (uint32_t)total;
+    geo.g0 = grids[0];
+    // the hot path over the concatenation
+    uint32_t* grad = buf<uint32_t>(ctx, "cx_grad", total);
+    int* d_err = buf<int>(ctx, "err_flag", 4);
+    check(ctx, hipMemsetAsync(d_err, 0, sizeof(int), s), "clear error flag");
+    mark(ctx, 0);
+    check(ctx, launch_gradient(d_f[0], d_fptr, geo, d_toff, tiles, grad, d_err, s), "gradient kernel launch");
+    mark(ctx, 1);
+    int64_t cnt[4];
+    ms_status st = MS_OK;
+    critical_impl(ctx, d_f[0], d_fptr, grad, geo, nullptr, cnt, d_err, &st);
+    if (st == MS_ERR_NONFINITE) fail(ctx, st, "a field contains NaN or infinite values");
+    const int64_t ncrit = cnt[0] + cnt[1] + cnt[2] + cnt[3];
+    ms_crit cr;
+    cr.id = buf<uint32_t>(ctx, "cx_crit_id", ncrit);
+    cr.index = buf<uint8_t>(ctx, "cx_crit_index", ncrit);
+    cr.value = buf<float>(ctx, "cx_crit_value", ncrit);
+    cr.vmax = buf<uint32_t>(ctx, "cx_crit_vmax", ncrit);
+    cr.capacity = ncrit;
+    if (ncrit > 0)
+        check(ctx, launch_crit_scatter(d_f[0], d_fptr, grad, geo, buf<uint64_t>(ctx, "crit_tmp", 1), cr.id, cr.index,
+                                       cr.value, cr.vmax, s),
+              "critical scatter launch");
+    mark(ctx, 2);
+    ms_arcs arcs;
+    connect_impl(ctx, grad, geo, cr.id, cnt, &arcs);
+    // ---- split into per-field results ------------------------------------
+    unsigned long long* d_fk = (unsigned long long*)buf<uint64_t>(ctx, "bx.fk", 4 * nf);
+    check(ctx, hipMemsetAsync(d_fk, 0, 8 * 4 * nf, s), "memset");
+    check(ctx, launch_crit_field_counts(cr.id, (uint64_t)ncrit, geo, d_fk, s), "field counts");
+    std::vector<uint64_t> fk(4 * nf);
+    {
+        const uint64_t* h = readback(ctx, (const uint64_t*)d_fk, 4 * nf);
+        for (uint32_t i = 0; i < 4 * nf; i++) fk[i] = h[i];
+    }
+    // fk_before[f][k]: cells of index k in earlier fields (f = nf: all);
+    // fk_start[f][k]: first output position of (f, k); crit_off[f]: first of f
+    std::vector<uint64_t> before(4 * (nf + 1)), start(4 * nf), crit_off(nf + 1), seg(4);
+    seg[0] = 0;
+    for (int k = 1; k < 4; k++) seg[k] = seg[k - 1] + (uint64_t)cnt[k - 1];
+    uint64_t run = 0;
+    for (uint32_t f = 0; f <= nf; f++) {
+        for (int k = 0; k < 4; k++) before[4 * f + k] = f == 0 ? 0 : before[4 * (f - 1) + k] + fk[4 * (f - 1) + k];
+        if (f == nf) break;
+        crit_off[f] = run;
+        for (int k = 0; k < 4; k++) {
+            start[4 * f + k] = run;
+            run += fk[4 * f + k];
+        }
+    }
+    crit_off[nf] = run;
+    uint64_t* d_tab = buf<uint64_t>(ctx, "bx.tab", 4 + 4 * (nf + 1) + 4 * nf);
+    check(ctx, hipMemcpyAsync(d_tab, seg.data(), 8 * 4, hipMemcpyHostToDevice, s), "table copy");
+    check(ctx, hipMemcpyAsync(d_tab + 4, before.data(), 8 * 4 * (nf + 1), hipMemcpyHostToDevice, s), "table copy");
+    check(ctx, hipMemcpyAsync(d_tab + 4 + 4 * (nf + 1), start.data(), 8 * 4 * nf, hipMemcpyHostToDevice, s),
+          "table copy");
+    ms_crit fc;
+    fc.id = buf<uint32_t>(ctx, "bx_crit_id", ncrit);
+    fc.index = buf<uint8_t>(ctx, "bx_crit_index", ncrit);
+    fc.value = buf<float>(ctx, "bx_crit_value", ncrit);
+    fc.vmax = buf<uint32_t>(ctx, "bx_crit_vmax", ncrit);
+    check(ctx, launch_crit_split(cr.id, cr.index, cr.value, cr.vmax, (uint64_t)ncrit, geo, d_tab, d_tab + 4,
+                                 d_tab + 4 + 4 * (nf + 1), fc.id, fc.index, fc.value, fc.vmax, s),
+          "critical split");
+    for (uint32_t f = 0; f < nf; f++) {
+        ms_result& o = outs[f];
+        memset(&o, 0, sizeof(o));
+        o.grad = grad + voff[f];
+        o.crit.id = fc.id + crit_off[f];
+        o.crit.index = fc.index + crit_off[f];
+        o.crit.value = fc.value + crit_off[f];
+        o.crit.vmax = fc.vmax + crit_off[f];
+        o.crit.capacity = (int64_t)(crit_off[f + 1] - crit_off[f]);
+        for (int k = 0; k < 4; k++) o.count[k] = (int64_t)fk[4 * f + k];
+        o.arcs.stats = arcs.stats;
+    }
+    // block-diagonal matrices -> per-field matrices
+    struct M {
+        ms_csr ms_arcs::*m;
+        int ri, ci;
+        const char* name;
+    };
+    const M mats[6] = {{&ms_arcs::m10, 1, 0, "bx.m10"},  {&ms_arcs::m10t, 0, 1, "bx.m10t"},
+                       {&ms_arcs::m21, 2, 1, "bx.m21"},  {&ms_arcs::m21t, 1, 2, "bx.m21t"},
+                       {&ms_arcs::m32, 3, 2, "bx.m32"},  {&ms_arcs::m32t, 2, 3, "bx.m32t"}};
+    uint64_t* d_off = buf<uint64_t>(ctx, "bx.off", 3 * (nf + 1));
+    std::vector<uint64_t> roff(nf + 1), coff(nf + 1);
+    for (const M& m : mats) {
+        const ms_csr& G = arcs.*(m.m);
+        for (uint32_t f = 0; f <= nf; f++) {
+            roff[f] = before[4 * f + m.ri];
+            coff[f] = before[4 * f + m.ci];
+        }
+        check(ctx, hipMemcpyAsync(d_off, roff.data(), 8 * (nf + 1), hipMemcpyHostToDevice, s), "table copy");
+        check(ctx, hipMemcpyAsync(d_off + (nf + 1), coff.data(), 8 * (nf + 1), hipMemcpyHostToDevice, s),
+              "table copy");
+        check(ctx, launch_gather_u64((const uint64_t*)G.rowptr, d_off, nf + 1, d_off + 2 * (nf + 1), s), "gather");
+        std::string nm = m.name;
+        uint64_t* orp = buf<uint64_t>(ctx, (nm + ".rowptr").c_str(), (uint64_t)G.nrows + nf);
+        uint32_t* ocol = buf<uint32_t>(ctx, (nm + ".col").c_str(), (uint64_t)G.nnz);
+        check(ctx, launch_csr_split((const uint64_t*)G.rowptr, (uint64_t)G.nrows, G.col, (uint64_t)G.nnz, d_off,
+                                    d_off + (nf + 1), d_off + 2 * (nf + 1), nf, orp, ocol, s),
+              "csr split");
+        const uint64_t* h = readback(ctx, d_off + 2 * (nf + 1), nf + 1);
+        for (uint32_t f = 0; f < nf; f++) {
+            ms_csr& o = outs[f].arcs.*(m.m);
+            o.nrows = (int64_t)(roff[f + 1] - roff[f]);
+            o.ncols = (int64_t)(coff[f + 1] - coff[f]);
+            o.nnz = (int64_t)(h[f + 1] - h[f]);
+            o.rowptr = (int64_t*)(orp + roff[f] + f);
+            o.col = ocol + h[f];
+            o.val = G.val + h[f];
+        }
+        if (m.m == &ms_arcs::m21t) {
+            unsigned long long* d_sat = (unsigned long long*)buf<uint64_t>(ctx, "bx.sat", nf);
+            check(ctx, hipMemsetAsync(d_sat, 0, 8 * nf, s), "memset");
+            check(ctx, launch_sat_per_field(G.val, (uint64_t)G.nnz, d_off + 2 * (nf + 1), nf, d_sat, s), "sat");
+            const uint64_t* hs = readback(ctx, (const uint64_t*)d_sat, nf);
+            for (uint32_t f = 0; f < nf; f++) outs[f].arcs.n_saturated = (int64_t)hs[f];
+        }
+    }
+    mark(ctx, 6);
+    accumulate_timing(ctx);
     API_END
 }
 

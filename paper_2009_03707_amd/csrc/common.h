@@ -61,6 +61,30 @@ struct Grid {
     }
 };
 
+// A batch of fields laid end to end in one vertex index space: field f owns
+// global vertex ids [voff[f], voff[f+1]) and cell ids 8 * that range.  Cells
+// of different fields are never adjacent, so every traversal stays inside
+// the field it starts in.  One field is the special case nf == 1.
+struct Geo {
+    const Grid* grids;     // device, nf entries
+    const uint32_t* voff;  // device, nf + 1 entries
+    uint32_t nf;
+    uint32_t nv;           // total vertices
+    Grid g0;               // the grid of field 0 (used directly when nf == 1)
+    __device__ inline uint32_t field_of(uint32_t v) const {
+        if (nf == 1) return 0;
+        uint32_t lo = 0, hi = nf;  // last f with voff[f] <= v
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (voff[mid] <= v) lo = mid;
+            else hi = mid;
+        }
+        return lo;
+    }
+    __device__ inline Grid grid(uint32_t f) const { return nf == 1 ? g0 : grids[f]; }
+    __device__ inline uint32_t base(uint32_t f) const { return nf == 1 ? 0u : voff[f]; }
+};
+
 __device__ inline uint32_t nib_of(uint32_t word, uint32_t k) { return (word >> (4u * k)) & 15u; }
 
 // Cell one refined step from (w, k) along `axis` with sign `s` (+1 / -1).

@@ -8,13 +8,13 @@
 
 namespace msc {
 
-hipError_t launch_pj_init(const uint32_t* grad, const Grid& g, uint32_t* Pv, uint32_t* Pc, int* err, hipStream_t s);
-hipError_t launch_label(const uint32_t* crit, const int64_t cnt[4], const uint32_t* grad, const Grid& g, uint32_t* Pv,
+hipError_t launch_pj_init(const uint32_t* grad, const Geo& g, uint32_t* Pv, uint32_t* Pc, int* err, hipStream_t s);
+hipError_t launch_label(const uint32_t* crit, const int64_t cnt[4], const uint32_t* grad, const Geo& g, uint32_t* Pv,
                         uint32_t* Pc, uint32_t* label, int* err, hipStream_t s);
 hipError_t launch_pj_round(uint32_t* P, uint32_t n, int* changed, hipStream_t s);
-hipError_t launch_m10(bool fill, const uint32_t* s1, uint64_t S1, const Grid& g, const uint32_t* Pv, uint32_t* cnt,
+hipError_t launch_m10(bool fill, const uint32_t* s1, uint64_t S1, const Geo& g, const uint32_t* Pv, uint32_t* cnt,
                       const uint64_t* rowptr, uint32_t* col, uint64_t* val, int* err, hipStream_t s);
-hipError_t launch_m32t(bool fill, const uint32_t* s2, uint64_t S2, const Grid& g, const uint32_t* Pc, uint32_t* cnt,
+hipError_t launch_m32t(bool fill, const uint32_t* s2, uint64_t S2, const Geo& g, const uint32_t* Pc, uint32_t* cnt,
                        const uint64_t* rowptr, uint32_t* col, uint64_t* val, int* err, hipStream_t s);
 int bit_width(uint64_t v);
 hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, uint32_t* rows, hipStream_t s);
@@ -33,11 +33,11 @@ hipError_t launch_esc_expand(const uint32_t* xrow, const uint32_t* xcol, const u
                              const uint64_t* poff, const uint64_t* yrowptr, const uint32_t* ycol, const uint64_t* yval,
                              uint32_t* prow, uint32_t* pcol, uint64_t* pval, hipStream_t s);
 hipError_t launch_count_sat(const uint64_t* v, uint64_t n, unsigned long long* out, hipStream_t s);
-hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Grid& g,
+hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Geo& g,
                              uint32_t* vis, uint32_t* next, unsigned long long* counts, uint32_t* label,
                              uint32_t* jlist, hipStream_t s);
 hipError_t launch_minor_trace(const uint32_t* s1, uint64_t S1, const uint32_t* jlist, uint64_t J, const uint32_t* grad,
-                              const Grid& g, const uint32_t* label, uint64_t max_steps, uint64_t S2, uint8_t* out_t,
+                              const Geo& g, const uint32_t* label, uint64_t max_steps, uint64_t S2, uint8_t* out_t,
                               uint32_t* out_id, int* err, hipStream_t s);
 hipError_t launch_minor_rows(bool fill, const uint8_t* out_t, const uint32_t* out_id, uint64_t S1, uint64_t NS,
                              uint32_t* cj, uint32_t* cs, const uint64_t* rpA, uint32_t* colA, uint64_t* valA,
@@ -349,7 +349,7 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
 }
 }  // namespace
 
-void connect_impl(ms_ctx* c, const uint32_t* grad, const Grid& g, const uint32_t* crit, const int64_t cnt[4],
+void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t* crit, const int64_t cnt[4],
                   ms_arcs* out) {
     memset(out, 0, sizeof(*out));
     hipStream_t s = c->stream;

@@ -61,12 +61,13 @@ __global__ void crit_totals(const uint64_t* __restrict__ excl, uint64_t nb, cons
     }
 }
 
-__global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f, const uint32_t* __restrict__ grad,
-                                                   Grid g, const uint64_t* __restrict__ excl,
+__global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f0, const float* const* __restrict__ fptr,
+                                                   const uint32_t* __restrict__ grad, Geo geo,
+                                                   const uint64_t* __restrict__ excl,
                                                    uint32_t* __restrict__ o_id, uint8_t* __restrict__ o_index,
                                                    float* __restrict__ o_value, uint32_t* __restrict__ o_vmax) {
     __shared__ uint64_t sc[CT / WAVE + 1];
-    const uint64_t nv = g.nv;
+    const uint64_t nv = geo.nv;
     const uint64_t nb = gridDim.x;
     uint64_t base = (uint64_t)blockIdx.x * CTILE + (uint64_t)threadIdx.x * CWPT;
     uint32_t w[CWPT];
@@ -93,12 +94,15 @@ __global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f, 
             if (nib < NB_CRIT) continue;
             uint32_t idx = (uint32_t)__builtin_popcount(k);
             uint32_t d = nib - NB_CRIT;
+            uint32_t fld = geo.field_of(v);
+            Grid g = geo.grid(fld);
             uint32_t vm = v + ((d & 1u) ? g.stride[0] : 0u) + ((d & 2u) ? g.stride[1] : 0u) +
                           ((d & 4u) ? g.stride[2] : 0u);
+            const float* f = fptr ? fptr[fld] : f0;
             uint64_t p = pos[idx]++;
             o_id[p] = 8u * v + k;
             o_index[p] = (uint8_t)idx;
-            o_value[p] = f[vm];
+            o_value[p] = f[vm - geo.base(fld)];
             o_vmax[p] = vm;
         }
     }
@@ -113,7 +117,7 @@ size_t crit_tmp_elems(uint64_t nv) {
 
 // Pass 1 + scan.  tmp layout: [4*nb counts][4*nb exclusive offsets][8 totals][scan tmp].
 // d_totals (8 uint64 inside tmp) receives per-index counts and segment starts.
-hipError_t launch_crit_count(const uint32_t* grad, const Grid& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s) {
+hipError_t launch_crit_count(const uint32_t* grad, const Geo& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s) {
     uint64_t nb = (g.nv + CTILE - 1) / CTILE;
     uint64_t* blk = tmp;
     uint64_t* excl = tmp + 4 * nb;
@@ -131,11 +135,13 @@ hipError_t launch_crit_count(const uint32_t* grad, const Grid& g, uint64_t* tmp,
 
 // Pass 2: the exclusive offsets over [index][block] are global positions in
 // the (index, id)-sorted list because index segments are concatenated.
-hipError_t launch_crit_scatter(const float* f, const uint32_t* grad, const Grid& g, const uint64_t* tmp, uint32_t* id,
-                               uint8_t* index, float* value, uint32_t* vmax, hipStream_t s) {
+hipError_t launch_crit_scatter(const float* f0, const float* const* fptr, const uint32_t* grad, const Geo& g,
+                               const uint64_t* tmp, uint32_t* id, uint8_t* index, float* value, uint32_t* vmax,
+                               hipStream_t s) {
     uint64_t nb = (g.nv + CTILE - 1) / CTILE;
     const uint64_t* excl = tmp + 4 * nb;
-    hipLaunchKernelGGL(crit_scatter, dim3((unsigned)nb), dim3(CT), 0, s, f, grad, g, excl, id, index, value, vmax);
+    hipLaunchKernelGGL(crit_scatter, dim3((unsigned)nb), dim3(CT), 0, s, f0, fptr, grad, g, excl, id, index, value,
+                       vmax);
     return hipGetLastError();
 }
 

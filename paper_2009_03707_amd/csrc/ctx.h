@@ -13,6 +13,8 @@
 #include "../../include/msc.h"
 #include "common.h"
 
+constexpr size_t HOST_SCRATCH_WORDS = 8192;  // pinned readback area (uint64 words)
+
 struct ms_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
@@ -98,8 +100,10 @@ inline void fail(ms_ctx* c, ms_status st, const std::string& msg) {
     throw Fail{st};
 }
 
-// Copies `n` uint64 words from device to the pinned scratch and waits.
+// Copies `n` uint64 words (n <= HOST_SCRATCH_WORDS) from device to the
+// pinned scratch and waits.
 inline uint64_t* readback(ms_ctx* c, const uint64_t* d, size_t n) {
+    if (n > HOST_SCRATCH_WORDS) fail(c, MS_ERR_INTERNAL, "readback larger than the pinned scratch");
     check(c, hipMemcpyAsync(c->h_small, d, n * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream), "readback");
     check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     return c->h_small;

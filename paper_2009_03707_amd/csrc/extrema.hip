@@ -19,13 +19,15 @@ namespace {
 
 constexpr int BT = 256;
 
-__global__ __launch_bounds__(BT) void k_pj_init(const uint32_t* __restrict__ grad, Grid g, uint32_t* __restrict__ Pv,
+__global__ __launch_bounds__(BT) void k_pj_init(const uint32_t* __restrict__ grad, Geo geo, uint32_t* __restrict__ Pv,
                                                 uint32_t* __restrict__ Pc, int* __restrict__ err) {
     uint32_t v = blockIdx.x * BT + threadIdx.x;
-    if (v >= g.nv) return;
+    if (v >= geo.nv) return;
+    uint32_t fld = geo.field_of(v);
+    const Grid g = geo.grid(fld);
     uint32_t w = grad[v];
     uint32_t c[3];
-    g.coords(v, c);
+    g.coords(v - geo.base(fld), c);
     uint32_t n0 = w & 15u;
     uint32_t pv = ROOT_FLAG;
     if (n0 >= NB_CRIT) {
@@ -63,7 +65,7 @@ __global__ __launch_bounds__(BT) void k_pj_init(const uint32_t* __restrict__ gra
 // Labels roots with ranks and checks the critical list against the gradient
 // (critical nibble, index of each segment, strictly increasing ids).
 __global__ __launch_bounds__(BT) void k_label(const uint32_t* __restrict__ crit, uint64_t c0, uint64_t c1,
-                                              uint64_t c2, uint64_t c3, const uint32_t* __restrict__ grad, Grid g,
+                                              uint64_t c2, uint64_t c3, const uint32_t* __restrict__ grad, Geo g,
                                               uint32_t* __restrict__ Pv, uint32_t* __restrict__ Pc,
                                               uint32_t* __restrict__ label, int* __restrict__ err) {
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
@@ -107,7 +109,7 @@ __global__ __launch_bounds__(BT) void k_pj_round(uint32_t* __restrict__ P, uint3
 
 // M10 rows: the two vertices of each 1-saddle lead to their minima.
 template <bool FILL>
-__global__ __launch_bounds__(BT) void k_m10(const uint32_t* __restrict__ s1, uint64_t S1, Grid g,
+__global__ __launch_bounds__(BT) void k_m10(const uint32_t* __restrict__ s1, uint64_t S1, Geo geo,
                                             const uint32_t* __restrict__ Pv, uint32_t* __restrict__ cnt,
                                             const uint64_t* __restrict__ rowptr, uint32_t* __restrict__ col,
                                             uint64_t* __restrict__ val, int* __restrict__ err) {
@@ -116,6 +118,7 @@ __global__ __launch_bounds__(BT) void k_m10(const uint32_t* __restrict__ s1, uin
     uint32_t id = s1[r];
     uint32_t w = id >> 3, k = id & 7u;
     uint32_t a = (uint32_t)__builtin_ctz(k);
+    const Grid g = geo.grid(geo.field_of(w));
     uint32_t pa = Pv[w], pb = Pv[w + g.stride[a]];
     if (!(pa & pb & ROOT_FLAG)) {
         atomicOr(err, 4);
@@ -141,7 +144,7 @@ __global__ __launch_bounds__(BT) void k_m10(const uint32_t* __restrict__ s1, uin
 // M32 transposed rows: the cofacet cubes of each 2-saddle lead to maxima
 // (or out of the grid, dropped).
 template <bool FILL>
-__global__ __launch_bounds__(BT) void k_m32t(const uint32_t* __restrict__ s2, uint64_t S2, Grid g,
+__global__ __launch_bounds__(BT) void k_m32t(const uint32_t* __restrict__ s2, uint64_t S2, Geo geo,
                                              const uint32_t* __restrict__ Pc, uint32_t* __restrict__ cnt,
                                              const uint64_t* __restrict__ rowptr, uint32_t* __restrict__ col,
                                              uint64_t* __restrict__ val, int* __restrict__ err) {
@@ -150,8 +153,10 @@ __global__ __launch_bounds__(BT) void k_m32t(const uint32_t* __restrict__ s2, ui
     uint32_t id = s2[r];
     uint32_t w = id >> 3, k = id & 7u;
     uint32_t j = (k == 3u) ? 2u : (k == 5u ? 1u : 0u);  // the even axis of the quad
+    uint32_t fld = geo.field_of(w);
+    const Grid g = geo.grid(fld);
     uint32_t c[3];
-    g.coords(w, c);
+    g.coords(w - geo.base(fld), c);
     uint32_t l[2] = {EXIT_LABEL, EXIT_LABEL};
     if (c[j] + 1 < g.n[j]) l[0] = Pc[w];
     if (c[j] >= 1) l[1] = Pc[w - g.stride[j]];
@@ -187,12 +192,12 @@ __global__ __launch_bounds__(BT) void k_m32t(const uint32_t* __restrict__ s2, ui
 
 }  // namespace
 
-hipError_t launch_pj_init(const uint32_t* grad, const Grid& g, uint32_t* Pv, uint32_t* Pc, int* err, hipStream_t s) {
+hipError_t launch_pj_init(const uint32_t* grad, const Geo& g, uint32_t* Pv, uint32_t* Pc, int* err, hipStream_t s) {
     hipLaunchKernelGGL(k_pj_init, dim3(grid_blocks(g.nv, BT)), dim3(BT), 0, s, grad, g, Pv, Pc, err);
     return hipGetLastError();
 }
 
-hipError_t launch_label(const uint32_t* crit, const int64_t cnt[4], const uint32_t* grad, const Grid& g, uint32_t* Pv,
+hipError_t launch_label(const uint32_t* crit, const int64_t cnt[4], const uint32_t* grad, const Geo& g, uint32_t* Pv,
                         uint32_t* Pc, uint32_t* label, int* err, hipStream_t s) {
     uint64_t total = (uint64_t)(cnt[0] + cnt[1] + cnt[2] + cnt[3]);
     if (total == 0) return hipSuccess;
@@ -206,7 +211,7 @@ hipError_t launch_pj_round(uint32_t* P, uint32_t n, int* changed, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_m10(bool fill, const uint32_t* s1, uint64_t S1, const Grid& g, const uint32_t* Pv, uint32_t* cnt,
+hipError_t launch_m10(bool fill, const uint32_t* s1, uint64_t S1, const Geo& g, const uint32_t* Pv, uint32_t* cnt,
                       const uint64_t* rowptr, uint32_t* col, uint64_t* val, int* err, hipStream_t s) {
     if (S1 == 0) return hipSuccess;
     if (fill)
@@ -218,7 +223,7 @@ hipError_t launch_m10(bool fill, const uint32_t* s1, uint64_t S1, const Grid& g,
     return hipGetLastError();
 }
 
-hipError_t launch_m32t(bool fill, const uint32_t* s2, uint64_t S2, const Grid& g, const uint32_t* Pc, uint32_t* cnt,
+hipError_t launch_m32t(bool fill, const uint32_t* s2, uint64_t S2, const Geo& g, const uint32_t* Pc, uint32_t* cnt,
                        const uint64_t* rowptr, uint32_t* col, uint64_t* val, int* err, hipStream_t s) {
     if (S2 == 0) return hipSuccess;
     if (fill)

@@ -241,15 +241,33 @@ __device__ void lower_star(const uint32_t* fk, int fidx, const Star& st, uint32_
     }
 }
 
-__global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restrict__ f, Grid g, uint32_t ntx,
-                                                           uint32_t nty, uint32_t* __restrict__ grad,
-                                                           int* __restrict__ err) {
+// One workgroup per tile; tiles of all fields of a batch are numbered
+// consecutively (tile_off: first tile of each field).
+__global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restrict__ f0,
+                                                           const float* const* __restrict__ fptr, Geo geo,
+                                                           const uint32_t* __restrict__ tile_off,
+                                                           uint32_t* __restrict__ grad_all, int* __restrict__ err) {
     __shared__ uint32_t fk[NF];
     __shared__ uint32_t words[NW];
     __shared__ uint32_t kk[27 * THREADS];
     __shared__ Tables tab;
     const int tid = threadIdx.x;
-    const uint32_t t = blockIdx.x;
+    uint32_t t = blockIdx.x;
+    uint32_t fld = 0;
+    if (geo.nf > 1) {
+        uint32_t lo = 0, hi = geo.nf;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (tile_off[mid] <= t) lo = mid;
+            else hi = mid;
+        }
+        fld = lo;
+        t -= tile_off[fld];
+    }
+    const Grid g = geo.grid(fld);
+    const float* __restrict__ f = fptr ? fptr[fld] : f0;
+    uint32_t* __restrict__ grad = grad_all + geo.base(fld);
+    const uint32_t ntx = (g.n[0] + OX - 1) / OX, nty = (g.n[1] + OY - 1) / OY;
     const uint32_t tx = t % ntx, ty = (t / ntx) % nty, tz = t / (ntx * nty);
     const int x0 = (int)(tx * OX), y0 = (int)(ty * OY), z0 = (int)(tz * OZ);
     const int nx = (int)g.n[0], ny = (int)g.n[1], nz = (int)g.n[2];
@@ -299,10 +317,18 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
 
 }  // namespace
 
-hipError_t launch_gradient(const float* f, const Grid& g, uint32_t* grad, int* err, hipStream_t s) {
-    uint32_t ntx = (g.n[0] + OX - 1) / OX, nty = (g.n[1] + OY - 1) / OY, ntz = (g.n[2] + OZ - 1) / OZ;
-    uint64_t nb = (uint64_t)ntx * nty * ntz;
-    hipLaunchKernelGGL(grad_lowerstar, dim3((unsigned)nb), dim3(THREADS), 0, s, f, g, ntx, nty, grad, err);
+// tiles of one field
+uint32_t gradient_tiles(const Grid& g) {
+    return ((g.n[0] + OX - 1) / OX) * ((g.n[1] + OY - 1) / OY) * ((g.n[2] + OZ - 1) / OZ);
+}
+
+// f0: the field when geo.nf == 1; otherwise fptr / tile_off (device arrays)
+// give each field's data and first tile, and total_tiles the sum.
+hipError_t launch_gradient(const float* f0, const float* const* fptr, const Geo& geo, const uint32_t* tile_off,
+                           uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s) {
+    if (total_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(grad_lowerstar, dim3((unsigned)total_tiles), dim3(THREADS), 0, s, f0, fptr, geo, tile_off, grad,
+                       err);
     return hipGetLastError();
 }
 

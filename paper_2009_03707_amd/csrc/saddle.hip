@@ -54,7 +54,7 @@ __device__ __forceinline__ bool quad_edge_partner(const Grid& g, uint32_t qw, ui
 }
 
 __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ cur, uint64_t ncur, int level0,
-                                                   const uint32_t* __restrict__ grad, Grid g,
+                                                   const uint32_t* __restrict__ grad, Geo geo,
                                                    uint32_t* __restrict__ vis, uint32_t* __restrict__ next,
                                                    unsigned long long* __restrict__ counts,
                                                    uint32_t* __restrict__ label, uint32_t* __restrict__ jlist) {
@@ -67,8 +67,10 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
         e = cur[i];
         uint32_t w = e >> 3, k = e & 7u;
         uint32_t a = (uint32_t)__builtin_ctz(k);
+        uint32_t fld = geo.field_of(w);
+        const Grid g = geo.grid(fld);
         uint32_t c[3];
-        g.coords(w, c);
+        g.coords(w - geo.base(fld), c);
         CellRef v;
         bool hv = paired_quad(g, w, k, nib_of(grad[w], k), c, a, v);
         for (uint32_t b = 0; b < 3; b++) {
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
 // Trace the simple path leaving source `src` through its out-edge `slot`.
 __global__ __launch_bounds__(BT) void k_minor_trace(const uint32_t* __restrict__ s1, uint64_t S1,
                                                     const uint32_t* __restrict__ jlist, uint64_t J,
-                                                    const uint32_t* __restrict__ grad, Grid g,
+                                                    const uint32_t* __restrict__ grad, Geo geo,
                                                     const uint32_t* __restrict__ label, uint64_t max_steps,
                                                     uint64_t S2, uint8_t* __restrict__ out_t,
                                                     uint32_t* __restrict__ out_id, int* __restrict__ err) {
@@ -129,8 +131,12 @@ __global__ __launch_bounds__(BT) void k_minor_trace(const uint32_t* __restrict__
     uint32_t e = si < S1 ? s1[si] : jlist[si - S1];
     uint32_t w = e >> 3, k = e & 7u;
     uint32_t a = (uint32_t)__builtin_ctz(k);
+    // a path never leaves the field it starts in
+    const uint32_t fld = geo.field_of(w);
+    const Grid g = geo.grid(fld);
+    const uint32_t fbase = geo.base(fld);
     uint32_t c[3];
-    g.coords(w, c);
+    g.coords(w - fbase, c);
     CellRef v;
     bool hv = paired_quad(g, w, k, nib_of(grad[w], k), c, a, v);
     uint32_t b0 = a == 0 ? 1u : 0u, b1 = a == 2 ? 1u : 2u;
@@ -162,7 +168,7 @@ __global__ __launch_bounds__(BT) void k_minor_trace(const uint32_t* __restrict__
             // e2 has out-degree <= 1 and is paired with q: find its only out-edge
             uint32_t a2 = (uint32_t)__builtin_ctz(e2.k);
             uint32_t c2[3];
-            g.coords(e2.w, c2);
+            g.coords(e2.w - fbase, c2);
             bool found = false;
             for (uint32_t bb = 0; bb < 3 && !found; bb++) {
                 if (bb == a2) continue;
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(BT) void k_minor_rows(const uint8_t* __restrict__ o
 
 }  // namespace
 
-hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Grid& g,
+hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Geo& g,
                              uint32_t* vis, uint32_t* next, unsigned long long* counts, uint32_t* label,
                              uint32_t* jlist, hipStream_t s) {
     if (ncur == 0) return hipSuccess;
@@ -265,7 +271,7 @@ hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, co
 }
 
 hipError_t launch_minor_trace(const uint32_t* s1, uint64_t S1, const uint32_t* jlist, uint64_t J, const uint32_t* grad,
-                              const Grid& g, const uint32_t* label, uint64_t max_steps, uint64_t S2, uint8_t* out_t,
+                              const Geo& g, const uint32_t* label, uint64_t max_steps, uint64_t S2, uint8_t* out_t,
                               uint32_t* out_id, int* err, hipStream_t s) {
     uint64_t lanes = 4 * (S1 + J);
     if (lanes == 0) return hipSuccess;

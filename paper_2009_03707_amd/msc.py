@@ -21,7 +21,7 @@ MS_OK, MS_ERR_INVALID_ARG, MS_ERR_NONFINITE, MS_ERR_TOO_LARGE, MS_ERR_CAPACITY, 
 
 EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_error", "ms_gradient",
             "ms_critical", "ms_connect", "ms_complex", "ms_ctx_set_timing", "ms_ctx_get_timing",
-            "ms_ctx_set_option"]
+            "ms_ctx_set_option", "ms_complex_batch"]
 
 MS_OPT_PATH_SCHEDULE, MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK = 1, 2, 3
 MS_PATHS_READY, MS_PATHS_POWER = 0, 1
@@ -91,6 +91,7 @@ def lib():
         L.ms_ctx_set_timing.argtypes = [vp, C.c_int]
         L.ms_ctx_get_timing.argtypes = [vp, C.POINTER(Timing)]
         L.ms_ctx_set_option.argtypes = [vp, C.c_int, C.c_int64]
+        L.ms_complex_batch.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(Dims), C.POINTER(Result)]
         for n in EXPORTED:
             getattr(L, n)
         _LIB = L
@@ -207,6 +208,21 @@ class Context:
         self._raise(st, "ms_connect")
         return arcs
 
+    def complex_batch_raw(self, fs):
+        """ms_complex_batch over a list of field tensors; returns one Result
+        per field, pointing at context-owned buffers valid until the next
+        call on this context."""
+        for f in fs:
+            _check_field(f)
+        self._sync_stream()
+        n = len(fs)
+        ptrs = (C.c_void_p * n)(*[f.data_ptr() for f in fs])
+        dims = (Dims * n)(*[_dims(f) for f in fs])
+        res = (Result * n)()
+        st = lib().ms_complex_batch(self._h, n, ptrs, dims, res)
+        self._raise(st, "ms_complex_batch")
+        return list(res)
+
     def complex_raw(self, f: torch.Tensor) -> Result:
         """ms_complex; the returned structure points at context-owned device
         buffers valid until the next call on this context."""
@@ -265,28 +281,46 @@ class Complex:
     stats: dict
 
 
+def _to_complex(r: Result, f: torch.Tensor) -> Complex:
+    dev = f.device
+    n = sum(r.count)
+    nv = f.numel()
+    return Complex(
+        grad=_copy_dev(r.grad, 4 * nv, torch.int32, nv, dev).view(f.shape),
+        crit_id=_copy_dev(r.crit.id, 4 * n, torch.int32, n, dev),
+        crit_index=_copy_dev(r.crit.index, n, torch.uint8, n, dev),
+        crit_value=_copy_dev(r.crit.value, 4 * n, torch.float32, n, dev),
+        crit_vmax=_copy_dev(r.crit.vmax, 4 * n, torch.int32, n, dev),
+        count=list(r.count),
+        m10=csr_to_torch(r.arcs.m10, dev), m10t=csr_to_torch(r.arcs.m10t, dev),
+        m21=csr_to_torch(r.arcs.m21, dev), m21t=csr_to_torch(r.arcs.m21t, dev),
+        m32=csr_to_torch(r.arcs.m32, dev), m32t=csr_to_torch(r.arcs.m32t, dev),
+        n_saturated=int(r.arcs.n_saturated),
+        stats={k: int(getattr(r.arcs.stats, k)) for k, _ in Stats._fields_},
+    )
+
+
 def complex_(f: torch.Tensor, ctx: Context | None = None) -> Complex:
     """Runs the whole hot path and copies the results into torch tensors."""
     own = ctx is None
     ctx = ctx or Context()
     try:
-        r = ctx.complex_raw(f)
-        dev = f.device
-        n = sum(r.count)
-        nv = f.numel()
-        out = Complex(
-            grad=_copy_dev(r.grad, 4 * nv, torch.int32, nv, dev).view(f.shape),
-            crit_id=_copy_dev(r.crit.id, 4 * n, torch.int32, n, dev),
-            crit_index=_copy_dev(r.crit.index, n, torch.uint8, n, dev),
-            crit_value=_copy_dev(r.crit.value, 4 * n, torch.float32, n, dev),
-            crit_vmax=_copy_dev(r.crit.vmax, 4 * n, torch.int32, n, dev),
-            count=list(r.count),
-            m10=csr_to_torch(r.arcs.m10, dev), m10t=csr_to_torch(r.arcs.m10t, dev),
-            m21=csr_to_torch(r.arcs.m21, dev), m21t=csr_to_torch(r.arcs.m21t, dev),
-            m32=csr_to_torch(r.arcs.m32, dev), m32t=csr_to_torch(r.arcs.m32t, dev),
-            n_saturated=int(r.arcs.n_saturated),
-            stats={k: int(getattr(r.arcs.stats, k)) for k, _ in Stats._fields_},
-        )
+        out = _to_complex(ctx.complex_raw(f), f)
+        torch.cuda.current_stream().synchronize()
+        return out
+    finally:
+        if own:
+            ctx.close()
+
+
+def complex_batch(fs, ctx: Context | None = None):
+    """Runs ms_complex_batch (one launch per phase for all fields) and copies
+    each field's result into torch tensors."""
+    own = ctx is None
+    ctx = ctx or Context()
+    try:
+        rs = ctx.complex_batch_raw(fs)
+        out = [_to_complex(r, f) for r, f in zip(rs, fs)]
         torch.cuda.current_stream().synchronize()
         return out
     finally:

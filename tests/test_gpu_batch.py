@@ -1,0 +1,96 @@
+"""Batched launch: many fields of uneven, non-cubic dims in one launch per
+phase.  Each field's result must be byte-identical to the same field run
+alone (and equal the oracle), under both path-counting schedules."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2009_03707_amd import fields
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+NAMES = ("m10", "m10t", "m21", "m21t", "m32", "m32t")
+
+
+@pytest.fixture(scope="module", params=["ready", "power"])
+def ctx(request):
+    from paper_2009_03707_amd import msc
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = msc.Context()
+    c.set_path_schedule(msc.MS_PATHS_READY if request.param == "ready" else msc.MS_PATHS_POWER)
+    yield c
+    c.close()
+
+
+def _same(a, b):
+    from gpu_util import csr_np, u32
+    np.testing.assert_array_equal(u32(a.grad), u32(b.grad))
+    assert a.count == b.count
+    for x, y in ((a.crit_id, b.crit_id), (a.crit_vmax, b.crit_vmax)):
+        np.testing.assert_array_equal(u32(x), u32(y))
+    np.testing.assert_array_equal(a.crit_index.cpu().numpy(), b.crit_index.cpu().numpy())
+    np.testing.assert_array_equal(a.crit_value.cpu().numpy().view(np.uint32), b.crit_value.cpu().numpy().view(np.uint32))
+    for nm in NAMES:
+        ma, mb = getattr(a, nm), getattr(b, nm)
+        assert (ma.nrows, ma.ncols) == (mb.nrows, mb.ncols), nm
+        for x, y in zip(csr_np(ma), csr_np(mb)):
+            np.testing.assert_array_equal(x, y, err_msg=nm)
+    assert a.n_saturated == b.n_saturated
+
+
+def _batch_fields(seed, n):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        dims = tuple(int(v) for v in rng.integers(1, 22, size=3))
+        kind = i % 3
+        if kind == 0:
+            out.append(fields.random_field(dims, seed=seed + i, levels=int(rng.choice([0, 3]))))
+        elif kind == 1:
+            out.append(fields.grf_field(tuple(max(d, 2) for d in dims), seed=seed + i))
+        else:
+            out.append(fields.blob_field(dims, nblobs=3, seed=seed + i))
+    return out
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_batch_equals_alone_and_oracle(ctx, seed):
+    from gpu_util import to_dev, u32, csr_np
+    from paper_2009_03707_amd import msc
+    fs = _batch_fields(100 * seed, 13)
+    fs.insert(3, np.zeros((1, 1, 1), np.float32))
+    fs.append(fields.sine_field(32))
+    devs = [to_dev(f) for f in fs]
+    batch = msc.complex_batch(devs, ctx)
+    for f, fd, b in zip(fs, devs, batch):
+        alone = msc.complex_(fd, ctx)
+        _same(b, alone)
+        ref = O.complex_(f)
+        np.testing.assert_array_equal(u32(b.grad).reshape(f.shape), ref.grad)
+        assert b.count == ref.crit.count.tolist()
+        rp, col, val = ref.p.csr()
+        g = csr_np(b.m21t)
+        np.testing.assert_array_equal(g[0], rp)
+        np.testing.assert_array_equal(g[1], col)
+        np.testing.assert_array_equal(g[2], val)
+
+
+def test_batch_of_one_equals_complex(ctx):
+    from gpu_util import to_dev
+    from paper_2009_03707_amd import msc
+    f = fields.blob_field((40, 33, 27), nblobs=3, seed=9)
+    fd = to_dev(f)
+    _same(msc.complex_batch([fd], ctx)[0], msc.complex_(fd, ctx))
+
+
+def test_batch_rejects_nonfinite(ctx):
+    from gpu_util import to_dev
+    from paper_2009_03707_amd import msc
+    a = fields.random_field((6, 5, 4), seed=1)
+    b = fields.random_field((7, 3, 2), seed=2)
+    b[1, 1, 1] = np.inf
+    with pytest.raises(msc.MscError) as e:
+        ctx.complex_batch_raw([to_dev(a), to_dev(b)])
+    assert e.value.status == msc.MS_ERR_NONFINITE

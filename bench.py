@@ -67,6 +67,47 @@ def cpu_baseline(f, side):
                       f"{dt:.1f} s on one core of {cpu_model()} (host has {os.cpu_count()} logical CPUs)"}
 
 
+def batch_bench(args, torch, msc):
+    """The same kernels on the uneven 64-field batch: one field per call in
+    sequence (plain) versus one ms_complex_batch call (batched)."""
+    from paper_2009_03707_amd import fields
+    specs = fields.batch_specs(args.batch)
+    log(f"generating the {args.batch}-field batch")
+    hs = fields.make_batch(specs)
+    fs = [torch.from_numpy(h).cuda() for h in hs]
+    del hs
+    nvox = sum(int(f.numel()) for f in fs)
+    ctx = msc.Context()
+    tuned = None
+    if not args.no_autotune:
+        from paper_2009_03707_amd import autotune
+        tuned = autotune.tune(ctx, fs, log=log)
+    for f in fs:  # warm every per-field shape
+        ctx.complex_raw(f)
+    ctx.complex_batch_raw(fs)
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 3))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for f in fs:
+            ctx.complex_raw(f)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) / reps * 1e3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.complex_batch_raw(fs)
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) / reps * 1e3
+    log(f"batch of {len(fs)}: plain {plain_ms:.1f} ms, batched {batch_ms:.1f} ms")
+    ctx.close()
+    return {"workload": f"batch{len(fs)}: {len(fs)} float32 fields, sides U{{64..320}} per axis (seeds 1000+i), "
+                        "even i k^-3 GRF, odd i blobs (2000 scaled by volume) + N(0,0.01)",
+            "fields": len(fs), "voxels": nvox, "reps": reps,
+            "plain_ms": round(plain_ms, 2), "batched_ms": round(batch_ms, 2),
+            "plain_mvox_s": round(nvox / plain_ms / 1e3, 2), "batched_mvox_s": round(nvox / batch_ms / 1e3, 2),
+            "speedup": round(plain_ms / batch_ms, 3), "launch_params": tuned}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +115,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="blobs512")
     ap.add_argument("--cpu-sample", type=int, default=160, help="side of the oracle crop (0 = skip)")
+    ap.add_argument("--batch", type=int, default=64, help="fields in the batched comparison (0 = skip)")
+    ap.add_argument("--no-autotune", action="store_true", help="use the default launch parameters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the hot path is measured on a single MI355X "
@@ -88,6 +131,10 @@ def main():
     n = int(f.size)
     fd = torch.from_numpy(f).cuda()
     ctx = msc.Context()
+    tuned = None
+    if not args.no_autotune:
+        from paper_2009_03707_amd import autotune
+        tuned = autotune.tune(ctx, [fd], log=log)
     for i in range(args.warmup):
         r = ctx.complex_raw(fd)
         log(f"warmup {i + 1}/{args.warmup} done")
@@ -130,13 +177,17 @@ def main():
                      "traffic": None, "bytes_per_launch": grad_bytes, "avg_launch_ms": round(grad_ms, 4)},
         "stages_ms": stages,
         "stats": stats,
+        "launch_params": tuned,
     }
+    ctx.close()
     del fd
+    torch.cuda.empty_cache()
+    if args.batch > 0:
+        out["batched"] = batch_bench(args, torch, msc)
     if args.cpu_sample > 0:
         log(f"timing the oracle on a {args.cpu_sample}^3 crop")
         out["cpu_baseline"] = cpu_baseline(f, args.cpu_sample)
     print(json.dumps(out))
-    ctx.close()
 
 
 if __name__ == "__main__":

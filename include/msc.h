@@ -87,17 +87,23 @@ void ms_ctx_destroy(ms_ctx* ctx);
 ms_status ms_ctx_set_stream(ms_ctx* ctx, void* stream);
 /* Text describing the last non-OK status returned on this context. */
 const char* ms_last_error(const ms_ctx* ctx);
+/* Frees the context's workspace (it is reallocated on demand by the next
+ * call); invalidates every context-owned output.  Synchronises the stream. */
+ms_status ms_ctx_release(ms_ctx* ctx);
 
 /* Context options (ms_ctx_set_option). */
 enum {
     MS_OPT_PATH_SCHEDULE = 1, /* how A* = sum_k A B^k is evaluated (Section 3.3) */
     /* Tuning of the ready schedule's column merges; results never depend on
-     * them.  A column with at most MERGE_LIGHT inputs (0..32, default 32)
+     * them.  A column with at most MERGE_LIGHT inputs (0..256, default 32)
      * and at most 8 input lists is merged by one thread; other columns are
      * merged by a workgroup in chunks of MERGE_CHUNK entries (1..4096,
      * default 4096). */
     MS_OPT_MERGE_LIGHT = 2,
-    MS_OPT_MERGE_CHUNK = 3
+    MS_OPT_MERGE_CHUNK = 3,
+    /* Gradient workgroup tile in vertices: 0 = 16x8x4 (default), 1 = 32x4x4,
+     * 2 = 8x8x8, 3 = 16x16x2.  Results never depend on it. */
+    MS_OPT_GRADIENT_TILE = 4
 };
 enum {
     /* Default.  A* is the solution of A* = A + A* B; its columns are formed by

@@ -9,9 +9,9 @@
 #include "prims.h"
 
 namespace msc {
-uint32_t gradient_tiles(const Grid& g);
-hipError_t launch_gradient(const float* f0, const float* const* fptr, const Geo& geo, const uint32_t* tile_off,
-                           uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s);
+uint32_t gradient_tiles(const Grid& g, int shape);
+hipError_t launch_gradient(int shape, const float* f0, const float* const* fptr, const Geo& geo,
+                           const uint32_t* tile_off, uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s);
 size_t crit_tmp_elems(uint64_t nv);
 hipError_t launch_crit_count(const uint32_t* grad, const Geo& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s);
 hipError_t launch_crit_scatter(const float* f0, const float* const* fptr, const uint32_t* grad, const Geo& g,
@@ -54,7 +54,8 @@ Grid check_dims(ms_ctx* c, ms_dims d) {
 // gradient + non-finite flag (flag left on the device at *d_err)
 void gradient_impl(ms_ctx* c, const float* f, const Grid& g, uint32_t* grad, int* d_err) {
     check(c, hipMemsetAsync(d_err, 0, sizeof(int), c->stream), "clear error flag");
-    check(c, launch_gradient(f, nullptr, single(g), nullptr, gradient_tiles(g), grad, d_err, c->stream),
+    check(c, launch_gradient(c->grad_tile, f, nullptr, single(g), nullptr, gradient_tiles(g, c->grad_tile), grad, d_err,
+                             c->stream),
           "gradient kernel launch");
 }
 
@@ -148,6 +149,15 @@ void ms_ctx_destroy(ms_ctx* ctx) {
     delete ctx;
 }
 
+ms_status ms_ctx_release(ms_ctx* ctx) {
+    if (!ctx) return MS_ERR_INVALID_ARG;
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& kv : ctx->bufs)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    ctx->bufs.clear();
+    return MS_OK;
+}
+
 ms_status ms_ctx_set_stream(ms_ctx* ctx, void* stream) {
     if (!ctx) return MS_ERR_INVALID_ARG;
     ctx->stream = (hipStream_t)stream;
@@ -162,12 +172,16 @@ ms_status ms_ctx_set_option(ms_ctx* ctx, int option, int64_t value) {
         ctx->path_schedule = (int)value;
         return MS_OK;
     }
-    if (option == MS_OPT_MERGE_LIGHT && value >= 0 && value <= 32) {
+    if (option == MS_OPT_MERGE_LIGHT && value >= 0 && value <= 256) {
         ctx->merge_light = (uint32_t)value;
         return MS_OK;
     }
     if (option == MS_OPT_MERGE_CHUNK && value >= 1 && value <= 4096) {
         ctx->merge_chunk = (uint32_t)value;
+        return MS_OK;
+    }
+    if (option == MS_OPT_GRADIENT_TILE && value >= 0 && value <= 3) {
+        ctx->grad_tile = (int)value;
         return MS_OK;
     }
     ctx->err = "unknown option or value";
@@ -269,7 +283,8 @@ ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out
     int* d_err = buf<int>(ctx, "err_flag", 4);
     check(ctx, hipMemsetAsync(d_err, 0, sizeof(int), ctx->stream), "clear error flag");
     mark(ctx, 0);
-    check(ctx, launch_gradient(d_f, nullptr, single(g), nullptr, gradient_tiles(g), grad, d_err, ctx->stream),
+    check(ctx, launch_gradient(ctx->grad_tile, d_f, nullptr, single(g), nullptr, gradient_tiles(g, ctx->grad_tile), grad,
+                               d_err, ctx->stream),
           "gradient kernel launch");
     mark(ctx, 1);
     int64_t cnt[4];
@@ -313,7 +328,7 @@ ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f
         voff[f] = (uint32_t)total;
         toff[f] = (uint32_t)tiles;
         total += grids[f].nv;
-        tiles += gradient_tiles(grids[f]);
+        tiles += gradient_tiles(grids[f], ctx->grad_tile);
         if (total > ((uint64_t)1 << 29)) fail(ctx, MS_ERR_TOO_LARGE, "the batch has more than 2^29 vertices");
     }
     voff[nf] = (uint32_t)total;
@@ -338,7 +353,8 @@ ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f
     int* d_err = buf<int>(ctx, "err_flag", 4);
     check(ctx, hipMemsetAsync(d_err, 0, sizeof(int), s), "clear error flag");
     mark(ctx, 0);
-    check(ctx, launch_gradient(d_f[0], d_fptr, geo, d_toff, tiles, grad, d_err, s), "gradient kernel launch");
+    check(ctx, launch_gradient(ctx->grad_tile, d_f[0], d_fptr, geo, d_toff, tiles, grad, d_err, s),
+          "gradient kernel launch");
     mark(ctx, 1);
     int64_t cnt[4];
     ms_status st = MS_OK;

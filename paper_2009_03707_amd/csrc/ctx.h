@@ -33,6 +33,7 @@ struct ms_ctx {
     int path_schedule = MS_PATHS_READY;
     uint32_t merge_light = 32;   // see MS_OPT_MERGE_LIGHT
     uint32_t merge_chunk = 4096; // see MS_OPT_MERGE_CHUNK
+    int grad_tile = 0;           // see MS_OPT_GRADIENT_TILE
 };
 
 namespace msc {

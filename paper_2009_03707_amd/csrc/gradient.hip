@@ -19,12 +19,17 @@
 namespace msc {
 namespace {
 
-constexpr int OX = 16, OY = 8, OZ = 4;           // output words per block
-constexpr int FX = OX + 3, FY = OY + 3, FZ = OZ + 3;  // staged field tile
-constexpr int NF = FX * FY * FZ;
-constexpr int NW = OX * OY * OZ;
-constexpr int PX = OX + 1, PY = OY + 1, PZ = OZ + 1;  // lower stars computed
-constexpr int NPLS = PX * PY * PZ;
+// Tile shapes (output words per workgroup), selectable at run time; the
+// autotuner picks one per size class.  Results do not depend on the shape.
+template <int X, int Y, int Z>
+struct Tile {
+    static constexpr int OX = X, OY = Y, OZ = Z;            // output words per block
+    static constexpr int FX = X + 3, FY = Y + 3, FZ = Z + 3;  // staged field tile
+    static constexpr int NF = FX * FY * FZ;
+    static constexpr int NW = X * Y * Z;
+    static constexpr int PX = X + 1, PY = Y + 1, PZ = Z + 1;  // lower stars computed
+    static constexpr int NPLS = PX * PY * PZ;
+};
 constexpr int THREADS = 256;
 constexpr uint32_t KEY_OUT = 0xFFFFFFFFu;  // vertex outside the grid
 constexpr uint32_t CENTER = 13;
@@ -85,7 +90,9 @@ __device__ __forceinline__ uint32_t float_key(uint32_t u) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+template <class T>
 struct Star {
+    static constexpr int OX = T::OX, OY = T::OY, OZ = T::OZ;
     int lx, ly, lz;          // position in the block (0..OX etc.)
     uint32_t* words;         // LDS word tile
     const Tables* tab;
@@ -147,7 +154,9 @@ struct Unroll<0> {
     __device__ __forceinline__ static void run(F&&) {}
 };
 
-__device__ void lower_star(const uint32_t* fk, int fidx, const Star& st, uint32_t* kk, int tid) {
+template <class T>
+__device__ void lower_star(const uint32_t* fk, int fidx, const Star<T>& st, uint32_t* kk, int tid) {
+    constexpr int FX = T::FX, FY = T::FY;
     uint32_t K[27];
     Unroll<27>::run([&](auto jc) {
         constexpr int j = decltype(jc)::value;
@@ -243,10 +252,13 @@ __device__ void lower_star(const uint32_t* fk, int fidx, const Star& st, uint32_
 
 // One workgroup per tile; tiles of all fields of a batch are numbered
 // consecutively (tile_off: first tile of each field).
+template <class T>
 __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restrict__ f0,
                                                            const float* const* __restrict__ fptr, Geo geo,
                                                            const uint32_t* __restrict__ tile_off,
                                                            uint32_t* __restrict__ grad_all, int* __restrict__ err) {
+    constexpr int OX = T::OX, OY = T::OY, OZ = T::OZ, FX = T::FX, FY = T::FY, NF = T::NF, NW = T::NW;
+    constexpr int PX = T::PX, PY = T::PY, NPLS = T::NPLS;
     __shared__ uint32_t fk[NF];
     __shared__ uint32_t words[NW];
     __shared__ uint32_t kk[27 * THREADS];
@@ -297,7 +309,7 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
         int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
         int x = x0 + lx, y = y0 + ly, z = z0 + lz;
         if (x >= nx || y >= ny || z >= nz) continue;
-        Star st{lx, ly, lz, words, &tab};
+        Star<T> st{lx, ly, lz, words, &tab};
         int fidx = (lx + 1) + FX * ((ly + 1) + FY * (lz + 1));
         lower_star(fk, fidx, st, kk, tid);
     }
@@ -315,20 +327,40 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
     }
 }
 
-}  // namespace
+using T0 = Tile<16, 8, 4>;
+using T1 = Tile<32, 4, 4>;
+using T2 = Tile<8, 8, 8>;
+using T3 = Tile<16, 16, 2>;
 
-// tiles of one field
-uint32_t gradient_tiles(const Grid& g) {
-    return ((g.n[0] + OX - 1) / OX) * ((g.n[1] + OY - 1) / OY) * ((g.n[2] + OZ - 1) / OZ);
+template <class T>
+uint32_t tiles_of(const Grid& g) {
+    return ((g.n[0] + T::OX - 1) / T::OX) * ((g.n[1] + T::OY - 1) / T::OY) * ((g.n[2] + T::OZ - 1) / T::OZ);
 }
 
-// f0: the field when geo.nf == 1; otherwise fptr / tile_off (device arrays)
+}  // namespace
+
+// tiles of one field for tile shape `shape` (0..3)
+uint32_t gradient_tiles(const Grid& g, int shape) {
+    switch (shape) {
+        case 1: return tiles_of<T1>(g);
+        case 2: return tiles_of<T2>(g);
+        case 3: return tiles_of<T3>(g);
+        default: return tiles_of<T0>(g);
+    }
+}
+
+// f0: the field when fptr is null; otherwise fptr / tile_off (device arrays)
 // give each field's data and first tile, and total_tiles the sum.
-hipError_t launch_gradient(const float* f0, const float* const* fptr, const Geo& geo, const uint32_t* tile_off,
-                           uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s) {
+hipError_t launch_gradient(int shape, const float* f0, const float* const* fptr, const Geo& geo,
+                           const uint32_t* tile_off, uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(grad_lowerstar, dim3((unsigned)total_tiles), dim3(THREADS), 0, s, f0, fptr, geo, tile_off, grad,
-                       err);
+    dim3 gd((unsigned)total_tiles), bd(THREADS);
+    switch (shape) {
+        case 1: hipLaunchKernelGGL(grad_lowerstar<T1>, gd, bd, 0, s, f0, fptr, geo, tile_off, grad, err); break;
+        case 2: hipLaunchKernelGGL(grad_lowerstar<T2>, gd, bd, 0, s, f0, fptr, geo, tile_off, grad, err); break;
+        case 3: hipLaunchKernelGGL(grad_lowerstar<T3>, gd, bd, 0, s, f0, fptr, geo, tile_off, grad, err); break;
+        default: hipLaunchKernelGGL(grad_lowerstar<T0>, gd, bd, 0, s, f0, fptr, geo, tile_off, grad, err); break;
+    }
     return hipGetLastError();
 }
 

@@ -137,6 +137,17 @@ def make_batch_field(item: BatchItem) -> np.ndarray:
     return blob_field(item.dims, nblobs=nb, seed=item.seed)
 
 
+def make_batch(specs, workers: int = 0):
+    """All fields of a batch, generated in a process pool (order kept)."""
+    import concurrent.futures as cf
+    import os
+    workers = workers or min(16, os.cpu_count() or 1)
+    if workers <= 1:
+        return [make_batch_field(s) for s in specs]
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(make_batch_field, specs))
+
+
 def advected_step(base: np.ndarray, t: int) -> np.ndarray:
     """Timestep t of the advected series: the periodic base field shifted by
     t voxels along x (constant velocity of one voxel per step)."""

@@ -21,9 +21,9 @@ MS_OK, MS_ERR_INVALID_ARG, MS_ERR_NONFINITE, MS_ERR_TOO_LARGE, MS_ERR_CAPACITY, 
 
 EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_error", "ms_gradient",
             "ms_critical", "ms_connect", "ms_complex", "ms_ctx_set_timing", "ms_ctx_get_timing",
-            "ms_ctx_set_option", "ms_complex_batch"]
+            "ms_ctx_set_option", "ms_complex_batch", "ms_ctx_release"]
 
-MS_OPT_PATH_SCHEDULE, MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK = 1, 2, 3
+MS_OPT_PATH_SCHEDULE, MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK, MS_OPT_GRADIENT_TILE = 1, 2, 3, 4
 MS_PATHS_READY, MS_PATHS_POWER = 0, 1
 
 
@@ -92,6 +92,7 @@ def lib():
         L.ms_ctx_get_timing.argtypes = [vp, C.POINTER(Timing)]
         L.ms_ctx_set_option.argtypes = [vp, C.c_int, C.c_int64]
         L.ms_complex_batch.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(Dims), C.POINTER(Result)]
+        L.ms_ctx_release.argtypes = [vp]
         for n in EXPORTED:
             getattr(L, n)
         _LIB = L
@@ -158,6 +159,10 @@ class Context:
     def set_path_schedule(self, schedule: int):
         """MS_PATHS_READY (default) or MS_PATHS_POWER (the paper's iteration)."""
         self._raise(lib().ms_ctx_set_option(self._h, MS_OPT_PATH_SCHEDULE, int(schedule)), "ms_ctx_set_option")
+
+    def release(self):
+        """Frees the context's workspace (outputs of earlier calls become invalid)."""
+        self._raise(lib().ms_ctx_release(self._h), "ms_ctx_release")
 
     def set_option(self, option: int, value: int):
         self._raise(lib().ms_ctx_set_option(self._h, int(option), int(value)), "ms_ctx_set_option")

@@ -10,12 +10,14 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[0, 1, 2, 3], ids=["tile16x8x4", "tile32x4x4", "tile8x8x8", "tile16x16x2"])
+def ctx(request):
+    """Every gradient workgroup tile shape the autotuner may pick."""
     from paper_2009_03707_amd import msc
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c = msc.Context()
+    c.set_option(msc.MS_OPT_GRADIENT_TILE, request.param)
     yield c
     c.close()
 

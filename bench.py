@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=160, help="side of the oracle crop (0 = skip)")
     ap.add_argument("--batch", type=int, default=64, help="fields in the batched comparison (0 = skip)")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch parameters")
+    ap.add_argument("--serve-steps", type=int, default=200,
+                    help="timesteps of the served advected-field stream (0 = skip)")
+    ap.add_argument("--serve-slots", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the hot path is measured on a single MI355X "
@@ -184,6 +187,11 @@ def main():
     torch.cuda.empty_cache()
     if args.batch > 0:
         out["batched"] = batch_bench(args, torch, msc)
+    if args.serve_steps > 0:
+        from paper_2009_03707_amd import serve
+        out["served"] = serve.serve_benchmark(steps=args.serve_steps, slots=args.serve_slots, options=tuned,
+                                              log=log)
+        torch.cuda.empty_cache()
     if args.cpu_sample > 0:
         log(f"timing the oracle on a {args.cpu_sample}^3 crop")
         out["cpu_baseline"] = cpu_baseline(f, args.cpu_sample)

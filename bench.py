@@ -20,6 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+GRAD_SRC = os.path.join(ROOT, "paper_2009_03707_amd", "csrc", "gradient.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grad_lowerstar_blobs512_traffic.txt")
 
 
 def log(msg):
@@ -65,6 +67,25 @@ def cpu_baseline(f, side):
     return {"value": round(n / dt / 1e6, 4), "unit": "Mvoxels/s", "cores": 1, "kind": "oracle",
             "sample": f"{side}^3 corner crop of the benchmark field ({n} voxels), whole hot path, "
                       f"{dt:.1f} s on one core of {cpu_model()} (host has {os.cpu_count()} logical CPUs)"}
+
+
+def measured_traffic():
+    """HBM bytes per launch of the gradient kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
+    or None when the kernel source has changed since it was measured."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    kv = dict(l.split(":", 1) for l in lines if ":" in l and not l.startswith("#"))
+    src = hashlib.sha256(open(GRAD_SRC, "rb").read()).hexdigest()
+    if kv.get("source_sha256", "").strip() != src:
+        return None
+    try:
+        return int(kv["traffic_bytes_per_launch"].strip())
+    except (KeyError, ValueError):
+        return None
 
 
 def batch_bench(args, torch, msc):
@@ -120,6 +141,9 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=200,
                     help="timesteps of the served advected-field stream (0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain device-to-device copy of this many MiB (a known-size kernel for "
+                         "scaling hardware traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the hot path is measured on a single MI355X "
@@ -128,6 +152,16 @@ def main():
 
     import torch
     from paper_2009_03707_amd import msc
+
+    if args.calibrate_copy > 0:
+        n_el = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n_el, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {4 * n_el} bytes read and written once")
+        del src, dst
 
     log(f"generating {args.workload}")
     f, desc = make_workload(args.workload)
@@ -177,7 +211,8 @@ def main():
                    "critical_counts": counts},
         "roofline": {"kernel": "grad_lowerstar", "bound": "hbm", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": grad_bytes, "avg_launch_ms": round(grad_ms, 4)},
+                     "traffic": measured_traffic(), "bytes_per_launch": grad_bytes,
+                     "avg_launch_ms": round(grad_ms, 4)},
         "stages_ms": stages,
         "stats": stats,
         "launch_params": tuned,

@@ -209,6 +209,9 @@ typedef struct {
     double paths_ms;     /* iterated products, P, M21 and transpose */
     double total_ms;     /* whole ms_complex */
     int64_t calls;
+    int64_t allocations;     /* device allocations the context made while timing was on
+                                (workspace growth; zero in the steady state) */
+    int64_t workspace_bytes; /* device memory the context holds now */
 } ms_timing;
 
 /* Enables (1) or disables (0) timing; enabling resets the accumulators. */

@@ -21,7 +21,7 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
                   ms_arcs* out);
 
 hipError_t launch_gather_u64(const uint64_t* src, const uint64_t* idx, uint64_t n, uint64_t* dst, hipStream_t s);
-hipError_t launch_crit_field_counts(const uint32_t* id, uint64_t n, const Geo& geo, unsigned long long* cnt,
+hipError_t launch_crit_field_counts(const uint32_t* id, const int64_t count[4], const Geo& geo, unsigned long long* cnt,
                                     hipStream_t s);
 hipError_t launch_crit_split(const uint32_t* id, const uint8_t* index, const float* value, const uint32_t* vmax,
                              uint64_t n, const Geo& geo, const uint64_t* seg, const uint64_t* fk_before,
@@ -134,6 +134,10 @@ ms_status ms_ctx_create(ms_ctx** out, void* stream) {
         delete c;
         return MS_ERR_OOM;
     }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+        c->wave_blocks = 4u * (uint32_t)cus;
+    (void)hipGetLastError();
     *out = c;
     return MS_OK;
 }
@@ -155,6 +159,7 @@ ms_status ms_ctx_release(ms_ctx* ctx) {
     for (auto& kv : ctx->bufs)
         if (kv.second.p) (void)hipFree(kv.second.p);
     ctx->bufs.clear();
+    ctx->ws_bytes = 0;
     return MS_OK;
 }
 
@@ -197,6 +202,7 @@ ms_status ms_ctx_set_timing(ms_ctx* ctx, int enable) {
     ctx->timing = enable != 0;
     for (double& a : ctx->acc_ms) a = 0;
     ctx->calls = 0;
+    ctx->allocations = 0;
     API_END
 }
 
@@ -210,6 +216,8 @@ ms_status ms_ctx_get_timing(ms_ctx* ctx, ms_timing* out) {
     out->paths_ms = ctx->acc_ms[5];
     out->total_ms = ctx->acc_ms[6];
     out->calls = ctx->calls;
+    out->allocations = ctx->allocations;
+    out->workspace_bytes = ctx->ws_bytes;
     return MS_OK;
 }
 
@@ -376,8 +384,7 @@ ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f
     connect_impl(ctx, grad, geo, cr.id, cnt, &arcs);
     // ---- split into per-field results ------------------------------------
     unsigned long long* d_fk = (unsigned long long*)buf<uint64_t>(ctx, "bx.fk", 4 * nf);
-    check(ctx, hipMemsetAsync(d_fk, 0, 8 * 4 * nf, s), "memset");
-    check(ctx, launch_crit_field_counts(cr.id, (uint64_t)ncrit, geo, d_fk, s), "field counts");
+    check(ctx, launch_crit_field_counts(cr.id, cnt, geo, d_fk, s), "field counts");
     std::vector<uint64_t> fk(4 * nf);
     {
         const uint64_t* h = readback(ctx, (const uint64_t*)d_fk, 4 * nf);

@@ -24,14 +24,30 @@ __device__ __forceinline__ uint32_t last_le(const uint64_t* off, uint32_t n, uin
     return lo;
 }
 
-// critical cells per (field, index)
-__global__ __launch_bounds__(BT) void k_crit_field_counts(const uint32_t* __restrict__ id, uint64_t n, Geo geo,
+// Critical cells per (field, index), one thread per pair.  The global list
+// is sorted by (index, id) and each field owns the contiguous id range
+// [8 * base(f), 8 * base(f + 1)), so the count is the distance between two
+// lower bounds inside the index segment (no atomics).
+__device__ __forceinline__ uint64_t lower_bound_id(const uint32_t* __restrict__ id, uint64_t lo, uint64_t hi,
+                                                   uint64_t x) {
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if ((uint64_t)id[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(BT) void k_crit_field_counts(const uint32_t* __restrict__ id, Geo geo, uint64_t s0,
+                                                          uint64_t s1, uint64_t s2, uint64_t s3, uint64_t s4,
                                                           unsigned long long* __restrict__ cnt) {
-    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
-    if (i >= n) return;
-    uint32_t c = id[i];
-    uint32_t f = geo.field_of(c >> 3);
-    atomicAdd(&cnt[4 * f + (uint32_t)__builtin_popcount(c & 7u)], 1ull);
+    uint64_t t = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (t >= 4ull * geo.nf) return;
+    const uint32_t f = (uint32_t)(t >> 2), k = (uint32_t)(t & 3u);
+    const uint64_t seg[5] = {s0, s1, s2, s3, s4};
+    const uint64_t lo = 8ull * geo.base(f);
+    const uint64_t hi = f + 1 < geo.nf ? 8ull * geo.base(f + 1) : 8ull * geo.nv;
+    cnt[t] = lower_bound_id(id, seg[k], seg[k + 1], hi) - lower_bound_id(id, seg[k], seg[k + 1], lo);
 }
 
 // Entry i of the global list (index segment k starting at seg[k]) goes to
@@ -115,10 +131,12 @@ hipError_t launch_gather_u64(const uint64_t* src, const uint64_t* idx, uint64_t 
     return hipGetLastError();
 }
 
-hipError_t launch_crit_field_counts(const uint32_t* id, uint64_t n, const Geo& geo, unsigned long long* cnt,
+hipError_t launch_crit_field_counts(const uint32_t* id, const int64_t count[4], const Geo& geo, unsigned long long* cnt,
                                     hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_crit_field_counts, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, id, n, geo, cnt);
+    uint64_t seg[5] = {0, 0, 0, 0, 0};
+    for (int k = 0; k < 4; k++) seg[k + 1] = seg[k] + (uint64_t)count[k];
+    hipLaunchKernelGGL(k_crit_field_counts, dim3(grid_blocks(4ull * geo.nf, BT)), dim3(BT), 0, s, id, geo, seg[0],
+                       seg[1], seg[2], seg[3], seg[4], cnt);
     return hipGetLastError();
 }
 

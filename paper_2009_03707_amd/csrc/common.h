@@ -17,6 +17,13 @@ constexpr uint32_t NB_CRIT = 8u;
 // the rank of the extremum), clear on a plain successor pointer.
 constexpr uint32_t ROOT_FLAG = 0x80000000u;
 constexpr uint32_t EXIT_LABEL = 0xFFFFFFFFu;  // a (2,3) path that leaves the grid
+// Label of a reachable non-saddle edge of the 1-2 DAG: its junction id
+// (< 2^31) if it has several out-edges; SUCC_FLAG | step if it has exactly
+// one, where the step names that out-edge: bits 0-2 = 2 * axis + (sign > 0)
+// of the cofacet quad, bits 3-6 = the quad's gradient nibble (1..6: the quad
+// is paired with an edge, >= 8: the quad is a 2-saddle); NOT_JUNCTION if it
+// has none.
+constexpr uint32_t SUCC_FLAG = 0x80000000u;
 constexpr uint32_t NOT_JUNCTION = 0xFFFFFFFFu;
 
 // floor(n / d) for 0 <= n < 2^30 via one 64-bit multiply and shift

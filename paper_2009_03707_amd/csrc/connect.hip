@@ -282,10 +282,12 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     uint32_t* alen = buf<uint32_t>(c, "pr.alen", J);
     uint64_t* ub = buf<uint64_t>(c, "pr.ub", nmax + 1);
     uint8_t* flag = buf<uint8_t>(c, "pr.flag", nmax);
-    uint32_t* heavy = buf<uint32_t>(c, "pr.heavy", nmax);
-    unsigned long long* d_n = (unsigned long long*)buf<uint64_t>(c, "pr.counts", 2);  // [0] ready, [1] heavy
+    uint32_t* qwave = buf<uint32_t>(c, "pr.qwave", nmax);
+    uint32_t* qblock = buf<uint32_t>(c, "pr.qblock", nmax);
+    // [0] ready, [1] wave-path queue, [2] workgroup-path queue
+    unsigned long long* d_n = (unsigned long long*)buf<uint64_t>(c, "pr.counts", 3);
     uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(nmax) + 1);
-    check(c, hipMemsetAsync(d_n, 0, 16, s), "memset");
+    check(c, hipMemsetAsync(d_n, 0, 24, s), "memset");
     check(c, launch_ready_init((const uint64_t*)Bt.rowptr, J, indeg, ready[0], d_n, s), "ready init");
     uint64_t r = J ? readback(c, (const uint64_t*)d_n, 1)[0] : 0;
     uint64_t used = 0, processed = 0;
@@ -295,16 +297,16 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     int cur = 0;
     while (r > 0) {
         MergeLaunch m{ready[cur], r, (const uint64_t*)At.rowptr, At.col, At.val, (const uint64_t*)Bt.rowptr, Bt.col,
-                      Bt.val, aoff, alen, arow, aval, c->merge_light, c->merge_chunk};
-        check(c, hipMemsetAsync(d_n + 1, 0, 8, s), "memset");
-        check(c, launch_merge_classify(m, ub, flag, heavy, d_n + 1, d_err, aoff, alen, s), "merge classify");
+                      Bt.val, aoff, alen, arow, aval, c->merge_light, c->merge_chunk, c->wave_blocks};
+        check(c, hipMemsetAsync(d_n + 1, 0, 16, s), "memset");
+        check(c, launch_merge_classify(m, ub, flag, qwave, qblock, d_n + 1, d_err, aoff, alen, s), "merge classify");
         check(c, scan_excl_u64(ub, ub, r, stmp, ub + r, s), "scan");
         uint64_t t = read_u64(c, ub + r);
         arow = buf_keep<uint32_t>(c, "astar.row", used + t, used);
         aval = buf_keep<uint64_t>(c, "astar.val", used + t, used);
         m.arow = arow;
         m.aval = aval;
-        check(c, launch_merge(m, flag, heavy, d_n + 1, ub, used, arow, aval, nullptr, aoff, alen, s), "merge");
+        check(c, launch_merge(m, flag, qwave, qblock, d_n + 1, ub, used, arow, aval, nullptr, aoff, alen, s), "merge");
         used += t;
         processed += r;
         levels++;
@@ -318,15 +320,15 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     if (processed != J) fail(c, MS_ERR_INTERNAL, "the junction graph has a cycle");
     // P columns: M21 rows are 2-saddles with their 1-saddle path counts
     MergeLaunch mp{nullptr, S2, (const uint64_t*)Dt.rowptr, Dt.col, Dt.val, (const uint64_t*)Bst.rowptr, Bst.col,
-                   Bst.val, aoff, alen, arow, aval, c->merge_light, c->merge_chunk};
-    check(c, hipMemsetAsync(d_n + 1, 0, 8, s), "memset");
-    check(c, launch_merge_classify(mp, ub, flag, heavy, d_n + 1, d_err, nullptr, nullptr, s), "merge classify");
+                   Bst.val, aoff, alen, arow, aval, c->merge_light, c->merge_chunk, c->wave_blocks};
+    check(c, hipMemsetAsync(d_n + 1, 0, 16, s), "memset");
+    check(c, launch_merge_classify(mp, ub, flag, qwave, qblock, d_n + 1, d_err, nullptr, nullptr, s), "merge classify");
     check(c, scan_excl_u64(ub, ub, S2, stmp, ub + S2, s), "scan");
     uint64_t tp = S2 ? read_u64(c, ub + S2) : 0;
     uint32_t* prow = buf<uint32_t>(c, "pt.row", tp);
     uint64_t* pval = buf<uint64_t>(c, "pt.val", tp);
     uint32_t* pcnt = buf<uint32_t>(c, "pt.cnt", S2 + 1);
-    check(c, launch_merge(mp, flag, heavy, d_n + 1, ub, 0, prow, pval, pcnt, nullptr, nullptr, s), "merge");
+    check(c, launch_merge(mp, flag, qwave, qblock, d_n + 1, ub, 0, prow, pval, pcnt, nullptr, nullptr, s), "merge");
     uint64_t* slot = buf<uint64_t>(c, "err_slot", 1);
     check(c, hipMemsetAsync(slot, 0, sizeof(uint64_t), s), "memset");
     check(c, hipMemcpyAsync(slot, d_err, sizeof(int), hipMemcpyDeviceToDevice, s), "copy");

@@ -30,10 +30,13 @@ struct ms_ctx {
     hipEvent_t ev[8] = {};
     double acc_ms[8] = {};
     int64_t calls = 0;
+    int64_t allocations = 0;     // device allocations since timing was enabled
+    int64_t ws_bytes = 0;        // device memory held in bufs
     int path_schedule = MS_PATHS_READY;
     uint32_t merge_light = 32;   // see MS_OPT_MERGE_LIGHT
     uint32_t merge_chunk = 4096; // see MS_OPT_MERGE_CHUNK
     int grad_tile = 0;           // see MS_OPT_GRADIENT_TILE
+    uint32_t wave_blocks = 1024; // workgroups of a wave-path merge launch (4 per compute unit)
 };
 
 namespace msc {
@@ -52,6 +55,7 @@ T* buf(ms_ctx* c, const char* name, size_t count) {
         if (b.p) {
             (void)hipStreamSynchronize(c->stream);
             (void)hipFree(b.p);
+            c->ws_bytes -= (int64_t)b.cap;
             b.p = nullptr;
             b.cap = 0;
         }
@@ -62,6 +66,8 @@ T* buf(ms_ctx* c, const char* name, size_t count) {
             throw Fail{MS_ERR_OOM};
         }
         b.cap = want;
+        c->ws_bytes += (int64_t)want;
+        c->allocations++;
     }
     return (T*)b.p;
 }
@@ -83,9 +89,12 @@ T* buf_keep(ms_ctx* c, const char* name, size_t count, size_t used) {
         if (used) (void)hipMemcpyAsync(p, b.p, used * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
         (void)hipStreamSynchronize(c->stream);
         (void)hipFree(b.p);
+        c->ws_bytes -= (int64_t)b.cap;
     }
     b.p = p;
     b.cap = want;
+    c->ws_bytes += (int64_t)want;
+    c->allocations++;
     return (T*)p;
 }
 

@@ -115,6 +115,74 @@ struct Star {
 
 __device__ __forceinline__ uint32_t ctz32(uint32_t x) { return (uint32_t)__builtin_ctz(x); }
 
+// Rank count over the 26 neighbours: for every pair a < b of star indices
+// (centre excluded), d = [K[a] > K[b]] (b precedes a) moves one unit from
+// rk[b] to rk[a].  d is a clamped (saturating) subtract and a min with 1;
+// with the two updates that is four plain VALU operations per pair.  They
+// are written out so that the compiler neither turns d back into a compare
+// (whose lane mask would have to be read back after wait states) nor keeps
+// many d values live to re-associate the sums.  The 325 pairs are taken in
+// the 25 rounds of a round-robin schedule (13 disjoint pairs per round), four
+// disjoint pairs per block, so one block never updates a rank twice.
+struct PairSchedule {
+    uint8_t a[325], b[325];
+};
+__host__ __device__ constexpr int star_of_player(int p) { return p < (int)CENTER ? p : p + 1; }
+__host__ __device__ constexpr PairSchedule make_schedule() {
+    PairSchedule s{};
+    int n = 0;
+    for (int r = 0; r < 25; r++) {
+        // circle method: players 0..24 rotate, player 25 is fixed
+        for (int k = 0; k < 13; k++) {
+            int x = k == 0 ? r : (r + k) % 25;
+            int y = k == 0 ? 25 : (r - k + 25) % 25;
+            int u = star_of_player(x), v = star_of_player(y);
+            s.a[n] = (uint8_t)(u < v ? u : v);
+            s.b[n] = (uint8_t)(u < v ? v : u);
+            n++;
+        }
+    }
+    return s;
+}
+constexpr PairSchedule kPairs = make_schedule();
+
+__device__ __forceinline__ void rank_pair(uint32_t ka, uint32_t kb, uint32_t& ra, uint32_t& rb) {
+    uint32_t d;
+    asm("v_sub_u32_e64 %2, %3, %4 clamp\n\t"
+        "v_min_u32_e32 %2, 1, %2\n\t"
+        "v_add_u32_e32 %0, %0, %2\n\t"
+        "v_sub_u32_e32 %1, %1, %2"
+        : "+v"(ra), "+v"(rb), "=&v"(d)
+        : "v"(ka), "v"(kb));
+}
+
+// four disjoint pairs
+__device__ __forceinline__ void rank_pair4(uint32_t ka0, uint32_t kb0, uint32_t& ra0, uint32_t& rb0, uint32_t ka1,
+                                           uint32_t kb1, uint32_t& ra1, uint32_t& rb1, uint32_t ka2, uint32_t kb2,
+                                           uint32_t& ra2, uint32_t& rb2, uint32_t ka3, uint32_t kb3, uint32_t& ra3,
+                                           uint32_t& rb3) {
+    uint32_t d0, d1, d2, d3;
+    asm("v_sub_u32_e64 %8, %12, %13 clamp\n\t"
+        "v_sub_u32_e64 %9, %14, %15 clamp\n\t"
+        "v_sub_u32_e64 %10, %16, %17 clamp\n\t"
+        "v_sub_u32_e64 %11, %18, %19 clamp\n\t"
+        "v_min_u32_e32 %8, 1, %8\n\t"
+        "v_min_u32_e32 %9, 1, %9\n\t"
+        "v_min_u32_e32 %10, 1, %10\n\t"
+        "v_min_u32_e32 %11, 1, %11\n\t"
+        "v_add_u32_e32 %0, %0, %8\n\t"
+        "v_sub_u32_e32 %1, %1, %8\n\t"
+        "v_add_u32_e32 %2, %2, %9\n\t"
+        "v_sub_u32_e32 %3, %3, %9\n\t"
+        "v_add_u32_e32 %4, %4, %10\n\t"
+        "v_sub_u32_e32 %5, %5, %10\n\t"
+        "v_add_u32_e32 %6, %6, %11\n\t"
+        "v_sub_u32_e32 %7, %7, %11"
+        : "+v"(ra0), "+v"(rb0), "+v"(ra1), "+v"(rb1), "+v"(ra2), "+v"(rb2), "+v"(ra3), "+v"(rb3), "=&v"(d0),
+          "=&v"(d1), "=&v"(d2), "=&v"(d3)
+        : "v"(ka0), "v"(kb0), "v"(ka1), "v"(kb1), "v"(ka2), "v"(kb2), "v"(ka3), "v"(kb3));
+}
+
 // argmin of the per-lane cell keys over the set bits of `m` (m != 0)
 __device__ __forceinline__ uint32_t argmin_key(uint32_t m, const uint32_t* kk, int tid) {
     uint32_t best = 0, bk = 0xFFFFFFFFu;
@@ -186,21 +254,25 @@ __device__ void lower_star(const uint32_t* fk, int fidx, const Star<T>& st, uint
         return;
     }
     // rank of every neighbour in the vertex order (ties broken by id, which
-    // among the neighbours of one vertex is the order of the star index)
+    // among the neighbours of one vertex is the order of the star index):
+    // rk[b] starts at the number of non-centre indices below b, and every
+    // pair a < b with K[a] > K[b] moves one unit from rk[b] to rk[a]
     uint32_t rk[27];
-    Unroll<27>::run([&](auto jc) { rk[decltype(jc)::value] = 0; });
-    Unroll<27>::run([&](auto bc) {
-        constexpr int b = decltype(bc)::value;
-        if constexpr (b != (int)CENTER) {
-            Unroll<b>::run([&](auto ac) {
-                constexpr int a = decltype(ac)::value;
-                if constexpr (a != (int)CENTER) {
-                    bool c = K[a] <= K[b];  // a precedes b
-                    rk[b] += c ? 1u : 0u;
-                    rk[a] += c ? 0u : 1u;
-                }
-            });
-        }
+    Unroll<27>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        rk[j] = (uint32_t)(j > (int)CENTER ? j - 1 : j);
+    });
+    Unroll<25>::run([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        Unroll<3>::run([&](auto gc) {
+            constexpr int p = 13 * r + 4 * decltype(gc)::value;
+            rank_pair4(K[kPairs.a[p]], K[kPairs.b[p]], rk[kPairs.a[p]], rk[kPairs.b[p]], K[kPairs.a[p + 1]],
+                       K[kPairs.b[p + 1]], rk[kPairs.a[p + 1]], rk[kPairs.b[p + 1]], K[kPairs.a[p + 2]],
+                       K[kPairs.b[p + 2]], rk[kPairs.a[p + 2]], rk[kPairs.b[p + 2]], K[kPairs.a[p + 3]],
+                       K[kPairs.b[p + 3]], rk[kPairs.a[p + 3]], rk[kPairs.b[p + 3]]);
+        });
+        constexpr int p = 13 * r + 12;
+        rank_pair(K[kPairs.a[p]], K[kPairs.b[p]], rk[kPairs.a[p]], rk[kPairs.b[p]]);
     });
     // cell keys: bit set of the ranks of the cell's other vertices; comparing
     // them as integers is the lexicographic comparison of the descending

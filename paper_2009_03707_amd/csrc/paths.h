@@ -22,19 +22,22 @@ struct MergeLaunch {
     const uint32_t* arow;
     const uint64_t* aval;
     uint32_t light_ub;  // columns with at most this many inputs (and <= 8 lists) merge in one thread
-    uint32_t chunk;     // other columns merge in chunks of this many entries (1..4096)
+    uint32_t chunk;     // other columns merge in chunks of at most this many entries (1..4096)
+    uint32_t wave_blocks;  // workgroups of the wave-path launch (each wave strides over its queue)
 };
 
-// Upper bound (input entries) per output column into ub, and the queue of
-// columns that need a workgroup (heavy / nheavy).  Columns with more than 256
-// inputs set bit 32 of *err and are given an empty range.
-hipError_t launch_merge_classify(const MergeLaunch& m, uint64_t* ub, uint8_t* heavy_flag, uint32_t* heavy,
-                                 unsigned long long* nheavy, int* err, uint64_t* col_off, uint32_t* col_len,
+// Upper bound (input entries) per output column into ub, a path flag per
+// column, and the queues of columns for the wave path (qwave, count qn[0])
+// and the workgroup path (qblock, count qn[1]); qn must be zero on entry.
+// Columns with more than 256 input lists set bit 32 of *err and are given an
+// empty range.
+hipError_t launch_merge_classify(const MergeLaunch& m, uint64_t* ub, uint8_t* flag, uint32_t* qwave, uint32_t* qblock,
+                                 unsigned long long* qn, int* err, uint64_t* col_off, uint32_t* col_len,
                                  hipStream_t s);
 // Forms every output column i at out_base + off[i] (off: exclusive scan of
 // ub).  Writes its length to cnt[i] and/or to (col_off, col_len)[column].
-hipError_t launch_merge(const MergeLaunch& m, const uint8_t* heavy_flag, const uint32_t* heavy,
-                        const unsigned long long* nheavy, const uint64_t* off, uint64_t out_base, uint32_t* orow,
+hipError_t launch_merge(const MergeLaunch& m, const uint8_t* flag, const uint32_t* qwave, const uint32_t* qblock,
+                        const unsigned long long* qn, const uint64_t* off, uint64_t out_base, uint32_t* orow,
                         uint64_t* oval, uint32_t* cnt, uint64_t* col_off, uint32_t* col_len, hipStream_t s);
 // Copies column i from src_off[i] to dst_off[i] (dst_off: n + 1 entries).
 hipError_t launch_compact(const uint64_t* src_off, const uint64_t* dst_off, uint64_t n, uint64_t total,

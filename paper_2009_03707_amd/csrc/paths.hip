@@ -14,13 +14,18 @@
 // P = D + A* B* is formed the same way per 2-saddle column, which yields M21
 // (rows 2-saddles, columns 1-saddles) directly in canonical order.
 //
-// Columns with few, short inputs are merged by one thread in registers.  All
-// others go to a workgroup that merges in chunks: a binary search on the row
-// value picks a threshold so that every input entry up to it fits in LDS;
-// those entries are loaded (coalesced, per input list), bitonic-sorted,
-// de-duplicated with saturating sums and written; the lists advance past the
-// threshold.  Entries with equal rows never straddle two chunks, so the
-// result is exact for any column length.
+// Columns with few, short inputs are merged by one thread in registers.
+// Columns with at most 32 input lists are merged by one wave: the lists'
+// next segments are staged in LDS (a chunk), every entry's place in the
+// merged chunk is its index in its own list plus, for every other list, the
+// number of entries below it there (ties ordered by list), found by binary
+// search in LDS; runs of equal rows are then summed and written.  The chunk
+// boundary is a row threshold t taken as the smallest of the lists' rows at
+// depth chunk/k, so at most `chunk` entries are at or below t, at least one
+// list advances, and entries with equal rows never straddle two chunks.
+// Columns with more lists go to a workgroup that picks the threshold by a
+// binary search on the row value and sorts the chunk in LDS (bitonic).
+// Every path is exact for any column length.
 //
 // Each column is written at an offset that reserves its input count (an
 // upper bound of its length), which avoids a separate counting pass; the A*
@@ -32,8 +37,11 @@ namespace {
 
 constexpr int BT = 256;
 constexpr int LIGHT_K = 8;         // thread path: at most this many input lists
+constexpr int WAVE_K = 32;         // wave path: at most this many input lists
 constexpr int MAX_K = 256;         // block path: at most this many input lists
-constexpr int CAP = 4096;          // entries per LDS chunk
+constexpr int CAP = 4096;          // block path: entries per LDS chunk
+constexpr int WCAP = 512;          // wave path: entries per LDS chunk
+constexpr int WPB = BT / WAVE;     // waves per workgroup
 constexpr uint32_t NOROW = 0xFFFFFFFFu;
 
 struct MergeArgs {
@@ -83,52 +91,55 @@ __device__ __forceinline__ uint32_t num_lists(const MergeArgs& a, uint32_t c) {
     return 1 + (uint32_t)(a.prp[c + 1] - a.prp[c]);
 }
 
-// Upper bound (input entries) of every output column, and the queue of
-// columns for the workgroup path.
-__global__ __launch_bounds__(BT) void k_classify(MergeArgs a, uint64_t* __restrict__ ub,
-                                                 uint8_t* __restrict__ heavy_flag, uint32_t* __restrict__ heavy,
-                                                 unsigned long long* __restrict__ nheavy, int* __restrict__ err,
+// Upper bound (input entries) of every output column, and the queues of
+// columns for the wave path (qn[0] entries in qwave) and the workgroup path
+// (qn[1] entries in qblock).  flag: 0 thread, 1 wave, 3 workgroup, 2 skipped.
+__global__ __launch_bounds__(BT) void k_classify(MergeArgs a, uint64_t* __restrict__ ub, uint8_t* __restrict__ flag,
+                                                 uint32_t* __restrict__ qwave, uint32_t* __restrict__ qblock,
+                                                 unsigned long long* __restrict__ qn, int* __restrict__ err,
                                                  uint64_t* __restrict__ col_off, uint32_t* __restrict__ col_len) {
     __shared__ unsigned long long sc[BT / WAVE + 1];
-    __shared__ unsigned long long base;
+    __shared__ unsigned long long base_w, base_b;
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
-    unsigned long long h = 0;
+    unsigned long long h = 0;  // low half: wave path, high half: workgroup path
     if (i < a.n) {
         uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
         uint32_t k = num_lists(a, c);
         uint64_t u = a.brp[c + 1] - a.brp[c];
         for (uint32_t s = 1; s < k; s++) u += a.alen[a.pcol[a.prp[c] + (s - 1)]];
         ub[i] = u;
-        bool hv = !(k <= (uint32_t)LIGHT_K && u <= (uint64_t)a.light_ub);
-        if (hv && k > (uint32_t)MAX_K) {
+        uint8_t f = (k <= (uint32_t)LIGHT_K && u <= (uint64_t)a.light_ub) ? 0 : (k <= (uint32_t)WAVE_K ? 1 : 3);
+        if (f == 3 && k > (uint32_t)MAX_K) {
             atomicOr(err, 32);  // skipped: the caller falls back to the power iteration
-            hv = false;
+            f = 2;
             ub[i] = 0;
-            heavy_flag[i] = 2;
             if (col_off) {  // an empty column keeps later reads in bounds
                 col_off[c] = 0;
                 col_len[c] = 0;
             }
-        } else {
-            heavy_flag[i] = hv ? 1 : 0;
         }
-        h = hv ? 1 : 0;
+        flag[i] = f;
+        h = f == 1 ? 1ull : (f == 3 ? (1ull << 32) : 0ull);
     }
     unsigned long long tot;
     unsigned long long ex = block_excl_scan<unsigned long long, BT>(h, sc, tot);
-    if (threadIdx.x == 0) base = tot ? atomicAdd(nheavy, tot) : 0;
+    if (threadIdx.x == 0) {
+        base_w = (tot & 0xFFFFFFFFull) ? atomicAdd(&qn[0], tot & 0xFFFFFFFFull) : 0;
+        base_b = (tot >> 32) ? atomicAdd(&qn[1], tot >> 32) : 0;
+    }
     __syncthreads();
-    if (h) heavy[base + ex] = (uint32_t)i;
+    if (h == 1) qwave[base_w + (ex & 0xFFFFFFFFull)] = (uint32_t)i;
+    if (h >> 32) qblock[base_b + (ex >> 32)] = (uint32_t)i;
 }
 
 // Thread-per-column merge (few, short inputs), written at out_base + off[i].
-__global__ __launch_bounds__(BT) void k_merge_thread(MergeArgs a, const uint8_t* __restrict__ heavy_flag,
+__global__ __launch_bounds__(BT) void k_merge_thread(MergeArgs a, const uint8_t* __restrict__ flag,
                                                      const uint64_t* __restrict__ off, uint64_t out_base,
                                                      uint32_t* __restrict__ orow, uint64_t* __restrict__ oval,
                                                      uint32_t* __restrict__ cnt, uint64_t* __restrict__ col_off,
                                                      uint32_t* __restrict__ col_len) {
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
-    if (i >= a.n || heavy_flag[i]) return;
+    if (i >= a.n || flag[i]) return;
     uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
     uint32_t k = num_lists(a, c);
     const uint32_t* rp[LIGHT_K];
@@ -191,9 +202,156 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t* row, uint32_t len, 
     return lo;
 }
 
+// number of entries of a sorted list with row < t
+__device__ __forceinline__ uint32_t count_lt(const uint32_t* row, uint32_t len, uint32_t t) {
+    uint32_t lo = 0, hi = len;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (row[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t x) {
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) x += __shfl_xor(x, d, WAVE);
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) {
+        uint32_t y = __shfl_xor(x, d, WAVE);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+// Orders the LDS accesses of one wave (the waves of a workgroup run
+// independently here, so there is no workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Wave-per-column chunked merge by rank (see the file comment).  Lane s < k
+// owns input list s.
+__global__ __launch_bounds__(BT) void k_merge_wave(MergeArgs a, const uint32_t* __restrict__ queue,
+                                                   const unsigned long long* __restrict__ qn,
+                                                   const uint64_t* __restrict__ off, uint64_t out_base,
+                                                   uint32_t* __restrict__ orow, uint64_t* __restrict__ oval,
+                                                   uint32_t* __restrict__ cnt, uint64_t* __restrict__ col_off,
+                                                   uint32_t* __restrict__ col_len) {
+    __shared__ uint32_t s_in[WPB][WCAP];       // staged rows, list segments back to back
+    __shared__ uint32_t s_key[WPB][WCAP];      // merged rows
+    __shared__ uint64_t s_val[WPB][WCAP];      // merged scaled counts
+    __shared__ uint32_t s_seg[WPB][WAVE_K + 1];
+    __shared__ uint32_t s_pos[WPB][WAVE_K];
+    __shared__ const uint64_t* s_vp[WPB][WAVE_K];
+    __shared__ uint64_t s_mul[WPB][WAVE_K];
+    const int lane = lane_id();
+    const int w = (int)threadIdx.x / WAVE;
+    uint32_t* in = s_in[w];
+    uint32_t* key = s_key[w];
+    uint64_t* val = s_val[w];
+    uint32_t* seg = s_seg[w];
+    const uint64_t nq = qn[0];
+    const uint64_t stride = (uint64_t)gridDim.x * WPB;
+    for (uint64_t h = (uint64_t)blockIdx.x * WPB + w; h < nq; h += stride) {
+        const uint32_t i = queue[h];
+        const uint32_t c = a.cols ? a.cols[i] : i;
+        const uint32_t k = num_lists(a, c);
+        const uint32_t* lr = nullptr;
+        uint32_t len = 0, pos = 0;
+        if ((uint32_t)lane < k) {
+            ListRef L = list_of(a, c, (uint32_t)lane);
+            lr = L.row;
+            len = (uint32_t)L.len;
+            s_vp[w][lane] = L.val;
+            s_mul[w][lane] = L.mul;
+        }
+        uint32_t chunk = a.chunk < (uint32_t)WCAP ? a.chunk : (uint32_t)WCAP;
+        if (chunk < k) chunk = k;  // rows are unique per list, so every list can give one
+        const uint32_t q = chunk / k;
+        const uint64_t o = out_base + off[i];
+        uint64_t written = 0;
+        for (;;) {
+            const uint32_t rem = len - pos;
+            if (wave_sum_u64(rem) == 0) break;
+            uint32_t take = rem;
+            if (wave_sum_u64(rem) > chunk) {
+                // the smallest row at depth q over the lists longer than q
+                const uint32_t t = wave_min_u32(rem > q ? lr[pos + q - 1] : NOROW);
+                take = rem ? count_le(lr + pos, rem, t) : 0u;
+            }
+            const uint32_t incl = wave_incl_scan(take);
+            const uint32_t m = __shfl(incl, WAVE - 1, WAVE);
+            if ((uint32_t)lane < k) {
+                seg[lane] = incl - take;
+                s_pos[w][lane] = pos;
+            }
+            if ((uint32_t)lane == k) seg[k] = m;
+            for (uint32_t s = 0; s < k; s++) {
+                const uint32_t* r = (const uint32_t*)(uintptr_t)__shfl((unsigned long long)(uintptr_t)lr, (int)s, WAVE);
+                const uint32_t ps = __shfl(pos, (int)s, WAVE);
+                const uint32_t ts = __shfl(take, (int)s, WAVE);
+                const uint32_t es = __shfl(incl - take, (int)s, WAVE);
+                for (uint32_t e = (uint32_t)lane; e < ts; e += WAVE) in[es + e] = r[ps + e];
+            }
+            wave_sync();
+            for (uint32_t j = (uint32_t)lane; j < m; j += WAVE) {
+                // the list of entry j: the last s with seg[s] <= j
+                uint32_t lo = 0, hi = k;
+                while (hi - lo > 1) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (seg[mid] <= j) lo = mid;
+                    else hi = mid;
+                }
+                const uint32_t s = lo;
+                const uint32_t x = in[j];
+                const uint32_t idx = j - seg[s];
+                uint32_t rank = idx;
+                for (uint32_t t = 0; t < k; t++) {
+                    if (t == s) continue;
+                    const uint32_t b = seg[t], l = seg[t + 1] - b;
+                    rank += t < s ? count_le(in + b, l, x) : count_lt(in + b, l, x);
+                }
+                key[rank] = x;
+                val[rank] = sat_mul(s_vp[w][s][s_pos[w][s] + idx], s_mul[w][s]);
+            }
+            wave_sync();
+            for (uint32_t b = 0; b < m; b += WAVE) {
+                const uint32_t p = b + (uint32_t)lane;
+                const bool head = p < m && (p == 0 || key[p] != key[p - 1]);
+                const uint64_t mask = __ballot(head);
+                if (head) {
+                    const uint32_t x = key[p];
+                    uint64_t sum = val[p];
+                    for (uint32_t f = p + 1; f < m && key[f] == x; f++) sum = sat_add(sum, val[f]);
+                    const uint64_t d = o + written + (uint64_t)__popcll(mask & ((1ull << lane) - 1ull));
+                    orow[d] = x;
+                    oval[d] = sum;
+                }
+                written += (uint64_t)__popcll(mask);
+            }
+            pos += take;
+            wave_sync();  // the next chunk reuses the LDS arrays
+        }
+        if (lane == 0) {
+            if (cnt) cnt[i] = (uint32_t)written;
+            if (col_off) {
+                col_off[c] = o;
+                col_len[c] = (uint32_t)written;
+            }
+        }
+    }
+}
+
 // Workgroup-per-column chunked merge (see the file comment).
 __global__ __launch_bounds__(BT) void k_merge_block(MergeArgs a, const uint32_t* __restrict__ heavy,
-                                                    const unsigned long long* __restrict__ nheavy,
+                                                    const unsigned long long* __restrict__ qn,
                                                     const uint64_t* __restrict__ off, uint64_t out_base,
                                                     uint32_t* __restrict__ orow, uint64_t* __restrict__ oval,
                                                     uint32_t* __restrict__ cnt, uint64_t* __restrict__ col_off,
@@ -207,7 +365,7 @@ __global__ __launch_bounds__(BT) void k_merge_block(MergeArgs a, const uint32_t*
     __shared__ unsigned long long sc[BT / WAVE + 1];
     __shared__ uint32_t s_thr, s_total;
     const int tid = threadIdx.x;
-    const uint64_t nh = *nheavy;
+    const uint64_t nh = qn[1];
     for (uint64_t h = blockIdx.x; h < nh; h += gridDim.x) {
         const uint32_t i = heavy[h];
         const uint32_t c = a.cols ? a.cols[i] : i;
@@ -426,25 +584,32 @@ constexpr unsigned BLOCK_GRID = 2048;
 
 }  // namespace
 
-hipError_t launch_merge_classify(const MergeLaunch& m, uint64_t* ub, uint8_t* heavy_flag, uint32_t* heavy,
-                                 unsigned long long* nheavy, int* err, uint64_t* col_off, uint32_t* col_len,
+hipError_t launch_merge_classify(const MergeLaunch& m, uint64_t* ub, uint8_t* flag, uint32_t* qwave, uint32_t* qblock,
+                                 unsigned long long* qn, int* err, uint64_t* col_off, uint32_t* col_len,
                                  hipStream_t s) {
     if (m.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_classify, dim3(grid_blocks(m.n, BT)), dim3(BT), 0, s, to_args(m), ub, heavy_flag, heavy,
-                       nheavy, err, col_off, col_len);
+    hipLaunchKernelGGL(k_classify, dim3(grid_blocks(m.n, BT)), dim3(BT), 0, s, to_args(m), ub, flag, qwave, qblock,
+                       qn, err, col_off, col_len);
     return hipGetLastError();
 }
 
-hipError_t launch_merge(const MergeLaunch& m, const uint8_t* heavy_flag, const uint32_t* heavy,
-                        const unsigned long long* nheavy, const uint64_t* off, uint64_t out_base, uint32_t* orow,
+hipError_t launch_merge(const MergeLaunch& m, const uint8_t* flag, const uint32_t* qwave, const uint32_t* qblock,
+                        const unsigned long long* qn, const uint64_t* off, uint64_t out_base, uint32_t* orow,
                         uint64_t* oval, uint32_t* cnt, uint64_t* col_off, uint32_t* col_len, hipStream_t s) {
     if (m.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_merge_thread, dim3(grid_blocks(m.n, BT)), dim3(BT), 0, s, to_args(m), heavy_flag, off,
-                       out_base, orow, oval, cnt, col_off, col_len);
+    const MergeArgs a = to_args(m);
+    hipLaunchKernelGGL(k_merge_thread, dim3(grid_blocks(m.n, BT)), dim3(BT), 0, s, a, flag, off, out_base, orow, oval,
+                       cnt, col_off, col_len);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge_block, dim3(BLOCK_GRID), dim3(BT), 0, s, to_args(m), heavy, nheavy, off, out_base, orow,
-                       oval, cnt, col_off, col_len);
+    const uint64_t wb = (m.n + WPB - 1) / WPB;
+    const unsigned wave_blocks = (unsigned)(wb < m.wave_blocks ? wb : m.wave_blocks);
+    hipLaunchKernelGGL(k_merge_wave, dim3(wave_blocks ? wave_blocks : 1u), dim3(BT), 0, s, a, qwave, qn, off, out_base,
+                       orow, oval, cnt, col_off, col_len);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_merge_block, dim3(BLOCK_GRID), dim3(BT), 0, s, a, qblock, qn, off, out_base, orow, oval, cnt,
+                       col_off, col_len);
     return hipGetLastError();
 }
 

@@ -90,45 +90,78 @@ __global__ __launch_bounds__(RT) void radix_hist(const K* __restrict__ keys, uin
     hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
+// One pass of the stable LSD sort over a tile of RTILE keys.  Every key's
+// rank among the keys of the tile with the same digit is found round by
+// round (a round is RT keys in index order; peers by ballot, earlier waves
+// by per-wave digit counts).  The tile is then staged in LDS ordered by
+// (digit, rank), and written out so that the keys of one digit leave as one
+// contiguous run at that digit's global offset for this tile.
 template <typename K>
 __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                     K* __restrict__ okeys, uint32_t* __restrict__ ovals, uint64_t n,
                                                     int shift, uint64_t nblk, const uint64_t* __restrict__ offs) {
-    __shared__ uint64_t base_of[256];
+    __shared__ uint64_t gbase[256];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t tstart[256];
     __shared__ uint32_t wcnt[RWAVES][256];
+    __shared__ K skey[RTILE];
+    __shared__ uint32_t sval[RTILE];
+    __shared__ uint32_t sc[RT / WAVE + 1];
     const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
-    base_of[tid] = offs[(uint64_t)tid * nblk + blockIdx.x];
+    gbase[tid] = offs[(uint64_t)tid * nblk + blockIdx.x];
+    run[tid] = 0;
     const uint64_t lt = (1ull << lane) - 1ull;
-    uint64_t tbase = (uint64_t)blockIdx.x * RTILE;
+    const uint64_t tbase = (uint64_t)blockIdx.x * RTILE;
+    K kr[RR];
+    uint32_t vr[RR], rk[RR];
+#pragma unroll
     for (int r = 0; r < RR; r++) {
         for (int i = tid; i < RWAVES * 256; i += RT) (&wcnt[0][0])[i] = 0;
         __syncthreads();
-        uint64_t j = tbase + (uint64_t)r * RT + tid;
-        bool valid = j < n;
-        K key = valid ? keys[j] : (K)0;
-        uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint64_t j = tbase + (uint64_t)r * RT + tid;
+        const bool valid = j < n;
+        const K key = valid ? keys[j] : (K)0;
+        kr[r] = key;
+        vr[r] = valid ? vals[j] : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
             uint64_t bb = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bb : ~bb;
         }
-        uint32_t wrank = (uint32_t)__popcll(peers & lt);
+        const uint32_t wrank = (uint32_t)__popcll(peers & lt);
         if (valid && wrank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
-        if (valid) {
-            uint64_t pos = base_of[d] + wrank;
-            for (int q = 0; q < w; q++) pos += wcnt[q][d];
-            okeys[pos] = key;
-            ovals[pos] = vals[j];
-        }
+        uint32_t pos = run[d] + wrank;
+        for (int q = 0; q < w; q++) pos += wcnt[q][d];
+        rk[r] = pos;
         __syncthreads();
-        {
-            uint32_t add = 0;
-            for (int q = 0; q < RWAVES; q++) add += wcnt[q][tid];
-            base_of[tid] += add;
+        uint32_t add = 0;
+        for (int q = 0; q < RWAVES; q++) add += wcnt[q][tid];
+        run[tid] += add;
+        __syncthreads();  // wcnt is cleared at the top of the next round
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<uint32_t, RT>(run[tid], sc, tot);
+    tstart[tid] = ex;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RR; r++) {
+        const uint64_t j = tbase + (uint64_t)r * RT + tid;
+        if (j < n) {
+            const uint32_t p = tstart[(uint32_t)(kr[r] >> shift) & 255u] + rk[r];
+            skey[p] = kr[r];
+            sval[p] = vr[r];
         }
-        __syncthreads();
+    }
+    __syncthreads();
+    for (uint32_t i = (uint32_t)tid; i < tot; i += RT) {
+        const K key = skey[i];
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint64_t g = gbase[d] + (i - tstart[d]);
+        okeys[g] = key;
+        ovals[g] = sval[i];
     }
 }
 

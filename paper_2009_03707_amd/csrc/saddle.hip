@@ -12,7 +12,9 @@
 // edge and appends the new ones to the next frontier with one atomic per
 // wave (the order inside a frontier does not matter, only the visited set).
 // The same lane counts the node's out-degree and, for reachable non-saddle
-// nodes, marks junctions (out-degree > 1, Section 3.3) and numbers them.
+// nodes, marks junctions (out-degree > 1, Section 3.3) and numbers them; a
+// node with a single out-edge records that edge's step in its label, so the
+// minor tracing below follows it without looking at the cofacets again.
 //
 // DAG minor (Section 3.3, "DAG minor construction"): every (source, out-edge)
 // pair -- sources are the 1-saddles and junctions -- is traced by one lane
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
     bool valid = i < ncur;
     uint32_t t[4];
-    uint32_t nt = 0, outdeg = 0;
+    uint32_t nt = 0, outdeg = 0, step = 0;
     uint32_t e = 0;
     if (valid) {
         e = cur[i];
@@ -82,11 +84,13 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
                 uint32_t nq = nib_of(grad[q.w], q.k);
                 if (nq >= NB_CRIT) {
                     outdeg++;
+                    step = (2u * b + (s > 0 ? 1u : 0u)) | (nq << 3);
                     continue;
                 }
                 CellRef e2;
                 if (!quad_edge_partner(g, q.w, q.k, nq, e2)) continue;
                 outdeg++;
+                step = (2u * b + (s > 0 ? 1u : 0u)) | (nq << 3);
                 uint32_t bit = 1u << (8u * (e2.w & 3u) + e2.k);
                 uint32_t old = atomicOr(&vis[e2.w >> 2], bit);
                 if (!(old & bit)) t[nt++] = 8u * e2.w + e2.k;
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
             label[e] = jid;
             jlist[jid] = e;
         } else {
-            label[e] = NOT_JUNCTION;
+            label[e] = outdeg == 1 ? (SUCC_FLAG | step) : NOT_JUNCTION;
         }
     }
 }
@@ -146,12 +150,12 @@ __global__ __launch_bounds__(BT) void k_minor_trace(const uint32_t* __restrict__
     uint32_t id = 0;
     CellRef q;
     if (cell_step(g, w, k, c, (int)b, s, q.w, q.k) && !(hv && q.w == v.w && q.k == v.k)) {
+        uint32_t nq = nib_of(grad[q.w], q.k);
         for (uint64_t step = 0;; step++) {
             if (step > max_steps) {
                 atomicOr(err, 8);
                 break;
             }
-            uint32_t nq = nib_of(grad[q.w], q.k);
             if (nq >= NB_CRIT) {
                 typ = T_S2;
                 id = label[8u * q.w + q.k];
@@ -159,32 +163,22 @@ __global__ __launch_bounds__(BT) void k_minor_trace(const uint32_t* __restrict__
             }
             CellRef e2;
             if (!quad_edge_partner(g, q.w, q.k, nq, e2)) break;  // paired with a cube: dead end
-            uint32_t lab = label[8u * e2.w + e2.k];
-            if (lab != NOT_JUNCTION) {
+            const uint32_t lab = label[8u * e2.w + e2.k];
+            if (!(lab & SUCC_FLAG)) {
                 typ = T_JUNC;
                 id = lab;
                 break;
             }
-            // e2 has out-degree <= 1 and is paired with q: find its only out-edge
-            uint32_t a2 = (uint32_t)__builtin_ctz(e2.k);
+            if (lab == NOT_JUNCTION) break;  // no out-edge: dead end
+            // e2 has exactly one out-edge; its step was recorded by the BFS
             uint32_t c2[3];
             g.coords(e2.w - fbase, c2);
-            bool found = false;
-            for (uint32_t bb = 0; bb < 3 && !found; bb++) {
-                if (bb == a2) continue;
-                for (int ss = -1; ss <= 1 && !found; ss += 2) {
-                    CellRef q2;
-                    if (!cell_step(g, e2.w, e2.k, c2, (int)bb, ss, q2.w, q2.k)) continue;
-                    if (q2.w == q.w && q2.k == q.k) continue;
-                    uint32_t n2 = nib_of(grad[q2.w], q2.k);
-                    CellRef tmp;
-                    if (n2 >= NB_CRIT || quad_edge_partner(g, q2.w, q2.k, n2, tmp)) {
-                        q = q2;
-                        found = true;
-                    }
-                }
+            const uint32_t st = lab & 7u;
+            if (!cell_step(g, e2.w, e2.k, c2, (int)(st >> 1), (st & 1u) ? 1 : -1, q.w, q.k)) {
+                atomicOr(err, 16);
+                break;
             }
-            if (!found) break;  // dead end
+            nq = (lab >> 3) & 15u;
         }
     }
     if ((typ == T_S2 && id >= S2) || (typ == T_JUNC && id >= J)) {

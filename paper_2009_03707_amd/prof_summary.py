@@ -1,0 +1,77 @@
+"""Summarise rocprofv3 output into short per-kernel tables.
+
+Kernel trace (rocpd SQLite, written by
+`rocprofv3 --kernel-trace --stats -d DIR -o run -- <command>`): calls, total
+ms, average us, share of GPU kernel time.
+
+    python -m paper_2009_03707_amd.prof_summary DIR/run_results.db [N]
+
+Counters (CSV, written by `rocprofv3 --pmc C1 C2 ... --output-format csv -d
+DIR -o run -- <command>`): per kernel and counter, the dispatch count and the
+mean value per dispatch.  With --copy-bytes B, the kernel whose name contains
+"copy" is taken as a plain copy of B bytes read and B bytes written, and each
+counter's bytes-per-KiB scale factor (B / (1024 * mean)) is printed.
+
+    python -m paper_2009_03707_amd.prof_summary DIR/run_counter_collection.csv [N] [--copy-bytes B]
+"""
+import collections
+import csv
+import re
+import sqlite3
+import sys
+
+
+def short(name: str) -> str:
+    name = name.replace("msc::(anonymous namespace)::", "").replace("void ", "")
+    depth, out = 0, []
+    for ch in name:  # drop the argument list, keep template arguments
+        if ch == "(":
+            depth += 1
+        if depth == 0:
+            out.append(ch)
+        if ch == ")":
+            depth -= 1
+    return re.sub(r"\s+", " ", "".join(out)).strip()
+
+
+def counters(path, n, copy_bytes):
+    acc = collections.defaultdict(lambda: [0, 0.0])
+    with open(path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            key = (short(row["Kernel_Name"]), row["Counter_Name"])
+            acc[key][0] += 1
+            acc[key][1] += float(row["Counter_Value"])
+    rows = sorted(acc.items(), key=lambda kv: -kv[1][1])
+    print(f"{'kernel':44s} {'counter':>12s} {'dispatches':>10s} {'mean/dispatch':>14s}")
+    for (k, c), (cnt, tot) in rows[:n]:
+        print(f"{k[:44]:44s} {c:>12s} {cnt:10d} {tot / cnt:14.1f}")
+    if copy_bytes:
+        for (k, c), (cnt, tot) in rows:
+            if "copy" in k.lower():
+                mean = tot / cnt
+                print(f"copy calibration: {k[:44]} {c} mean {mean:.1f} per dispatch for {copy_bytes} B "
+                      f"-> {copy_bytes / (1024.0 * mean):.4f} bytes per counted KiB / 1024")
+
+
+def main():
+    if sys.argv[1].endswith(".csv"):
+        args = [a for a in sys.argv[2:] if not a.startswith("--")]
+        cb = 0
+        if "--copy-bytes" in sys.argv:
+            cb = int(sys.argv[sys.argv.index("--copy-bytes") + 1])
+            args = [a for a in args if a != str(cb)]
+        counters(sys.argv[1], int(args[0]) if args else 40, cb)
+        return
+    db = sys.argv[1]
+    n = int(sys.argv[2]) if len(sys.argv) > 2 else 25
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    total = sum(r[2] for r in rows)
+    print(f"{'kernel':44s} {'calls':>7s} {'total_ms':>10s} {'avg_us':>10s} {'pct':>6s}")
+    for r in rows[:n]:
+        print(f"{short(r[0])[:44]:44s} {r[1]:7d} {r[2] / 1000:10.2f} {r[3]:10.1f} {r[4]:6.1f}")
+    print(f"{'(all kernels)':44s} {sum(r[1] for r in rows):7d} {total / 1000:10.2f}")
+
+
+if __name__ == "__main__":
+    main()

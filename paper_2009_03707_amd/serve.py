@@ -95,6 +95,14 @@ class GpuSlot:
     def release(self):
         self.ctx.release()
 
+    def start_counting(self):
+        self.ctx.set_timing(True)
+
+    def counters(self) -> dict:
+        t = self.ctx.timing()
+        return {"allocations": t["allocations"], "workspace_gb": round(t["workspace_bytes"] / 1e9, 2),
+                "busy_s": round(t["total_ms"] / 1e3, 3), "calls": t["calls"]}
+
     def close(self):
         self.ctx.close()
 
@@ -349,11 +357,15 @@ def serve_benchmark(steps: int = 200, slots: int = 3, options: dict | None = Non
     slot_set = [GpuSlot(options) for _ in range(slots)]
 
     def serve(time_scale):
+        for sl in slot_set:
+            sl.start_counting()
         srv = Server(slot_set, hbm_budget=budget, close_slots=False)
         try:
-            return run_stream(srv, fresh(), produce=produce, time_scale=time_scale), srv
+            summ = run_stream(srv, fresh(), produce=produce, time_scale=time_scale)
         finally:
             srv.close()
+        summ["slots"] = [sl.counters() for sl in slot_set]
+        return summ, srv
 
     try:
         _, warm = serve(0.0)  # warm the slots' workspaces on the whole stream

@@ -109,12 +109,17 @@ enum {
     /* Default.  A* is the solution of A* = A + A* B; its columns are formed by
      * sparse products restricted to the junctions whose minor predecessors
      * are complete (a ready frontier in topological order), so every
-     * (1-saddle, junction) pair is produced once.  Falls back to
-     * MS_PATHS_POWER by itself when a column has more than 64 inputs. */
+     * (1-saddle, junction) pair is produced once.  Columns are merged by a
+     * thread, a wave or a workgroup depending on their size.  Falls back to
+     * MS_PATHS_POWER by itself when a column has more than 256 inputs. */
     MS_PATHS_READY = 0,
     /* The paper's iteration: A* accumulates the frontier A, advanced by
      * A <- A B until the product is empty, then P = D + A* B*. */
-    MS_PATHS_POWER = 1
+    MS_PATHS_POWER = 1,
+    /* The ready frontier of MS_PATHS_READY with entry-parallel merges: one
+     * thread per input entry of a level ranks it in its column; run heads
+     * are then compacted by a scan.  No limit on column inputs. */
+    MS_PATHS_ENTRY = 2
 };
 /* Sets an option; MS_ERR_INVALID_ARG for an unknown option or value. */
 ms_status ms_ctx_set_option(ms_ctx* ctx, int option, int64_t value);

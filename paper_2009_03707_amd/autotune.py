@@ -25,7 +25,7 @@ from . import msc
 
 DEFAULT = {"tile": 0, "schedule": msc.MS_PATHS_READY, "light": 32, "chunk": 4096}
 TILES = (0, 1, 2, 3)
-SCHEDULES = (msc.MS_PATHS_READY, msc.MS_PATHS_POWER)
+SCHEDULES = (msc.MS_PATHS_READY, msc.MS_PATHS_ENTRY, msc.MS_PATHS_POWER)
 LIGHTS = (8, 16, 32, 64, 128)
 CHUNKS = (2048, 4096)
 # the power iteration materialises every frontier (about four times the

@@ -173,7 +173,7 @@ const char* ms_last_error(const ms_ctx* ctx) { return ctx ? ctx->err.c_str() : "
 
 ms_status ms_ctx_set_option(ms_ctx* ctx, int option, int64_t value) {
     if (!ctx) return MS_ERR_INVALID_ARG;
-    if (option == MS_OPT_PATH_SCHEDULE && (value == MS_PATHS_READY || value == MS_PATHS_POWER)) {
+    if (option == MS_OPT_PATH_SCHEDULE && (value == MS_PATHS_READY || value == MS_PATHS_POWER || value == MS_PATHS_ENTRY)) {
         ctx->path_schedule = (int)value;
         return MS_OK;
     }

@@ -349,6 +349,98 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     st.products = (int64_t)(used + tp);
     return true;
 }
+// The ready schedule with entry-parallel merges (see paths.hip): per level,
+// input counts, their scan, one thread per input entry ranking it in its
+// column, a scan of the run heads and a compaction.  A* columns are stored
+// gap-free within a level; levels are placed at their upper-bound offsets.
+// P is written directly as M21 (rows 2-saddles).  No column size limit.
+void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, const ms_csr& D, uint64_t S1,
+                 uint64_t S2, uint64_t J, ms_arcs* out, int* d_err) {
+    hipStream_t s = c->stream;
+    ms_stats& st = out->stats;
+    ms_csr At, Bt, Bst, Dt;
+    transpose(c, A, "At", At);     // junction x 1-saddle
+    transpose(c, B, "Bt", Bt);     // junction x predecessor junction
+    transpose(c, Bs, "Bst", Bst);  // 2-saddle x junction
+    transpose(c, D, "Dt", Dt);     // 2-saddle x 1-saddle
+    const uint64_t nmax = (J > S2 ? J : S2) + 1;
+    uint32_t* indeg = buf<uint32_t>(c, "pr.indeg", J);
+    uint32_t* ready[2] = {buf<uint32_t>(c, "pr.ready0", J), buf<uint32_t>(c, "pr.ready1", J)};
+    uint64_t* aoff = buf<uint64_t>(c, "pr.aoff", J);
+    uint32_t* alen = buf<uint32_t>(c, "pr.alen", J);
+    uint64_t* ub = buf<uint64_t>(c, "pr.ub", nmax + 1);
+    unsigned long long* d_n = (unsigned long long*)buf<uint64_t>(c, "pr.counts", 3);
+    check(c, hipMemsetAsync(d_n, 0, 24, s), "memset");
+    check(c, launch_ready_init((const uint64_t*)Bt.rowptr, J, indeg, ready[0], d_n, s), "ready init");
+    uint64_t r = J ? readback(c, (const uint64_t*)d_n, 1)[0] : 0;
+    uint64_t used = 0, processed = 0, products = 0;
+    int64_t levels = 0;
+    uint32_t* arow = buf_keep<uint32_t>(c, "astar.row", 1, 0);
+    uint64_t* aval = buf_keep<uint64_t>(c, "astar.val", 1, 0);
+    int cur = 0;
+    // per-level scratch: ranked heads and their scan
+    auto level = [&](const MergeLaunch& m, uint64_t n, uint64_t& T, uint32_t*& hrow, uint64_t*& hval, uint64_t*& hp) {
+        uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(n) + 1);
+        check(c, launch_entry_ub(m, ub, s), "entry ub");
+        check(c, scan_excl_u64(ub, ub, n, stmp, ub + n, s), "scan");
+        T = n ? read_u64(c, ub + n) : 0;
+        hrow = buf<uint32_t>(c, "pe.hrow", T);
+        hval = buf<uint64_t>(c, "pe.hval", T);
+        uint32_t* head = buf<uint32_t>(c, "pe.head", T);
+        hp = buf<uint64_t>(c, "pe.hp", T + 1);
+        check(c, launch_entry_rank(m, ub, T, hrow, hval, head, s), "entry rank");
+        uint64_t* stmp2 = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(T) + 1);
+        check(c, scan_excl_u32_to_u64(head, hp, T, stmp2, hp + T, s), "scan");
+        return head;
+    };
+    while (r > 0) {
+        MergeLaunch m{ready[cur], r, (const uint64_t*)At.rowptr, At.col, At.val, (const uint64_t*)Bt.rowptr, Bt.col,
+                      Bt.val, aoff, alen, arow, aval, 0, 1, 1};
+        uint64_t T;
+        uint32_t* hrow;
+        uint64_t* hval;
+        uint64_t* hp;
+        uint32_t* head = level(m, r, T, hrow, hval, hp);
+        arow = buf_keep<uint32_t>(c, "astar.row", used + T, used);
+        aval = buf_keep<uint64_t>(c, "astar.val", used + T, used);
+        check(c, launch_entry_emit(T, head, hp, hrow, hval, used, arow, aval, s), "entry emit");
+        check(c, launch_entry_cols(m, ub, hp, used, aoff, alen, nullptr, s), "entry cols");
+        used += T;
+        products += T;
+        processed += r;
+        levels++;
+        check(c, hipMemsetAsync(d_n, 0, 8, s), "memset");
+        check(c, launch_release(ready[cur], r, (const uint64_t*)B.rowptr, B.col, indeg, ready[1 - cur], d_n, d_err, s),
+              "release");
+        r = readback(c, (const uint64_t*)d_n, 1)[0];
+        cur = 1 - cur;
+        if ((uint64_t)levels > J + 1) fail(c, MS_ERR_INTERNAL, "path counting did not terminate");
+    }
+    if (processed != J) fail(c, MS_ERR_INTERNAL, "the junction graph has a cycle");
+    // P columns, written as M21 (rows 2-saddles) in canonical order
+    MergeLaunch mp{nullptr, S2, (const uint64_t*)Dt.rowptr, Dt.col, Dt.val, (const uint64_t*)Bst.rowptr, Bst.col,
+                   Bst.val, aoff, alen, arow, aval, 0, 1, 1};
+    uint64_t T;
+    uint32_t* hrow;
+    uint64_t* hval;
+    uint64_t* hp;
+    uint32_t* head = level(mp, S2, T, hrow, hval, hp);
+    const uint64_t nP = T ? read_u64(c, hp + T) : 0;
+    ms_csr m21 = csr_buf(c, "m21", S2, S1, nP);
+    if (S2 == 0) check(c, hipMemsetAsync(m21.rowptr, 0, sizeof(int64_t), s), "memset");
+    check(c, launch_entry_emit(T, head, hp, hrow, hval, 0, m21.col, m21.val, s), "entry emit");
+    check(c, launch_entry_cols(mp, ub, hp, 0, nullptr, nullptr, (uint64_t*)m21.rowptr, s), "entry cols");
+    check_err_flag(c, d_err, "path counting");
+    out->m21 = m21;
+    transpose(c, out->m21, "m21t", out->m21t);
+    // exact nnz of A*: the sum of the column lengths
+    uint64_t* sum = buf<uint64_t>(c, "pe.asum", J + 1);
+    uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(J) + 1);
+    check(c, scan_excl_u32_to_u64(alen, sum, J, stmp, sum + J, s), "scan");
+    st.spgemm_iters = levels;
+    st.nnz_astar = J ? (int64_t)read_u64(c, sum + J) : 0;
+    st.products = (int64_t)(products + T);
+}
 }  // namespace
 
 void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t* crit, const int64_t cnt[4],
@@ -482,6 +574,10 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
     // ---- path counting --------------------------------------------------------
     bool done = false;
     if (c->path_schedule == MS_PATHS_READY) done = paths_ready(c, A, B, Bs, D, S1, S2, J, out, d_err);
+    if (c->path_schedule == MS_PATHS_ENTRY) {
+        paths_entry(c, A, B, Bs, D, S1, S2, J, out, d_err);
+        done = true;
+    }
     if (!done) paths_power(c, A, B, Bs, D, S1, S2, J, out);
     unsigned long long* d_sat = (unsigned long long*)buf<uint64_t>(c, "sat_count", 1);
     check(c, hipMemsetAsync(d_sat, 0, 8, s), "memset");

@@ -39,6 +39,19 @@ hipError_t launch_merge_classify(const MergeLaunch& m, uint64_t* ub, uint8_t* fl
 hipError_t launch_merge(const MergeLaunch& m, const uint8_t* flag, const uint32_t* qwave, const uint32_t* qblock,
                         const unsigned long long* qn, const uint64_t* off, uint64_t out_base, uint32_t* orow,
                         uint64_t* oval, uint32_t* cnt, uint64_t* col_off, uint32_t* col_len, hipStream_t s);
+// Entry-parallel merges (one thread per input entry): input counts per
+// column into ub; then, with off the exclusive scan of ub (n + 1 entries,
+// off[n] = T), the ranked run heads (head flags, rows, summed values at
+// their merged positions); then, with hp the exclusive scan of the head
+// flags (T + 1 entries), the compacted output at base + hp[p] and each
+// column's range (col_off/col_len by column id and/or a CSR row pointer).
+hipError_t launch_entry_ub(const MergeLaunch& m, uint64_t* ub, hipStream_t s);
+hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* hrow, uint64_t* hval,
+                             uint32_t* head, hipStream_t s);
+hipError_t launch_entry_emit(uint64_t T, const uint32_t* head, const uint64_t* hp, const uint32_t* hrow,
+                             const uint64_t* hval, uint64_t base, uint32_t* orow, uint64_t* oval, hipStream_t s);
+hipError_t launch_entry_cols(const MergeLaunch& m, const uint64_t* off, const uint64_t* hp, uint64_t base,
+                             uint64_t* col_off, uint32_t* col_len, uint64_t* rowptr, hipStream_t s);
 // Copies column i from src_off[i] to dst_off[i] (dst_off: n + 1 entries).
 hipError_t launch_compact(const uint64_t* src_off, const uint64_t* dst_off, uint64_t n, uint64_t total,
                           const uint32_t* srow, const uint64_t* sval, uint32_t* drow, uint64_t* dval, hipStream_t s);

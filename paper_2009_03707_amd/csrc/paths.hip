@@ -561,6 +561,106 @@ __global__ __launch_bounds__(BT) void k_release(const uint32_t* __restrict__ rea
     for (unsigned long long t = 0; t < m; t++) next[base + ex + t] = out[t];
 }
 
+// ---- entry-parallel merges ---------------------------------------------------
+// One thread per input entry of a level (the entries of all columns, column
+// by column, each column's lists back to back: base list, then predecessor
+// columns).  An entry's place in its merged column is its index in its own
+// list plus, for every other list of the column, the number of entries
+// below it there (ties ordered by list), found by binary search.  The first
+// entry of a run of equal rows (the "head": no earlier list holds the row)
+// also sums the run's scaled counts; a scan of the head flags then gives
+// every output row its final, gap-free position.
+
+__global__ __launch_bounds__(BT) void k_entry_ub(MergeArgs a, uint64_t* __restrict__ ub) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= a.n) return;
+    uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
+    uint32_t k = num_lists(a, c);
+    uint64_t u = a.brp[c + 1] - a.brp[c];
+    for (uint32_t s = 1; s < k; s++) u += a.alen[a.pcol[a.prp[c] + (s - 1)]];
+    ub[i] = u;
+}
+
+// off: exclusive scan of ub (n + 1 entries, off[n] = T)
+__global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* __restrict__ off, uint64_t T,
+                                                   uint32_t* __restrict__ hrow, uint64_t* __restrict__ hval,
+                                                   uint32_t* __restrict__ head) {
+    const uint64_t e = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (e >= T) return;
+    // the column holding entry e: the last i with off[i] <= e
+    uint64_t lo = 0, hi = a.n;
+    while (hi - lo > 1) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (off[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    const uint64_t i = lo;
+    const uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
+    const uint32_t k = num_lists(a, c);
+    uint64_t local = e - off[i];
+    uint32_t s = 0;
+    ListRef L = list_of(a, c, 0);
+    while (local >= L.len) {  // e < off[i + 1], so the walk stops at a list s < k
+        local -= L.len;
+        s++;
+        L = list_of(a, c, s);
+    }
+    const uint32_t x = L.row[local];
+    uint64_t sum = sat_mul(L.val[local], L.mul);
+    uint64_t rank = local;
+    bool is_head = true;
+    for (uint32_t t = 0; t < k; t++) {
+        if (t == s) continue;
+        const ListRef M = list_of(a, c, t);
+        const uint32_t lt = count_lt(M.row, (uint32_t)M.len, x);
+        const bool has = lt < M.len && M.row[lt] == x;
+        if (t < s) {
+            rank += lt + (has ? 1u : 0u);
+            is_head = is_head && !has;
+        } else {
+            rank += lt;
+            if (has) sum = sat_add(sum, sat_mul(M.val[lt], M.mul));
+        }
+    }
+    const uint64_t p = off[i] + rank;
+    head[p] = is_head ? 1u : 0u;
+    if (is_head) {
+        hrow[p] = x;
+        hval[p] = sum;
+    }
+}
+
+// hp: exclusive scan of head (T + 1 entries)
+__global__ __launch_bounds__(BT) void k_entry_emit(uint64_t T, const uint32_t* __restrict__ head,
+                                                   const uint64_t* __restrict__ hp, const uint32_t* __restrict__ hrow,
+                                                   const uint64_t* __restrict__ hval, uint64_t base,
+                                                   uint32_t* __restrict__ orow, uint64_t* __restrict__ oval) {
+    const uint64_t p = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (p >= T || !head[p]) return;
+    const uint64_t d = base + hp[p];
+    orow[d] = hrow[p];
+    oval[d] = hval[p];
+}
+
+// per column: its output range; optionally a CSR row pointer (n + 1 entries)
+__global__ __launch_bounds__(BT) void k_entry_cols(MergeArgs a, const uint64_t* __restrict__ off,
+                                                   const uint64_t* __restrict__ hp, uint64_t base,
+                                                   uint64_t* __restrict__ col_off, uint32_t* __restrict__ col_len,
+                                                   uint64_t* __restrict__ rowptr) {
+    const uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= a.n) return;
+    const uint64_t s0 = hp[off[i]], s1 = hp[off[i + 1]];
+    if (col_off) {
+        const uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
+        col_off[c] = base + s0;
+        col_len[c] = (uint32_t)(s1 - s0);
+    }
+    if (rowptr) {
+        rowptr[i] = s0;
+        if (i + 1 == a.n) rowptr[a.n] = s1;
+    }
+}
+
 MergeArgs to_args(const MergeLaunch& m) {
     MergeArgs a;
     a.cols = m.cols;
@@ -610,6 +710,35 @@ hipError_t launch_merge(const MergeLaunch& m, const uint8_t* flag, const uint32_
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_merge_block, dim3(BLOCK_GRID), dim3(BT), 0, s, a, qblock, qn, off, out_base, orow, oval, cnt,
                        col_off, col_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_entry_ub(const MergeLaunch& m, uint64_t* ub, hipStream_t s) {
+    if (m.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_entry_ub, dim3(grid_blocks(m.n, BT)), dim3(BT), 0, s, to_args(m), ub);
+    return hipGetLastError();
+}
+
+hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* hrow, uint64_t* hval,
+                             uint32_t* head, hipStream_t s) {
+    if (T == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_entry_rank, dim3(grid_blocks(T, BT)), dim3(BT), 0, s, to_args(m), off, T, hrow, hval, head);
+    return hipGetLastError();
+}
+
+hipError_t launch_entry_emit(uint64_t T, const uint32_t* head, const uint64_t* hp, const uint32_t* hrow,
+                             const uint64_t* hval, uint64_t base, uint32_t* orow, uint64_t* oval, hipStream_t s) {
+    if (T == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_entry_emit, dim3(grid_blocks(T, BT)), dim3(BT), 0, s, T, head, hp, hrow, hval, base, orow,
+                       oval);
+    return hipGetLastError();
+}
+
+hipError_t launch_entry_cols(const MergeLaunch& m, const uint64_t* off, const uint64_t* hp, uint64_t base,
+                             uint64_t* col_off, uint32_t* col_len, uint64_t* rowptr, hipStream_t s) {
+    if (m.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_entry_cols, dim3(grid_blocks(m.n, BT)), dim3(BT), 0, s, to_args(m), off, hp, base, col_off,
+                       col_len, rowptr);
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_err
             "ms_ctx_set_option", "ms_complex_batch", "ms_ctx_release"]
 
 MS_OPT_PATH_SCHEDULE, MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK, MS_OPT_GRADIENT_TILE = 1, 2, 3, 4
-MS_PATHS_READY, MS_PATHS_POWER = 0, 1
+MS_PATHS_READY, MS_PATHS_POWER, MS_PATHS_ENTRY = 0, 1, 2
 
 
 class MscError(RuntimeError):
@@ -159,7 +159,8 @@ class Context:
             raise MscError(st, f"{what}: {msg.decode() if msg else ''}")
 
     def set_path_schedule(self, schedule: int):
-        """MS_PATHS_READY (default) or MS_PATHS_POWER (the paper's iteration)."""
+        """MS_PATHS_READY (default), MS_PATHS_POWER (the paper's iteration) or
+        MS_PATHS_ENTRY (ready frontier with entry-parallel merges)."""
         self._raise(lib().ms_ctx_set_option(self._h, MS_OPT_PATH_SCHEDULE, int(schedule)), "ms_ctx_set_option")
 
     def release(self):

@@ -11,13 +11,14 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=["ready", "power"])
+@pytest.fixture(scope="module", params=["ready", "power", "entry"])
 def ctx(request):
     from paper_2009_03707_amd import msc
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c = msc.Context()
-    c.set_path_schedule(msc.MS_PATHS_READY if request.param == "ready" else msc.MS_PATHS_POWER)
+    c.set_path_schedule({"ready": msc.MS_PATHS_READY, "power": msc.MS_PATHS_POWER,
+                         "entry": msc.MS_PATHS_ENTRY}[request.param])
     yield c
     c.close()
 

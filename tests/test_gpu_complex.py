@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=["ready", "power", "ready-chunked"])
+@pytest.fixture(scope="module", params=["ready", "power", "ready-chunked", "entry"])
 def ctx(request):
     """Both path-counting schedules: the default ready frontier and the
     paper's power iteration; "ready-chunked" sends every column through the
@@ -21,7 +21,8 @@ def ctx(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c = msc.Context()
-    c.set_path_schedule(msc.MS_PATHS_POWER if request.param == "power" else msc.MS_PATHS_READY)
+    c.set_path_schedule({"power": msc.MS_PATHS_POWER, "entry": msc.MS_PATHS_ENTRY}.get(request.param,
+                                                                                      msc.MS_PATHS_READY))
     if request.param == "ready-chunked":
         c.set_option(msc.MS_OPT_MERGE_LIGHT, 0)
         c.set_option(msc.MS_OPT_MERGE_CHUNK, 3)

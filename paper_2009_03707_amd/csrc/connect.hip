@@ -20,6 +20,7 @@ int bit_width(uint64_t v);
 hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, uint32_t* rows, hipStream_t s);
 hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s);
 hipError_t launch_hist(const uint32_t* keys, uint64_t n, uint32_t* h, hipStream_t s);
+hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, uint64_t* rowptr, hipStream_t s);
 hipError_t launch_gather_t(const uint32_t* perm, const uint32_t* rows, const uint64_t* val, uint32_t* ocol,
                            uint64_t* oval, uint64_t n, hipStream_t s);
 hipError_t launch_make_keys(const uint32_t* row, const uint32_t* col, uint64_t n, int cb, uint64_t* keys,
@@ -95,11 +96,12 @@ uint64_t counts_to_rowptr(ms_ctx* c, const uint32_t* cnt, uint64_t n, uint64_t* 
 
 // Transpose of a CSR (stable radix sort by column; rows of the output come out
 // with ascending columns because input entries are in row-major order).
+// Transpose: a stable radix sort of the column ids (read in place, entry
+// index as payload), a gather of rows and values, and the row pointer of
+// the result from the boundaries between equal keys.
 void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out) {
     uint64_t nnz = (uint64_t)in.nnz;
     out = csr_buf(c, name, (uint64_t)in.ncols, (uint64_t)in.nrows, nnz);
-    uint32_t* h = buf<uint32_t>(c, "tr.hist", (uint64_t)in.ncols + 1);
-    check(c, hipMemsetAsync(h, 0, sizeof(uint32_t) * ((uint64_t)in.ncols + 1), c->stream), "memset");
     if (nnz == 0) {
         check(c, hipMemsetAsync(out.rowptr, 0, sizeof(int64_t) * ((uint64_t)in.ncols + 1), c->stream), "memset");
         return;
@@ -111,17 +113,13 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out) {
     uint32_t* vb = buf<uint32_t>(c, "tr.vb", nnz);
     uint64_t* tmp = buf<uint64_t>(c, "tr.tmp", radix_tmp_elems(nnz));
     check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, rows, c->stream), "expand rows");
-    check(c, hipMemcpyAsync(ka, in.col, sizeof(uint32_t) * nnz, hipMemcpyDeviceToDevice, c->stream), "copy");
-    check(c, launch_iota(va, nnz, c->stream), "iota");
-    check(c, launch_hist(ka, nnz, h, c->stream), "hist");
     bool in_b = false;
-    check(c, radix_sort_u32(ka, va, kb, vb, nnz, bit_width((uint64_t)in.ncols - 1), tmp, &in_b, c->stream), "sort");
+    check(c, radix_sort_u32_from(in.col, ka, va, kb, vb, nnz, bit_width((uint64_t)in.ncols - 1), tmp, &in_b, c->stream),
+          "sort");
+    const uint32_t* keys = in_b ? kb : ka;
     const uint32_t* perm = in_b ? vb : va;
     check(c, launch_gather_t(perm, rows, in.val, out.col, out.val, nnz, c->stream), "gather");
-    uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems((uint64_t)in.ncols) + 1);
-    check(c, scan_excl_u32_to_u64(h, (uint64_t*)out.rowptr, (uint64_t)in.ncols, stmp,
-                                  (uint64_t*)out.rowptr + in.ncols, c->stream),
-          "scan");
+    check(c, launch_key_bounds(keys, nnz, (uint64_t)in.ncols, (uint64_t*)out.rowptr, c->stream), "bounds");
 }
 
 // Sort a COO by (row, col) and merge repeats; result in buffer set `name`.
@@ -288,7 +286,7 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     unsigned long long* d_n = (unsigned long long*)buf<uint64_t>(c, "pr.counts", 3);
     uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(nmax) + 1);
     check(c, hipMemsetAsync(d_n, 0, 24, s), "memset");
-    check(c, launch_ready_init((const uint64_t*)Bt.rowptr, J, indeg, ready[0], d_n, s), "ready init");
+    check(c, launch_ready_init((const uint64_t*)Bt.rowptr, J, indeg, ready[0], d_n, nullptr, nullptr, s), "ready init");
     uint64_t r = J ? readback(c, (const uint64_t*)d_n, 1)[0] : 0;
     uint64_t used = 0, processed = 0;
     int64_t levels = 0;
@@ -311,7 +309,8 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
         processed += r;
         levels++;
         check(c, hipMemsetAsync(d_n, 0, 8, s), "memset");
-        check(c, launch_release(ready[cur], r, (const uint64_t*)B.rowptr, B.col, indeg, ready[1 - cur], d_n, d_err, s),
+        check(c, launch_release(ready[cur], r, (const uint64_t*)B.rowptr, B.col, indeg, ready[1 - cur], d_n, d_err,
+                                nullptr, nullptr, nullptr, nullptr, nullptr, s),
               "release");
         r = readback(c, (const uint64_t*)d_n, 1)[0];
         cur = 1 - cur;
@@ -366,51 +365,70 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     const uint64_t nmax = (J > S2 ? J : S2) + 1;
     uint32_t* indeg = buf<uint32_t>(c, "pr.indeg", J);
     uint32_t* ready[2] = {buf<uint32_t>(c, "pr.ready0", J), buf<uint32_t>(c, "pr.ready1", J)};
+    // input counts of the ready columns, in ready order (scanned in place)
+    uint64_t* ubs[2] = {buf<uint64_t>(c, "pr.ub0", nmax + 1), buf<uint64_t>(c, "pr.ub1", nmax + 1)};
     uint64_t* aoff = buf<uint64_t>(c, "pr.aoff", J);
     uint32_t* alen = buf<uint32_t>(c, "pr.alen", J);
-    uint64_t* ub = buf<uint64_t>(c, "pr.ub", nmax + 1);
     unsigned long long* d_n = (unsigned long long*)buf<uint64_t>(c, "pr.counts", 3);
     check(c, hipMemsetAsync(d_n, 0, 24, s), "memset");
-    check(c, launch_ready_init((const uint64_t*)Bt.rowptr, J, indeg, ready[0], d_n, s), "ready init");
+    check(c, launch_ready_init((const uint64_t*)Bt.rowptr, J, indeg, ready[0], d_n, (const uint64_t*)At.rowptr,
+                               ubs[0], s),
+          "ready init");
     uint64_t r = J ? readback(c, (const uint64_t*)d_n, 1)[0] : 0;
     uint64_t used = 0, processed = 0, products = 0;
     int64_t levels = 0;
     uint32_t* arow = buf_keep<uint32_t>(c, "astar.row", 1, 0);
     uint64_t* aval = buf_keep<uint64_t>(c, "astar.val", 1, 0);
     int cur = 0;
-    // per-level scratch: ranked heads and their scan
-    auto level = [&](const MergeLaunch& m, uint64_t n, uint64_t& T, uint32_t*& hrow, uint64_t*& hval, uint64_t*& hp) {
+    ms_csr m21{};
+    // one level: scan the input counts, rank every input entry, then scan the
+    // run heads and write them at base (into the A* storage or M21)
+    auto level = [&](MergeLaunch& m, uint64_t* ub, uint64_t n, bool to_astar, uint32_t*& orow, uint64_t*& oval,
+                     uint64_t& base, uint64_t*& hp) -> uint64_t {
         uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(n) + 1);
-        check(c, launch_entry_ub(m, ub, s), "entry ub");
         check(c, scan_excl_u64(ub, ub, n, stmp, ub + n, s), "scan");
-        T = n ? read_u64(c, ub + n) : 0;
-        hrow = buf<uint32_t>(c, "pe.hrow", T);
-        hval = buf<uint64_t>(c, "pe.hval", T);
+        const uint64_t T = n ? read_u64(c, ub + n) : 0;
+        if (to_astar) {  // room for this level's columns at their upper bound
+            arow = buf_keep<uint32_t>(c, "astar.row", used + T, used);
+            aval = buf_keep<uint64_t>(c, "astar.val", used + T, used);
+            m.arow = arow;
+            m.aval = aval;
+            orow = arow;
+            oval = aval;
+            base = used;
+        } else {
+            base = 0;
+        }
+        uint32_t* hrow = buf<uint32_t>(c, "pe.hrow", T);
+        uint64_t* hval = buf<uint64_t>(c, "pe.hval", T);
         uint32_t* head = buf<uint32_t>(c, "pe.head", T);
         hp = buf<uint64_t>(c, "pe.hp", T + 1);
         check(c, launch_entry_rank(m, ub, T, hrow, hval, head, s), "entry rank");
-        uint64_t* stmp2 = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(T) + 1);
-        check(c, scan_excl_u32_to_u64(head, hp, T, stmp2, hp + T, s), "scan");
-        return head;
+        if (!to_astar) {  // M21 sized for the upper bound; nnz is set once the heads are counted
+            m21 = csr_buf(c, "m21", S2, S1, T);
+            orow = m21.col;
+            oval = m21.val;
+        }
+        uint64_t* htmp = buf<uint64_t>(c, "pe.htmp", head_scan_tmp_elems(T));
+        check(c, launch_head_scan_emit(head, T, hrow, hval, base, orow, oval, hp, htmp, s), "head scan");
+        return T;
     };
     while (r > 0) {
         MergeLaunch m{ready[cur], r, (const uint64_t*)At.rowptr, At.col, At.val, (const uint64_t*)Bt.rowptr, Bt.col,
                       Bt.val, aoff, alen, arow, aval, 0, 1, 1};
-        uint64_t T;
-        uint32_t* hrow;
-        uint64_t* hval;
+        uint32_t* orow;
+        uint64_t* oval;
+        uint64_t base;
         uint64_t* hp;
-        uint32_t* head = level(m, r, T, hrow, hval, hp);
-        arow = buf_keep<uint32_t>(c, "astar.row", used + T, used);
-        aval = buf_keep<uint64_t>(c, "astar.val", used + T, used);
-        check(c, launch_entry_emit(T, head, hp, hrow, hval, used, arow, aval, s), "entry emit");
-        check(c, launch_entry_cols(m, ub, hp, used, aoff, alen, nullptr, s), "entry cols");
+        const uint64_t T = level(m, ubs[cur], r, true, orow, oval, base, hp);
+        check(c, launch_entry_cols(m, ubs[cur], hp, base, aoff, alen, nullptr, s), "entry cols");
         used += T;
         products += T;
         processed += r;
         levels++;
         check(c, hipMemsetAsync(d_n, 0, 8, s), "memset");
-        check(c, launch_release(ready[cur], r, (const uint64_t*)B.rowptr, B.col, indeg, ready[1 - cur], d_n, d_err, s),
+        check(c, launch_release(ready[cur], r, (const uint64_t*)B.rowptr, B.col, indeg, ready[1 - cur], d_n, d_err,
+                                (const uint64_t*)At.rowptr, (const uint64_t*)Bt.rowptr, Bt.col, alen, ubs[1 - cur], s),
               "release");
         r = readback(c, (const uint64_t*)d_n, 1)[0];
         cur = 1 - cur;
@@ -420,16 +438,16 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     // P columns, written as M21 (rows 2-saddles) in canonical order
     MergeLaunch mp{nullptr, S2, (const uint64_t*)Dt.rowptr, Dt.col, Dt.val, (const uint64_t*)Bst.rowptr, Bst.col,
                    Bst.val, aoff, alen, arow, aval, 0, 1, 1};
-    uint64_t T;
-    uint32_t* hrow;
-    uint64_t* hval;
+    uint64_t* ubp = ubs[0];
+    check(c, launch_entry_ub(mp, ubp, s), "entry ub");
+    uint32_t* prow;
+    uint64_t* pval;
+    uint64_t pbase;
     uint64_t* hp;
-    uint32_t* head = level(mp, S2, T, hrow, hval, hp);
-    const uint64_t nP = T ? read_u64(c, hp + T) : 0;
-    ms_csr m21 = csr_buf(c, "m21", S2, S1, nP);
+    const uint64_t T = level(mp, ubp, S2, false, prow, pval, pbase, hp);
+    m21.nnz = (int64_t)read_u64(c, hp + T);
     if (S2 == 0) check(c, hipMemsetAsync(m21.rowptr, 0, sizeof(int64_t), s), "memset");
-    check(c, launch_entry_emit(T, head, hp, hrow, hval, 0, m21.col, m21.val, s), "entry emit");
-    check(c, launch_entry_cols(mp, ub, hp, 0, nullptr, nullptr, (uint64_t*)m21.rowptr, s), "entry cols");
+    check(c, launch_entry_cols(mp, ubp, hp, 0, nullptr, nullptr, (uint64_t*)m21.rowptr, s), "entry cols");
     check_err_flag(c, d_err, "path counting");
     out->m21 = m21;
     transpose(c, out->m21, "m21t", out->m21t);

@@ -55,9 +55,21 @@ hipError_t launch_entry_cols(const MergeLaunch& m, const uint64_t* off, const ui
 // Copies column i from src_off[i] to dst_off[i] (dst_off: n + 1 entries).
 hipError_t launch_compact(const uint64_t* src_off, const uint64_t* dst_off, uint64_t n, uint64_t total,
                           const uint32_t* srow, const uint64_t* sval, uint32_t* drow, uint64_t* dval, hipStream_t s);
+// base_rp / ub optional: the input counts of the first frontier's columns
 hipError_t launch_ready_init(const uint64_t* prp, uint64_t J, uint32_t* indeg, uint32_t* ready,
-                             unsigned long long* nready, hipStream_t s);
+                             unsigned long long* nready, const uint64_t* base_rp, uint64_t* ub, hipStream_t s);
+// ub_next optional (with base_rp, prp, pcol, alen): the input counts of
+// the released columns, in the order of `next`
 hipError_t launch_release(const uint32_t* ready, uint64_t n, const uint64_t* brp, const uint32_t* bcol,
-                          uint32_t* indeg, uint32_t* next, unsigned long long* nnext, int* err, hipStream_t s);
+                          uint32_t* indeg, uint32_t* next, unsigned long long* nnext, int* err, const uint64_t* base_rp,
+                          const uint64_t* prp, const uint32_t* pcol, const uint32_t* alen, uint64_t* ub_next,
+                          hipStream_t s);
+// Exclusive scan of the head flags into hp (T + 1 entries, hp[T] = number of
+// heads) with each head's row and count written at base + hp[p]; tmp needs
+// head_scan_tmp_elems(T) entries.
+size_t head_scan_tmp_elems(uint64_t T);
+hipError_t launch_head_scan_emit(const uint32_t* head, uint64_t T, const uint32_t* hrow, const uint64_t* hval,
+                                 uint64_t base, uint32_t* orow, uint64_t* oval, uint64_t* hp, uint64_t* tmp,
+                                 hipStream_t s);
 
 }  // namespace msc

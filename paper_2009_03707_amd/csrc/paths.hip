@@ -509,11 +509,22 @@ __global__ __launch_bounds__(BT) void k_compact(const uint64_t* __restrict__ src
     dval[e] = sval[src];
 }
 
+// input entries of column c: its base list plus its predecessors' columns
+__device__ __forceinline__ uint64_t column_inputs(const uint64_t* __restrict__ base_rp,
+                                                  const uint64_t* __restrict__ prp, const uint32_t* __restrict__ pcol,
+                                                  const uint32_t* __restrict__ alen, uint32_t c) {
+    uint64_t u = base_rp[c + 1] - base_rp[c];
+    for (uint64_t q = prp[c]; q < prp[c + 1]; q++) u += alen[pcol[q]];
+    return u;
+}
+
 // in-degree of every junction in the minor; junctions without predecessors
-// form the first ready frontier
+// form the first ready frontier (with their input counts in ub when base_rp
+// is given)
 __global__ __launch_bounds__(BT) void k_ready_init(const uint64_t* __restrict__ prp, uint64_t J,
                                                    uint32_t* __restrict__ indeg, uint32_t* __restrict__ ready,
-                                                   unsigned long long* __restrict__ nready) {
+                                                   unsigned long long* __restrict__ nready,
+                                                   const uint64_t* __restrict__ base_rp, uint64_t* __restrict__ ub) {
     __shared__ unsigned long long sc[BT / WAVE + 1];
     __shared__ unsigned long long base;
     uint64_t j = (uint64_t)blockIdx.x * BT + threadIdx.x;
@@ -527,16 +538,23 @@ __global__ __launch_bounds__(BT) void k_ready_init(const uint64_t* __restrict__ 
     unsigned long long ex = block_excl_scan<unsigned long long, BT>(is0, sc, tot);
     if (threadIdx.x == 0) base = tot ? atomicAdd(nready, tot) : 0;
     __syncthreads();
-    if (is0) ready[base + ex] = (uint32_t)j;
+    if (is0) {
+        ready[base + ex] = (uint32_t)j;
+        if (ub) ub[base + ex] = base_rp[j + 1] - base_rp[j];
+    }
 }
 
 // after the columns of `ready` are complete: release their successors (a
 // junction is an edge paired with a quad, so it has at most three minor
-// successors)
+// successors); with ub_next, also the input counts of the released columns
+// (every predecessor column is complete by then)
 __global__ __launch_bounds__(BT) void k_release(const uint32_t* __restrict__ ready, uint64_t n,
                                                 const uint64_t* __restrict__ brp, const uint32_t* __restrict__ bcol,
                                                 uint32_t* __restrict__ indeg, uint32_t* __restrict__ next,
-                                                unsigned long long* __restrict__ nnext, int* __restrict__ err) {
+                                                unsigned long long* __restrict__ nnext, int* __restrict__ err,
+                                                const uint64_t* __restrict__ base_rp, const uint64_t* __restrict__ prp,
+                                                const uint32_t* __restrict__ pcol, const uint32_t* __restrict__ alen,
+                                                uint64_t* __restrict__ ub_next) {
     __shared__ unsigned long long sc[BT / WAVE + 1];
     __shared__ unsigned long long base;
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
@@ -558,7 +576,10 @@ __global__ __launch_bounds__(BT) void k_release(const uint32_t* __restrict__ rea
     unsigned long long ex = block_excl_scan<unsigned long long, BT>(m, sc, tot);
     if (threadIdx.x == 0) base = tot ? atomicAdd(nnext, tot) : 0;
     __syncthreads();
-    for (unsigned long long t = 0; t < m; t++) next[base + ex + t] = out[t];
+    for (unsigned long long t = 0; t < m; t++) {
+        next[base + ex + t] = out[t];
+        if (ub_next) ub_next[base + ex + t] = column_inputs(base_rp, prp, pcol, alen, out[t]);
+    }
 }
 
 // ---- entry-parallel merges ---------------------------------------------------
@@ -581,52 +602,220 @@ __global__ __launch_bounds__(BT) void k_entry_ub(MergeArgs a, uint64_t* __restri
     ub[i] = u;
 }
 
-// off: exclusive scan of ub (n + 1 entries, off[n] = T)
+constexpr int EPT = 4;           // entries per thread of a rank block
+constexpr int EPB = BT * EPT;     // entries per rank block
+constexpr int CW = 512;           // columns per LDS window of a rank block
+constexpr int LCAP = 768;         // list descriptors per LDS window
+
+// One rank block handles EPB consecutive input entries (the level's inputs
+// are column by column, each column's lists back to back).  Their columns
+// form a contiguous run; its offsets and list descriptors are staged in LDS
+// once per block.  Phase 1 maps every entry to (column, list, index) and
+// stages its row in LDS; phase 2 ranks it: for every other list of the
+// column, the count of rows below it there -- searched in LDS when that
+// list lies inside the block's entry range, else in global memory.  The
+// head of a run of equal rows (no earlier list holds the row) sums the
+// run's scaled counts.  Entries of columns beyond the staged window read
+// their metadata from global memory (same result).
+// off: exclusive scan of ub (n + 1 entries, off[n] = T).
 __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* __restrict__ off, uint64_t T,
                                                    uint32_t* __restrict__ hrow, uint64_t* __restrict__ hval,
                                                    uint32_t* __restrict__ head) {
-    const uint64_t e = (uint64_t)blockIdx.x * BT + threadIdx.x;
-    if (e >= T) return;
-    // the column holding entry e: the last i with off[i] <= e
-    uint64_t lo = 0, hi = a.n;
-    while (hi - lo > 1) {
-        uint64_t mid = (lo + hi) >> 1;
-        if (off[mid] <= e) lo = mid;
-        else hi = mid;
-    }
-    const uint64_t i = lo;
-    const uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
-    const uint32_t k = num_lists(a, c);
-    uint64_t local = e - off[i];
-    uint32_t s = 0;
-    ListRef L = list_of(a, c, 0);
-    while (local >= L.len) {  // e < off[i + 1], so the walk stops at a list s < k
-        local -= L.len;
-        s++;
-        L = list_of(a, c, s);
-    }
-    const uint32_t x = L.row[local];
-    uint64_t sum = sat_mul(L.val[local], L.mul);
-    uint64_t rank = local;
-    bool is_head = true;
-    for (uint32_t t = 0; t < k; t++) {
-        if (t == s) continue;
-        const ListRef M = list_of(a, c, t);
-        const uint32_t lt = count_lt(M.row, (uint32_t)M.len, x);
-        const bool has = lt < M.len && M.row[lt] == x;
-        if (t < s) {
-            rank += lt + (has ? 1u : 0u);
-            is_head = is_head && !has;
-        } else {
-            rank += lt;
-            if (has) sum = sat_add(sum, sat_mul(M.val[lt], M.mul));
+    __shared__ uint64_t s_off[CW + 1];
+    __shared__ uint32_t s_lbase[CW + 1];
+    __shared__ const uint32_t* s_row[LCAP];
+    __shared__ const uint64_t* s_val[LCAP];
+    __shared__ uint32_t s_len[LCAP];
+    __shared__ uint64_t s_mul[LCAP];
+    __shared__ uint32_t s_x[EPB];
+    __shared__ uint32_t s_sc[BT / WAVE + 1];
+    __shared__ uint64_t s_i0;
+    __shared__ uint32_t s_nused;
+    const uint64_t e0 = (uint64_t)blockIdx.x * EPB;
+    const uint64_t e_end = e0 + EPB < T ? e0 + EPB : T;
+    if (threadIdx.x == 0) {  // the column of the block's first entry: the last i with off[i] <= e0
+        uint64_t lo = 0, hi = a.n;
+        while (hi - lo > 1) {
+            uint64_t mid = (lo + hi) >> 1;
+            if (off[mid] <= e0) lo = mid;
+            else hi = mid;
         }
+        s_i0 = lo;
     }
-    const uint64_t p = off[i] + rank;
-    head[p] = is_head ? 1u : 0u;
-    if (is_head) {
-        hrow[p] = x;
-        hval[p] = sum;
+    __syncthreads();
+    const uint64_t i0 = s_i0;
+    const uint32_t wn = (uint32_t)((a.n - i0) < (uint64_t)CW ? (a.n - i0) : (uint64_t)CW);  // >= 1
+    for (uint32_t t = threadIdx.x; t <= wn; t += BT) s_off[t] = off[i0 + t];
+    __syncthreads();
+    if (threadIdx.x == 0) {  // window columns that hold entries of this block
+        uint32_t lo = 0, hi = wn;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= e_end - 1) lo = mid;
+            else hi = mid;
+        }
+        s_nused = lo + 1;
+    }
+    __syncthreads();
+    const uint32_t nused = s_nused;
+    // list counts of the used columns (CW / BT per thread), their scan, the descriptors
+    uint32_t kt[CW / BT], ct[CW / BT], ksum = 0;
+#pragma unroll
+    for (int r = 0; r < CW / BT; r++) {
+        const uint32_t t = threadIdx.x * (CW / BT) + r;
+        kt[r] = 0;
+        ct[r] = 0;
+        if (t < nused) {
+            ct[r] = a.cols ? a.cols[i0 + t] : (uint32_t)(i0 + t);
+            kt[r] = num_lists(a, ct[r]);
+        }
+        ksum += kt[r];
+    }
+    uint32_t nl;
+    uint32_t lb = block_excl_scan<uint32_t, BT>(ksum, s_sc, nl);
+#pragma unroll
+    for (int r = 0; r < CW / BT; r++) {
+        const uint32_t t = threadIdx.x * (CW / BT) + r;
+        if (t < nused) {
+            s_lbase[t] = lb;
+            for (uint32_t q = 0; q < kt[r] && lb + q < (uint32_t)LCAP; q++) {
+                const ListRef L = list_of(a, ct[r], q);
+                s_row[lb + q] = L.row;
+                s_val[lb + q] = L.val;
+                s_len[lb + q] = (uint32_t)L.len;
+                s_mul[lb + q] = L.mul;
+            }
+        }
+        lb += kt[r];
+    }
+    if (threadIdx.x == 0) s_lbase[nused] = nl;
+    __syncthreads();
+
+    // phase 1: map entries, stage rows
+    uint32_t e_col[EPT], e_list[EPT], e_loc[EPT], x[EPT];
+    bool e_win[EPT];
+    uint64_t e_glo[EPT];
+#pragma unroll
+    for (int r = 0; r < EPT; r++) {
+        const uint32_t j = (uint32_t)r * BT + threadIdx.x;
+        const uint64_t e = e0 + j;
+        e_win[r] = false;
+        e_glo[r] = 0;
+        e_col[r] = 0;
+        e_list[r] = 0;
+        e_loc[r] = 0;
+        x[r] = 0;
+        if (e >= e_end) continue;
+        uint32_t lo = 0, hi = nused;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (s_off[mid] <= e) lo = mid;
+            else hi = mid;
+        }
+        if (e < s_off[nused] && s_lbase[lo + 1] <= (uint32_t)LCAP) {
+            e_win[r] = true;
+            e_col[r] = lo;
+            const uint32_t b = s_lbase[lo];
+            uint64_t local = e - s_off[lo];
+            uint32_t q = 0;
+            while (local >= s_len[b + q]) {
+                local -= s_len[b + q];
+                q++;
+            }
+            e_list[r] = q;
+            e_loc[r] = (uint32_t)local;
+            x[r] = s_row[b + q][local];
+        } else {
+            uint64_t glo = i0 + lo, ghi = a.n;  // last i with off[i] <= e
+            while (ghi - glo > 1) {
+                uint64_t mid = (glo + ghi) >> 1;
+                if (off[mid] <= e) glo = mid;
+                else ghi = mid;
+            }
+            e_glo[r] = glo;
+            const uint32_t c = a.cols ? a.cols[glo] : (uint32_t)glo;
+            uint64_t local = e - off[glo];
+            uint32_t q = 0;
+            ListRef L = list_of(a, c, 0);
+            while (local >= L.len) {
+                local -= L.len;
+                q++;
+                L = list_of(a, c, q);
+            }
+            e_list[r] = q;
+            e_loc[r] = (uint32_t)local;
+            x[r] = L.row[local];
+        }
+        s_x[j] = x[r];
+    }
+    __syncthreads();
+
+    // phase 2: rank
+#pragma unroll
+    for (int r = 0; r < EPT; r++) {
+        const uint64_t e = e0 + (uint32_t)r * BT + threadIdx.x;
+        if (e >= e_end) continue;
+        const uint32_t xs = x[r], s = e_list[r];
+        uint64_t rank = e_loc[r];
+        bool is_head = true;
+        uint64_t sum = 0;
+        uint64_t start;
+        if (e_win[r]) {
+            const uint32_t lo = e_col[r], b = s_lbase[lo], k = s_lbase[lo + 1] - b;
+            start = s_off[lo];
+            sum = sat_mul(s_val[b + s][e_loc[r]], s_mul[b + s]);
+            uint64_t lstart = start;  // first entry of list t
+            for (uint32_t t = 0; t < k; t++) {
+                const uint32_t l = s_len[b + t];
+                if (t != s) {
+                    uint32_t lt;
+                    bool has;
+                    if (lstart >= e0 && lstart + l <= e_end) {  // list t is staged
+                        const uint32_t* rt = s_x + (lstart - e0);
+                        lt = count_lt(rt, l, xs);
+                        has = lt < l && rt[lt] == xs;
+                    } else {
+                        const uint32_t* rt = s_row[b + t];
+                        lt = count_lt(rt, l, xs);
+                        has = lt < l && rt[lt] == xs;
+                    }
+                    if (t < s) {
+                        rank += lt + (has ? 1u : 0u);
+                        is_head = is_head && !has;
+                    } else {
+                        rank += lt;
+                        if (has) sum = sat_add(sum, sat_mul(s_val[b + t][lt], s_mul[b + t]));
+                    }
+                }
+                lstart += l;
+            }
+        } else {
+            const uint64_t glo = e_glo[r];
+            const uint32_t c = a.cols ? a.cols[glo] : (uint32_t)glo;
+            const uint32_t k = num_lists(a, c);
+            start = off[glo];
+            const ListRef L = list_of(a, c, s);
+            sum = sat_mul(L.val[e_loc[r]], L.mul);
+            for (uint32_t t = 0; t < k; t++) {
+                if (t == s) continue;
+                const ListRef M = list_of(a, c, t);
+                const uint32_t lt = count_lt(M.row, (uint32_t)M.len, xs);
+                const bool has = lt < M.len && M.row[lt] == xs;
+                if (t < s) {
+                    rank += lt + (has ? 1u : 0u);
+                    is_head = is_head && !has;
+                } else {
+                    rank += lt;
+                    if (has) sum = sat_add(sum, sat_mul(M.val[lt], M.mul));
+                }
+            }
+        }
+        const uint64_t p = start + rank;
+        head[p] = is_head ? 1u : 0u;
+        if (is_head) {
+            hrow[p] = xs;
+            hval[p] = sum;
+        }
     }
 }
 
@@ -640,6 +829,72 @@ __global__ __launch_bounds__(BT) void k_entry_emit(uint64_t T, const uint32_t* _
     const uint64_t d = base + hp[p];
     orow[d] = hrow[p];
     oval[d] = hval[p];
+}
+
+// Run heads per tile of the head flags, then (with the tile offsets
+// scanned) the exclusive prefix of every position into hp and each head's
+// row and count written at base + hp[p].  A tile is 2048 positions; wave w
+// of its workgroup covers positions [512 w, 512 w + 512) in 8 rounds of 64
+// consecutive positions, so every access is coalesced and the prefix of a
+// 0/1 flag inside a round is a popcount of the round's ballot.
+constexpr int HT_R = 8;                   // rounds per wave
+constexpr int HT_WAVE = HT_R * WAVE;      // positions per wave
+constexpr int HT_TILE = (BT / WAVE) * HT_WAVE;
+
+__global__ __launch_bounds__(BT) void k_head_tiles(const uint32_t* __restrict__ head, uint64_t T,
+                                                   uint64_t* __restrict__ part) {
+    __shared__ uint32_t wsum[BT / WAVE];
+    const int lane = lane_id(), w = (int)threadIdx.x / WAVE;
+    const uint64_t b0 = (uint64_t)blockIdx.x * HT_TILE + (uint64_t)w * HT_WAVE;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < HT_R; r++) {
+        const uint64_t j = b0 + (uint64_t)r * WAVE + lane;
+        cnt += (uint32_t)__popcll(__ballot(j < T && head[j] != 0u));
+    }
+    if (lane == 0) wsum[w] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t t = 0;
+        for (int q = 0; q < BT / WAVE; q++) t += wsum[q];
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(BT) void k_head_emit(const uint32_t* __restrict__ head, uint64_t T,
+                                                  const uint64_t* __restrict__ part,
+                                                  const uint32_t* __restrict__ hrow, const uint64_t* __restrict__ hval,
+                                                  uint64_t base, uint32_t* __restrict__ orow,
+                                                  uint64_t* __restrict__ oval, uint64_t* __restrict__ hp) {
+    __shared__ uint32_t wsum[BT / WAVE];
+    const int lane = lane_id(), w = (int)threadIdx.x / WAVE;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const uint64_t b0 = (uint64_t)blockIdx.x * HT_TILE + (uint64_t)w * HT_WAVE;
+    uint64_t mask[HT_R];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < HT_R; r++) {
+        const uint64_t j = b0 + (uint64_t)r * WAVE + lane;
+        mask[r] = __ballot(j < T && head[j] != 0u);
+        cnt += (uint32_t)__popcll(mask[r]);
+    }
+    if (lane == 0) wsum[w] = cnt;
+    __syncthreads();
+    uint64_t ex = part[blockIdx.x];
+    for (int q = 0; q < w; q++) ex += wsum[q];
+#pragma unroll
+    for (int r = 0; r < HT_R; r++) {
+        const uint64_t j = b0 + (uint64_t)r * WAVE + lane;
+        const uint64_t p = ex + (uint64_t)__popcll(mask[r] & lt);
+        if (j < T) {
+            hp[j] = p;
+            if ((mask[r] >> lane) & 1ull) {
+                orow[base + p] = hrow[j];
+                oval[base + p] = hval[j];
+            }
+        }
+        ex += (uint64_t)__popcll(mask[r]);
+    }
 }
 
 // per column: its output range; optionally a CSR row pointer (n + 1 entries)
@@ -722,7 +977,7 @@ hipError_t launch_entry_ub(const MergeLaunch& m, uint64_t* ub, hipStream_t s) {
 hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* hrow, uint64_t* hval,
                              uint32_t* head, hipStream_t s) {
     if (T == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_entry_rank, dim3(grid_blocks(T, BT)), dim3(BT), 0, s, to_args(m), off, T, hrow, hval, head);
+    hipLaunchKernelGGL(k_entry_rank, dim3(grid_blocks(T, EPB)), dim3(BT), 0, s, to_args(m), off, T, hrow, hval, head);
     return hipGetLastError();
 }
 
@@ -731,6 +986,24 @@ hipError_t launch_entry_emit(uint64_t T, const uint32_t* head, const uint64_t* h
     if (T == 0) return hipSuccess;
     hipLaunchKernelGGL(k_entry_emit, dim3(grid_blocks(T, BT)), dim3(BT), 0, s, T, head, hp, hrow, hval, base, orow,
                        oval);
+    return hipGetLastError();
+}
+
+size_t head_scan_tmp_elems(uint64_t T) { return (T + HT_TILE - 1) / HT_TILE + 1 + scan_tmp_elems((T + HT_TILE - 1) / HT_TILE + 1); }
+
+hipError_t launch_head_scan_emit(const uint32_t* head, uint64_t T, const uint32_t* hrow, const uint64_t* hval,
+                                 uint64_t base, uint32_t* orow, uint64_t* oval, uint64_t* hp, uint64_t* tmp,
+                                 hipStream_t s) {
+    if (T == 0) return hipMemsetAsync(hp, 0, sizeof(uint64_t), s);
+    const uint64_t nt = (T + HT_TILE - 1) / HT_TILE;
+    uint64_t* part = tmp;
+    hipLaunchKernelGGL(k_head_tiles, dim3((unsigned)nt), dim3(BT), 0, s, head, T, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_excl_u64(part, part, nt, tmp + nt + 1, hp + T, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_head_emit, dim3((unsigned)nt), dim3(BT), 0, s, head, T, (const uint64_t*)part, hrow, hval,
+                       base, orow, oval, hp);
     return hipGetLastError();
 }
 
@@ -751,17 +1024,20 @@ hipError_t launch_compact(const uint64_t* src_off, const uint64_t* dst_off, uint
 }
 
 hipError_t launch_ready_init(const uint64_t* prp, uint64_t J, uint32_t* indeg, uint32_t* ready,
-                             unsigned long long* nready, hipStream_t s) {
+                             unsigned long long* nready, const uint64_t* base_rp, uint64_t* ub, hipStream_t s) {
     if (J == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ready_init, dim3(grid_blocks(J, BT)), dim3(BT), 0, s, prp, J, indeg, ready, nready);
+    hipLaunchKernelGGL(k_ready_init, dim3(grid_blocks(J, BT)), dim3(BT), 0, s, prp, J, indeg, ready, nready, base_rp,
+                       ub);
     return hipGetLastError();
 }
 
 hipError_t launch_release(const uint32_t* ready, uint64_t n, const uint64_t* brp, const uint32_t* bcol,
-                          uint32_t* indeg, uint32_t* next, unsigned long long* nnext, int* err, hipStream_t s) {
+                          uint32_t* indeg, uint32_t* next, unsigned long long* nnext, int* err, const uint64_t* base_rp,
+                          const uint64_t* prp, const uint32_t* pcol, const uint32_t* alen, uint64_t* ub_next,
+                          hipStream_t s) {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_release, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, ready, n, brp, bcol, indeg, next, nnext,
-                       err);
+                       err, base_rp, prp, pcol, alen, ub_next);
     return hipGetLastError();
 }
 

@@ -65,5 +65,10 @@ hipError_t radix_sort_u64(uint64_t* keys_a, uint32_t* vals_a, uint64_t* keys_b, 
                           int bits, uint64_t* tmp, bool* result_in_b, hipStream_t s);
 hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, uint32_t* vals_b, uint64_t n,
                           int bits, uint64_t* tmp, bool* result_in_b, hipStream_t s);
+// Same, reading the keys from `keys` (left intact) with the entry index as
+// payload; the result lands in (a) or (b).
+hipError_t radix_sort_u32_from(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,
+                               uint32_t* vals_b, uint64_t n, int bits, uint64_t* tmp, bool* result_in_b,
+                               hipStream_t s);
 
 }  // namespace msc

@@ -122,7 +122,7 @@ __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, 
         const bool valid = j < n;
         const K key = valid ? keys[j] : (K)0;
         kr[r] = key;
-        vr[r] = valid ? vals[j] : 0u;
+        vr[r] = valid ? (vals ? vals[j] : (uint32_t)j) : 0u;
         const uint32_t d = (uint32_t)(key >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -165,16 +165,25 @@ __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, 
     }
 }
 
+// Stable LSD sort.  Pass 0 reads (keys0, vals0) -- vals0 null means the
+// payload is the entry index -- and the passes then alternate between the
+// (ka, va) and (kb, vb) buffers; *in_b tells where the result is.
 template <typename K>
-hipError_t radix_impl(K* ka, uint32_t* va, K* kb, uint32_t* vb, uint64_t n, int bits, uint64_t* tmp, bool* in_b,
-                      hipStream_t s) {
+hipError_t radix_impl(const K* keys0, const uint32_t* vals0, K* ka, uint32_t* va, K* kb, uint32_t* vb, uint64_t n,
+                      int bits, uint64_t* tmp, bool* in_b, hipStream_t s) {
     *in_b = false;
-    if (n <= 1 || bits <= 0) return hipSuccess;
+    if (n == 0) return hipSuccess;
     uint64_t nblk = (n + RTILE - 1) / RTILE;
     uint64_t* hist = tmp;
     uint64_t* stmp = tmp + 256 * nblk;
-    K* src_k = ka; uint32_t* src_v = va; K* dst_k = kb; uint32_t* dst_v = vb;
-    for (int sh = 0; sh < bits; sh += 8) {
+    const K* src_k = keys0;
+    const uint32_t* src_v = vals0;
+    K* dst_k = ka;
+    uint32_t* dst_v = va;
+    bool dst_is_b = false;
+    const int passes = bits <= 0 ? 1 : (bits + 7) / 8;  // at least one pass: the result always lands in a buffer
+    for (int p = 0; p < passes; p++) {
+        const int sh = 8 * p;
         hipLaunchKernelGGL(radix_hist<K>, dim3((unsigned)nblk), dim3(RT), 0, s, src_k, n, sh, nblk, hist);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -184,9 +193,12 @@ hipError_t radix_impl(K* ka, uint32_t* va, K* kb, uint32_t* vb, uint64_t n, int 
                            nblk, (const uint64_t*)hist);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        K* tk = src_k; src_k = dst_k; dst_k = tk;
-        uint32_t* tv = src_v; src_v = dst_v; dst_v = tv;
-        *in_b = !*in_b;
+        *in_b = dst_is_b;
+        src_k = dst_k;
+        src_v = dst_v;
+        dst_k = dst_is_b ? ka : kb;
+        dst_v = dst_is_b ? va : vb;
+        dst_is_b = !dst_is_b;
     }
     return hipSuccess;
 }
@@ -228,12 +240,22 @@ size_t radix_tmp_elems(uint64_t n) {
 
 hipError_t radix_sort_u64(uint64_t* ka, uint32_t* va, uint64_t* kb, uint32_t* vb, uint64_t n, int bits,
                           uint64_t* tmp, bool* in_b, hipStream_t s) {
-    return radix_impl<uint64_t>(ka, va, kb, vb, n, bits, tmp, in_b, s);
+    // the first pass reads (ka, va) and writes (kb, vb)
+    hipError_t e = radix_impl<uint64_t>(ka, va, kb, vb, ka, va, n, bits, tmp, in_b, s);
+    *in_b = !*in_b;
+    return e;
 }
 
 hipError_t radix_sort_u32(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, uint64_t n, int bits,
                           uint64_t* tmp, bool* in_b, hipStream_t s) {
-    return radix_impl<uint32_t>(ka, va, kb, vb, n, bits, tmp, in_b, s);
+    hipError_t e = radix_impl<uint32_t>(ka, va, kb, vb, ka, va, n, bits, tmp, in_b, s);
+    *in_b = !*in_b;
+    return e;
+}
+
+hipError_t radix_sort_u32_from(const uint32_t* keys, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
+                               uint64_t n, int bits, uint64_t* tmp, bool* in_b, hipStream_t s) {
+    return radix_impl<uint32_t>(keys, nullptr, ka, va, kb, vb, n, bits, tmp, in_b, s);
 }
 
 }  // namespace msc

@@ -31,6 +31,17 @@ __global__ __launch_bounds__(BT) void k_hist(const uint32_t* __restrict__ keys, 
     if (i < n) atomicAdd(&h[keys[i]], 1u);
 }
 
+// rowptr[k] = first position of a key >= k in the sorted keys (n + 1
+// threads; thread e fills the keys between keys[e - 1] and keys[e])
+__global__ __launch_bounds__(BT) void k_key_bounds(const uint32_t* __restrict__ keys, uint64_t n, uint64_t nkeys,
+                                                   uint64_t* __restrict__ rowptr) {
+    uint64_t e = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (e > n) return;
+    const uint64_t lo = e == 0 ? 0 : (uint64_t)keys[e - 1] + 1;
+    const uint64_t hi = e == n ? nkeys : (uint64_t)keys[e];
+    for (uint64_t k = lo; k <= hi; k++) rowptr[k] = e;
+}
+
 __global__ __launch_bounds__(BT) void k_gather_t(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ rows,
                                                  const uint64_t* __restrict__ val, uint32_t* __restrict__ ocol,
                                                  uint64_t* __restrict__ oval, uint64_t n) {
@@ -115,6 +126,11 @@ int bit_width(uint64_t v) {
     int b = 0;
     while (b < 64 && (v >> b) != 0) b++;
     return b < 1 ? 1 : b;
+}
+
+hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, uint64_t* rowptr, hipStream_t s) {
+    hipLaunchKernelGGL(k_key_bounds, dim3(grid_blocks(n + 1, BT)), dim3(BT), 0, s, keys, n, nkeys, rowptr);
+    return hipGetLastError();
 }
 
 hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, uint32_t* rows, hipStream_t s) {

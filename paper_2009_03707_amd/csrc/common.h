@@ -94,6 +94,13 @@ struct Geo {
 
 __device__ inline uint32_t nib_of(uint32_t word, uint32_t k) { return (word >> (4u * k)) & 15u; }
 
+// p[i] for a pointer known to address device memory but taken from a table
+// (the compiler cannot infer that itself and would use generic loads).
+template <typename T>
+__device__ inline T load_global(const T* p, uint64_t i) {
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+
 // Cell one refined step from (w, k) along `axis` with sign `s` (+1 / -1).
 // Returns false when the step leaves the grid.  `c` holds the coordinates of
 // vertex w.

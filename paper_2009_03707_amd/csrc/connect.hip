@@ -403,7 +403,8 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
         uint64_t* hval = buf<uint64_t>(c, "pe.hval", T);
         uint32_t* head = buf<uint32_t>(c, "pe.head", T);
         hp = buf<uint64_t>(c, "pe.hp", T + 1);
-        check(c, launch_entry_rank(m, ub, T, hrow, hval, head, s), "entry rank");
+        uint32_t* bstart = buf<uint32_t>(c, "pe.bstart", rank_blocks(T));
+        check(c, launch_entry_rank(m, ub, T, bstart, hrow, hval, head, s), "entry rank");
         if (!to_astar) {  // M21 sized for the upper bound; nnz is set once the heads are counted
             m21 = csr_buf(c, "m21", S2, S1, T);
             orow = m21.col;

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f0,
             uint64_t p = pos[idx]++;
             o_id[p] = 8u * v + k;
             o_index[p] = (uint8_t)idx;
-            o_value[p] = f[vm - geo.base(fld)];
+            o_value[p] = load_global(f, vm - geo.base(fld));
             o_vmax[p] = vm;
         }
     }

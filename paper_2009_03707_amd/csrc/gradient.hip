@@ -367,7 +367,7 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
         int x = x0 - 1 + fx, y = y0 - 1 + fy, z = z0 - 1 + fz;
         uint32_t key = KEY_OUT;
         if (x >= 0 && x < nx && y >= 0 && y < ny && z >= 0 && z < nz) {
-            uint32_t u = __float_as_uint(f[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * (size_t)z)]);
+            uint32_t u = __float_as_uint(load_global(f, (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * (size_t)z)));
             if ((u & 0x7F800000u) == 0x7F800000u) bad = true;
             key = float_key(u);
         }

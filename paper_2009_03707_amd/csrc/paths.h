@@ -46,8 +46,10 @@ hipError_t launch_merge(const MergeLaunch& m, const uint8_t* flag, const uint32_
 // flags (T + 1 entries), the compacted output at base + hp[p] and each
 // column's range (col_off/col_len by column id and/or a CSR row pointer).
 hipError_t launch_entry_ub(const MergeLaunch& m, uint64_t* ub, hipStream_t s);
-hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* hrow, uint64_t* hval,
-                             uint32_t* head, hipStream_t s);
+// bstart: scratch of rank_blocks(T) entries (the first column of each rank block)
+size_t rank_blocks(uint64_t T);
+hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* bstart, uint32_t* hrow,
+                             uint64_t* hval, uint32_t* head, hipStream_t s);
 hipError_t launch_entry_emit(uint64_t T, const uint32_t* head, const uint64_t* hp, const uint32_t* hrow,
                              const uint64_t* hval, uint64_t base, uint32_t* orow, uint64_t* oval, hipStream_t s);
 hipError_t launch_entry_cols(const MergeLaunch& m, const uint64_t* off, const uint64_t* hp, uint64_t base,

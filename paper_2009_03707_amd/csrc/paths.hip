@@ -607,6 +607,16 @@ constexpr int EPB = BT * EPT;     // entries per rank block
 constexpr int CW = 512;           // columns per LDS window of a rank block
 constexpr int LCAP = 768;         // list descriptors per LDS window
 
+// bstart[b] = the column holding entry b * EPB: every non-empty column i
+// claims the rank blocks whose first entry lies in [off[i], off[i + 1]).
+__global__ __launch_bounds__(BT) void k_block_start(const uint64_t* __restrict__ off, uint64_t n,
+                                                    uint32_t* __restrict__ bstart) {
+    const uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t lo = off[i], hi = off[i + 1];
+    for (uint64_t b = (lo + EPB - 1) / EPB; b * EPB < hi; b++) bstart[b] = (uint32_t)i;
+}
+
 // One rank block handles EPB consecutive input entries (the level's inputs
 // are column by column, each column's lists back to back).  Their columns
 // form a contiguous run; its offsets and list descriptors are staged in LDS
@@ -619,31 +629,19 @@ constexpr int LCAP = 768;         // list descriptors per LDS window
 // their metadata from global memory (same result).
 // off: exclusive scan of ub (n + 1 entries, off[n] = T).
 __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* __restrict__ off, uint64_t T,
-                                                   uint32_t* __restrict__ hrow, uint64_t* __restrict__ hval,
-                                                   uint32_t* __restrict__ head) {
+                                                   const uint32_t* __restrict__ bstart, uint32_t* __restrict__ hrow,
+                                                   uint64_t* __restrict__ hval, uint32_t* __restrict__ head) {
     __shared__ uint64_t s_off[CW + 1];
     __shared__ uint32_t s_lbase[CW + 1];
-    __shared__ const uint32_t* s_row[LCAP];
-    __shared__ const uint64_t* s_val[LCAP];
+    __shared__ uint64_t s_lo[LCAP];  // list start: in the base arrays (list 0) or the A* storage
     __shared__ uint32_t s_len[LCAP];
     __shared__ uint64_t s_mul[LCAP];
     __shared__ uint32_t s_x[EPB];
     __shared__ uint32_t s_sc[BT / WAVE + 1];
-    __shared__ uint64_t s_i0;
     __shared__ uint32_t s_nused;
     const uint64_t e0 = (uint64_t)blockIdx.x * EPB;
     const uint64_t e_end = e0 + EPB < T ? e0 + EPB : T;
-    if (threadIdx.x == 0) {  // the column of the block's first entry: the last i with off[i] <= e0
-        uint64_t lo = 0, hi = a.n;
-        while (hi - lo > 1) {
-            uint64_t mid = (lo + hi) >> 1;
-            if (off[mid] <= e0) lo = mid;
-            else hi = mid;
-        }
-        s_i0 = lo;
-    }
-    __syncthreads();
-    const uint64_t i0 = s_i0;
+    const uint64_t i0 = bstart[blockIdx.x];  // the column of the block's first entry
     const uint32_t wn = (uint32_t)((a.n - i0) < (uint64_t)CW ? (a.n - i0) : (uint64_t)CW);  // >= 1
     for (uint32_t t = threadIdx.x; t <= wn; t += BT) s_off[t] = off[i0 + t];
     __syncthreads();
@@ -679,11 +677,18 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
         if (t < nused) {
             s_lbase[t] = lb;
             for (uint32_t q = 0; q < kt[r] && lb + q < (uint32_t)LCAP; q++) {
-                const ListRef L = list_of(a, ct[r], q);
-                s_row[lb + q] = L.row;
-                s_val[lb + q] = L.val;
-                s_len[lb + q] = (uint32_t)L.len;
-                s_mul[lb + q] = L.mul;
+                if (q == 0) {
+                    const uint64_t b0 = a.brp[ct[r]];
+                    s_lo[lb] = b0;
+                    s_len[lb] = (uint32_t)(a.brp[ct[r] + 1] - b0);
+                    s_mul[lb] = 1;
+                } else {
+                    const uint64_t pq = a.prp[ct[r]] + (q - 1);
+                    const uint32_t p = a.pcol[pq];
+                    s_lo[lb + q] = a.aoff[p];
+                    s_len[lb + q] = a.alen[p];
+                    s_mul[lb + q] = a.pval[pq];
+                }
             }
         }
         lb += kt[r];
@@ -724,7 +729,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
             }
             e_list[r] = q;
             e_loc[r] = (uint32_t)local;
-            x[r] = s_row[b + q][local];
+            x[r] = (q == 0 ? a.bcol : a.arow)[s_lo[b + q] + local];
         } else {
             uint64_t glo = i0 + lo, ghi = a.n;  // last i with off[i] <= e
             while (ghi - glo > 1) {
@@ -763,7 +768,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
         if (e_win[r]) {
             const uint32_t lo = e_col[r], b = s_lbase[lo], k = s_lbase[lo + 1] - b;
             start = s_off[lo];
-            sum = sat_mul(s_val[b + s][e_loc[r]], s_mul[b + s]);
+            sum = sat_mul((s == 0 ? a.bval : a.aval)[s_lo[b + s] + e_loc[r]], s_mul[b + s]);
             uint64_t lstart = start;  // first entry of list t
             for (uint32_t t = 0; t < k; t++) {
                 const uint32_t l = s_len[b + t];
@@ -775,7 +780,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
                         lt = count_lt(rt, l, xs);
                         has = lt < l && rt[lt] == xs;
                     } else {
-                        const uint32_t* rt = s_row[b + t];
+                        const uint32_t* rt = (t == 0 ? a.bcol : a.arow) + s_lo[b + t];
                         lt = count_lt(rt, l, xs);
                         has = lt < l && rt[lt] == xs;
                     }
@@ -784,7 +789,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
                         is_head = is_head && !has;
                     } else {
                         rank += lt;
-                        if (has) sum = sat_add(sum, sat_mul(s_val[b + t][lt], s_mul[b + t]));
+                        if (has) sum = sat_add(sum, sat_mul((t == 0 ? a.bval : a.aval)[s_lo[b + t] + lt], s_mul[b + t]));
                     }
                 }
                 lstart += l;
@@ -974,10 +979,16 @@ hipError_t launch_entry_ub(const MergeLaunch& m, uint64_t* ub, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* hrow, uint64_t* hval,
-                             uint32_t* head, hipStream_t s) {
+size_t rank_blocks(uint64_t T) { return (T + EPB - 1) / EPB; }
+
+hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* bstart, uint32_t* hrow,
+                             uint64_t* hval, uint32_t* head, hipStream_t s) {
     if (T == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_entry_rank, dim3(grid_blocks(T, EPB)), dim3(BT), 0, s, to_args(m), off, T, hrow, hval, head);
+    hipLaunchKernelGGL(k_block_start, dim3(grid_blocks(m.n, BT)), dim3(BT), 0, s, off, m.n, bstart);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_entry_rank, dim3(grid_blocks(T, EPB)), dim3(BT), 0, s, to_args(m), off, T,
+                       (const uint32_t*)bstart, hrow, hval, head);
     return hipGetLastError();
 }
 

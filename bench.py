@@ -20,8 +20,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-GRAD_SRC = os.path.join(ROOT, "paper_2009_03707_amd", "csrc", "gradient.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grad_lowerstar_blobs512_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_2009_03707_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
 
 
 def log(msg):
@@ -69,23 +69,31 @@ def cpu_baseline(f, side):
                       f"{dt:.1f} s on one core of {cpu_model()} (host has {os.cpu_count()} logical CPUs)"}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the gradient kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size),
-    or None when the kernel source has changed since it was measured."""
+def measured_traffic(kernel, source):
+    """HBM bytes per launch of `kernel` from its committed counter summary
+    (profiles/<kernel>_blobs512_traffic.txt: FETCH_SIZE and WRITE_SIZE,
+    scaled by a plain copy of known size), or None when the kernel's source
+    file has changed since it was measured."""
     import hashlib
     try:
-        lines = open(TRAFFIC_FILE).read().splitlines()
+        lines = open(os.path.join(PROFILES, f"{kernel}_blobs512_traffic.txt")).read().splitlines()
     except OSError:
         return None
     kv = dict(l.split(":", 1) for l in lines if ":" in l and not l.startswith("#"))
-    src = hashlib.sha256(open(GRAD_SRC, "rb").read()).hexdigest()
+    src = hashlib.sha256(open(os.path.join(CSRC, source), "rb").read()).hexdigest()
     if kv.get("source_sha256", "").strip() != src:
         return None
     try:
         return int(kv["traffic_bytes_per_launch"].strip())
     except (KeyError, ValueError):
         return None
+
+
+def roofline(kernel, source, bytes_per_launch, avg_launch_ms):
+    achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel, source),
+            "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_launch_ms, 4)}
 
 
 def batch_bench(args, torch, msc):
@@ -192,8 +200,17 @@ def main():
     calls = max(tm["calls"], 1)
     grad_ms = tm["gradient_ms"] / calls
     grad_bytes = 8 * n  # 4 B field read + 4 B gradient word written per vertex
-    achieved = grad_bytes / (grad_ms / 1e3) / 1e9
-    stages = {k.replace("_ms", ""): round(v / calls, 3) for k, v in tm.items() if k.endswith("_ms")}
+    grad_roof = roofline("grad_lowerstar", "gradient.hip", grad_bytes, grad_ms)
+    if tm["rank_launches"] > 0:
+        # path-count ranking: per input entry 4 B row + 8 B count read and a
+        # 4 B head flag written; per run head 4 B row + 8 B sum written
+        rank_bytes = 16 * tm["rank_entries"] + 12 * tm["rank_heads"]
+        main_roof = roofline("k_entry_rank", "paths.hip", rank_bytes / tm["rank_launches"],
+                             tm["rank_ms"] / tm["rank_launches"])
+        main_roof["launches_per_step"] = tm["rank_launches"] // calls
+    else:
+        main_roof = grad_roof
+    stages = {k.replace("_ms", ""): round(v / calls, 3) for k, v in tm.items() if k.endswith("_ms") and k != "rank_ms"}
     out = {
         "metric": "MS-complex Mvoxels/s at 512^3 (plain vs batched), %HBM peak; p50/p99 latency",
         "value": round(value, 2),
@@ -209,10 +226,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "method": "plain (one field per call)", "voxels": n,
                    "critical_counts": counts},
-        "roofline": {"kernel": "grad_lowerstar", "bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(), "bytes_per_launch": grad_bytes,
-                     "avg_launch_ms": round(grad_ms, 4)},
+        "roofline": main_roof,
+        "roofline_gradient": grad_roof,
         "stages_ms": stages,
         "stats": stats,
         "launch_params": tuned,

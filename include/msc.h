@@ -217,6 +217,11 @@ typedef struct {
     int64_t allocations;     /* device allocations the context made while timing was on
                                 (workspace growth; zero in the steady state) */
     int64_t workspace_bytes; /* device memory the context holds now */
+    /* Launches of the path-count ranking kernel of MS_PATHS_ENTRY (the
+     * dominant kernel): summed event-timed duration, launch count, input
+     * entries ranked and run heads written. */
+    double rank_ms;
+    int64_t rank_launches, rank_entries, rank_heads;
 } ms_timing;
 
 /* Enables (1) or disables (0) timing; enabling resets the accumulators. */

@@ -150,6 +150,7 @@ void ms_ctx_destroy(ms_ctx* ctx) {
     if (ctx->h_small) (void)hipHostFree(ctx->h_small);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->rank_ev) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -203,6 +204,9 @@ ms_status ms_ctx_set_timing(ms_ctx* ctx, int enable) {
     for (double& a : ctx->acc_ms) a = 0;
     ctx->calls = 0;
     ctx->allocations = 0;
+    ctx->rank_ms = 0;
+    ctx->rank_launches = ctx->rank_entries = ctx->rank_heads = 0;
+    ctx->rank_used = 0;
     API_END
 }
 
@@ -218,6 +222,10 @@ ms_status ms_ctx_get_timing(ms_ctx* ctx, ms_timing* out) {
     out->calls = ctx->calls;
     out->allocations = ctx->allocations;
     out->workspace_bytes = ctx->ws_bytes;
+    out->rank_ms = ctx->rank_ms;
+    out->rank_launches = ctx->rank_launches;
+    out->rank_entries = ctx->rank_entries;
+    out->rank_heads = ctx->rank_heads;
     return MS_OK;
 }
 
@@ -280,6 +288,13 @@ static void accumulate_timing(ms_ctx* ctx) {
     check(ctx, hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[6]), "event elapsed");
     ctx->acc_ms[6] += tot;
     ctx->calls++;
+    for (size_t i = 0; i < ctx->rank_used; i++) {
+        float ms = 0;
+        check(ctx, hipEventElapsedTime(&ms, ctx->rank_ev[2 * i], ctx->rank_ev[2 * i + 1]), "event elapsed");
+        ctx->rank_ms += ms;
+    }
+    ctx->rank_launches += (int64_t)ctx->rank_used;
+    ctx->rank_used = 0;
 }
 
 ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out) {

@@ -404,7 +404,21 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
         uint32_t* head = buf<uint32_t>(c, "pe.head", T);
         hp = buf<uint64_t>(c, "pe.hp", T + 1);
         uint32_t* bstart = buf<uint32_t>(c, "pe.bstart", rank_blocks(T));
+        const bool timed = c->timing && T > 0;
+        if (timed) {
+            while (c->rank_ev.size() < 2 * (c->rank_used + 1)) {
+                hipEvent_t ev;
+                check(c, hipEventCreate(&ev), "event create");
+                c->rank_ev.push_back(ev);
+            }
+            check(c, hipEventRecord(c->rank_ev[2 * c->rank_used], s), "event record");
+        }
         check(c, launch_entry_rank(m, ub, T, bstart, hrow, hval, head, s), "entry rank");
+        if (timed) {
+            check(c, hipEventRecord(c->rank_ev[2 * c->rank_used + 1], s), "event record");
+            c->rank_used++;
+            c->rank_entries += (int64_t)T;
+        }
         if (!to_astar) {  // M21 sized for the upper bound; nnz is set once the heads are counted
             m21 = csr_buf(c, "m21", S2, S1, T);
             orow = m21.col;
@@ -459,12 +473,14 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     st.spgemm_iters = levels;
     st.nnz_astar = J ? (int64_t)read_u64(c, sum + J) : 0;
     st.products = (int64_t)(products + T);
+    if (c->timing) c->rank_heads += st.nnz_astar + m21.nnz;
 }
 }  // namespace
 
 void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t* crit, const int64_t cnt[4],
                   ms_arcs* out) {
     memset(out, 0, sizeof(*out));
+    c->rank_used = 0;  // rank timing pairs of an earlier call that were not accumulated
     hipStream_t s = c->stream;
     const uint64_t S0 = (uint64_t)cnt[0], S1 = (uint64_t)cnt[1], S2 = (uint64_t)cnt[2], S3 = (uint64_t)cnt[3];
     const uint32_t* s1 = crit + S0;

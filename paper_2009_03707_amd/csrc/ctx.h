@@ -9,6 +9,7 @@
 
 #include <map>
 #include <string>
+#include <vector>
 
 #include "../../include/msc.h"
 #include "common.h"
@@ -31,6 +32,12 @@ struct ms_ctx {
     double acc_ms[8] = {};
     int64_t calls = 0;
     int64_t allocations = 0;     // device allocations since timing was enabled
+    // launch-level timing of the entry-rank kernel (the dominant one): event
+    // pairs recorded around each launch of a call, accumulated at its end
+    std::vector<hipEvent_t> rank_ev;
+    size_t rank_used = 0;        // pairs recorded in the current call
+    double rank_ms = 0;
+    int64_t rank_launches = 0, rank_entries = 0, rank_heads = 0;
     int64_t ws_bytes = 0;        // device memory held in bufs
     int path_schedule = MS_PATHS_READY;
     uint32_t merge_light = 32;   // see MS_OPT_MERGE_LIGHT

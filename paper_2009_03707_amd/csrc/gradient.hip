@@ -31,6 +31,7 @@ struct Tile {
     static constexpr int NPLS = PX * PY * PZ;
 };
 constexpr int THREADS = 256;
+constexpr uint32_t NXCD = 8;  // accelerator complex dies of an MI355X
 constexpr uint32_t KEY_OUT = 0xFFFFFFFFu;  // vertex outside the grid
 constexpr uint32_t CENTER = 13;
 // edge cells of the star: offsets (+-1,0,0), (0,+-1,0), (0,0,+-1)
@@ -328,7 +329,8 @@ template <class T>
 __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restrict__ f0,
                                                            const float* const* __restrict__ fptr, Geo geo,
                                                            const uint32_t* __restrict__ tile_off,
-                                                           uint32_t* __restrict__ grad_all, int* __restrict__ err) {
+                                                           uint32_t total_tiles, uint32_t* __restrict__ grad_all,
+                                                           int* __restrict__ err) {
     constexpr int OX = T::OX, OY = T::OY, OZ = T::OZ, FX = T::FX, FY = T::FY, NF = T::NF, NW = T::NW;
     constexpr int PX = T::PX, PY = T::PY, NPLS = T::NPLS;
     __shared__ uint32_t fk[NF];
@@ -336,7 +338,12 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
     __shared__ uint32_t kk[27 * THREADS];
     __shared__ Tables tab;
     const int tid = threadIdx.x;
-    uint32_t t = blockIdx.x;
+    // Workgroups are dealt to the 8 XCDs round-robin; block b takes tile
+    // (b % 8) * per + b / 8, so each XCD works through a contiguous slab of
+    // tiles and the tiles' halos are shared in that XCD's L2.
+    const uint32_t per = (total_tiles + NXCD - 1) / NXCD;
+    uint32_t t = (blockIdx.x % NXCD) * per + blockIdx.x / NXCD;
+    if (t >= total_tiles) return;
     uint32_t fld = 0;
     if (geo.nf > 1) {
         uint32_t lo = 0, hi = geo.nf;
@@ -426,12 +433,13 @@ uint32_t gradient_tiles(const Grid& g, int shape) {
 hipError_t launch_gradient(int shape, const float* f0, const float* const* fptr, const Geo& geo,
                            const uint32_t* tile_off, uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
-    dim3 gd((unsigned)total_tiles), bd(THREADS);
+    const uint32_t tt = (uint32_t)total_tiles;
+    dim3 gd((unsigned)(NXCD * ((tt + NXCD - 1) / NXCD))), bd(THREADS);
     switch (shape) {
-        case 1: hipLaunchKernelGGL(grad_lowerstar<T1>, gd, bd, 0, s, f0, fptr, geo, tile_off, grad, err); break;
-        case 2: hipLaunchKernelGGL(grad_lowerstar<T2>, gd, bd, 0, s, f0, fptr, geo, tile_off, grad, err); break;
-        case 3: hipLaunchKernelGGL(grad_lowerstar<T3>, gd, bd, 0, s, f0, fptr, geo, tile_off, grad, err); break;
-        default: hipLaunchKernelGGL(grad_lowerstar<T0>, gd, bd, 0, s, f0, fptr, geo, tile_off, grad, err); break;
+        case 1: hipLaunchKernelGGL(grad_lowerstar<T1>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
+        case 2: hipLaunchKernelGGL(grad_lowerstar<T2>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
+        case 3: hipLaunchKernelGGL(grad_lowerstar<T3>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
+        default: hipLaunchKernelGGL(grad_lowerstar<T0>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
     }
     return hipGetLastError();
 }

@@ -62,7 +62,11 @@ class Timing(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("gradient_ms", "critical_ms", "extrema_ms", "bfs_ms", "minor_ms",
                                           "paths_ms", "total_ms")] + [("calls", C.c_int64),
                                                                       ("allocations", C.c_int64),
-                                                                      ("workspace_bytes", C.c_int64)]
+                                                                      ("workspace_bytes", C.c_int64),
+                                                                      ("rank_ms", C.c_double),
+                                                                      ("rank_launches", C.c_int64),
+                                                                      ("rank_entries", C.c_int64),
+                                                                      ("rank_heads", C.c_int64)]
 
 
 class Result(C.Structure):

@@ -13,6 +13,14 @@ mean value per dispatch.  With --copy-bytes B, the kernel whose name contains
 counter's bytes-per-KiB scale factor (B / (1024 * mean)) is printed.
 
     python -m paper_2009_03707_amd.prof_summary DIR/run_counter_collection.csv [N] [--copy-bytes B]
+
+Traffic of one kernel (per launch, in bytes) from a FETCH_SIZE run and a
+WRITE_SIZE run of the same command, each scaled by what the counter reads
+for the run's first plain copy dispatch of B bytes (bench.py
+--calibrate-copy issues it before anything else); the kernel's source file
+is hashed so that a later change of the kernel invalidates the figure.
+
+    python -m paper_2009_03707_amd.prof_summary traffic FETCH.csv WRITE.csv KERNEL SOURCE B
 """
 import collections
 import csv
@@ -53,7 +61,43 @@ def counters(path, n, copy_bytes):
                       f"-> {copy_bytes / (1024.0 * mean):.4f} bytes per counted KiB / 1024")
 
 
+def _dispatches(path, counter):
+    with open(path, newline="") as fh:
+        rows = [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return rows
+
+
+def traffic(fetch_csv, write_csv, kernel, source, copy_bytes):
+    import hashlib
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = hashlib.sha256(open(os.path.join(here, "csrc", source), "rb").read()).hexdigest()
+    out = {}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _dispatches(path, name)
+        cal = next(r for r in rows if "copyBuffer" in r["Kernel_Name"])
+        factor = copy_bytes / (1024.0 * float(cal["Counter_Value"]))  # bytes per counted byte
+        ks = [float(r["Counter_Value"]) for r in rows if short(r["Kernel_Name"]).startswith(kernel)]
+        out[name] = (factor, float(cal["Counter_Value"]), len(ks), sum(ks) * 1024.0 * factor / max(len(ks), 1))
+    f_fac, f_cal, n, f_b = out["FETCH_SIZE"]
+    w_fac, w_cal, _, w_b = out["WRITE_SIZE"]
+    print(f"# {kernel}: HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch)")
+    print(f"# calibration: first plain copy of {copy_bytes} B reads FETCH_SIZE {f_cal:.1f} KiB "
+          f"(x{f_fac:.4f}) and WRITE_SIZE {w_cal:.1f} KiB (x{w_fac:.4f})")
+    print(f"kernel: {kernel}")
+    print(f"source: {source}")
+    print(f"source_sha256: {src}")
+    print(f"launches: {n}")
+    print(f"fetch_bytes_per_launch: {int(f_b)}")
+    print(f"write_bytes_per_launch: {int(w_b)}")
+    print(f"traffic_bytes_per_launch: {int(f_b + w_b)}")
+
+
 def main():
+    if sys.argv[1] == "traffic":
+        traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]))
+        return
     if sys.argv[1].endswith(".csv"):
         args = [a for a in sys.argv[2:] if not a.startswith("--")]
         cb = 0

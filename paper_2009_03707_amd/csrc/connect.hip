@@ -6,6 +6,8 @@
 #include "ctx.h"
 #include "paths.h"
 
+#include <vector>
+
 namespace msc {
 
 hipError_t launch_pj_init(const uint32_t* grad, const Geo& g, uint32_t* Pv, uint32_t* Pc, int* err, hipStream_t s);
@@ -20,7 +22,9 @@ int bit_width(uint64_t v);
 hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, uint32_t* rows, hipStream_t s);
 hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s);
 hipError_t launch_hist(const uint32_t* keys, uint64_t n, uint32_t* h, hipStream_t s);
-hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, uint64_t* rowptr, hipStream_t s);
+size_t key_bounds_tmp_elems(uint64_t n, uint64_t nkeys);
+hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, uint64_t* rowptr, uint64_t* tmp,
+                             hipStream_t s);
 hipError_t launch_gather_t(const uint32_t* perm, const uint32_t* rows, const uint64_t* val, uint32_t* ocol,
                            uint64_t* oval, uint64_t n, hipStream_t s);
 hipError_t launch_make_keys(const uint32_t* row, const uint32_t* col, uint64_t n, int cb, uint64_t* keys,
@@ -119,7 +123,8 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out) {
     const uint32_t* keys = in_b ? kb : ka;
     const uint32_t* perm = in_b ? vb : va;
     check(c, launch_gather_t(perm, rows, in.val, out.col, out.val, nnz, c->stream), "gather");
-    check(c, launch_key_bounds(keys, nnz, (uint64_t)in.ncols, (uint64_t*)out.rowptr, c->stream), "bounds");
+    uint64_t* gtmp = buf<uint64_t>(c, "tr.gaps", key_bounds_tmp_elems(nnz, (uint64_t)in.ncols));
+    check(c, launch_key_bounds(keys, nnz, (uint64_t)in.ncols, (uint64_t*)out.rowptr, gtmp, c->stream), "bounds");
 }
 
 // Sort a COO by (row, col) and merge repeats; result in buffer set `name`.
@@ -348,46 +353,73 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     st.products = (int64_t)(used + tp);
     return true;
 }
-// The ready schedule with entry-parallel merges (see paths.hip): per level,
-// input counts, their scan, one thread per input entry ranking it in its
-// column, a scan of the run heads and a compaction.  A* columns are stored
-// gap-free within a level; levels are placed at their upper-bound offsets.
-// P is written directly as M21 (rows 2-saddles).  No column size limit.
+// The ready schedule with entry-parallel merges (see paths.hip).
+// Junctions are first numbered in topological order: a sweep over the
+// junction DAG releases each level's successors (the ready frontier) and
+// the concatenated frontiers give the new numbering, applied to A, B and
+// B* before their transposes.  A level is then a contiguous range of
+// columns, so per-column metadata is read in order and no frontier has to
+// be kept while merging.  Per level: input counts, their scan, one thread
+// per input entry ranking it in its column, a scan of the run heads that
+// writes them out.  A* columns are stored gap-free within a level; levels are
+// placed at their upper-bound offsets.  P is written directly as M21 (rows
+// 2-saddles).  No column size limit.
 void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, const ms_csr& D, uint64_t S1,
                  uint64_t S2, uint64_t J, ms_arcs* out, int* d_err) {
     hipStream_t s = c->stream;
     ms_stats& st = out->stats;
+    // ---- topological numbering --------------------------------------------
+    uint32_t* indeg = buf<uint32_t>(c, "pr.indeg", J + 1);
+    uint32_t* order = buf<uint32_t>(c, "pr.order", J + 1);
+    uint32_t* newid = buf<uint32_t>(c, "pr.newid", J + 1);
+    unsigned long long* d_n = (unsigned long long*)buf<uint64_t>(c, "pr.counts", 3);
+    check(c, hipMemsetAsync(indeg, 0, sizeof(uint32_t) * (J + 1), s), "memset");
+    check(c, hipMemsetAsync(d_n, 0, 24, s), "memset");
+    check(c, launch_hist(B.col, (uint64_t)B.nnz, indeg, s), "in-degrees");
+    check(c, launch_sources(indeg, J, order, d_n, s), "sources");
+    std::vector<uint64_t> lvl{0};
+    uint64_t r = J ? readback(c, (const uint64_t*)d_n, 1)[0] : 0;
+    while (r > 0) {
+        const uint64_t pos = lvl.back();
+        lvl.push_back(pos + r);
+        check(c, hipMemsetAsync(d_n, 0, 8, s), "memset");
+        check(c, launch_release(order + pos, r, (const uint64_t*)B.rowptr, B.col, indeg, order + pos + r, d_n, d_err,
+                                nullptr, nullptr, nullptr, nullptr, nullptr, s),
+              "release");
+        r = readback(c, (const uint64_t*)d_n, 1)[0];
+        if (lvl.size() > J + 2) fail(c, MS_ERR_INTERNAL, "path counting did not terminate");
+    }
+    if (lvl.back() != J) fail(c, MS_ERR_INTERNAL, "the junction graph has a cycle");
+    const uint64_t nlev = lvl.size() - 1;
+    check(c, launch_invert(order, J, newid, s), "invert");
+    // A, B by their target junctions in the new numbering; sources relabelled after the transposes
+    check(c, launch_relabel(A.col, (uint64_t)A.nnz, newid, s), "relabel");
+    check(c, launch_relabel(B.col, (uint64_t)B.nnz, newid, s), "relabel");
     ms_csr At, Bt, Bst, Dt;
     transpose(c, A, "At", At);     // junction x 1-saddle
     transpose(c, B, "Bt", Bt);     // junction x predecessor junction
     transpose(c, Bs, "Bst", Bst);  // 2-saddle x junction
     transpose(c, D, "Dt", Dt);     // 2-saddle x 1-saddle
+    check(c, launch_relabel(Bt.col, (uint64_t)Bt.nnz, newid, s), "relabel");
+    check(c, launch_relabel(Bst.col, (uint64_t)Bst.nnz, newid, s), "relabel");
+    // ---- levels --------------------------------------------------------------
     const uint64_t nmax = (J > S2 ? J : S2) + 1;
-    uint32_t* indeg = buf<uint32_t>(c, "pr.indeg", J);
-    uint32_t* ready[2] = {buf<uint32_t>(c, "pr.ready0", J), buf<uint32_t>(c, "pr.ready1", J)};
-    // input counts of the ready columns, in ready order (scanned in place)
-    uint64_t* ubs[2] = {buf<uint64_t>(c, "pr.ub0", nmax + 1), buf<uint64_t>(c, "pr.ub1", nmax + 1)};
-    uint64_t* aoff = buf<uint64_t>(c, "pr.aoff", J);
-    uint32_t* alen = buf<uint32_t>(c, "pr.alen", J);
-    unsigned long long* d_n = (unsigned long long*)buf<uint64_t>(c, "pr.counts", 3);
-    check(c, hipMemsetAsync(d_n, 0, 24, s), "memset");
-    check(c, launch_ready_init((const uint64_t*)Bt.rowptr, J, indeg, ready[0], d_n, (const uint64_t*)At.rowptr,
-                               ubs[0], s),
-          "ready init");
-    uint64_t r = J ? readback(c, (const uint64_t*)d_n, 1)[0] : 0;
-    uint64_t used = 0, processed = 0, products = 0;
-    int64_t levels = 0;
+    uint64_t* ub = buf<uint64_t>(c, "pr.ub", nmax + 1);
+    uint64_t* aoff = buf<uint64_t>(c, "pr.aoff", J + 1);
+    uint32_t* alen = buf<uint32_t>(c, "pr.alen", J + 1);
+    uint64_t used = 0, products = 0;
     uint32_t* arow = buf_keep<uint32_t>(c, "astar.row", 1, 0);
     uint64_t* aval = buf_keep<uint64_t>(c, "astar.val", 1, 0);
-    int cur = 0;
     ms_csr m21{};
-    // one level: scan the input counts, rank every input entry, then scan the
-    // run heads and write them at base (into the A* storage or M21)
-    auto level = [&](MergeLaunch& m, uint64_t* ub, uint64_t n, bool to_astar, uint32_t*& orow, uint64_t*& oval,
-                     uint64_t& base, uint64_t*& hp) -> uint64_t {
+    // one level: input counts and their scan, rank every input entry, then
+    // scan the run heads and write them at base (into the A* storage or M21)
+    auto level = [&](MergeLaunch& m, uint64_t n, bool to_astar, uint64_t& base, uint64_t*& hp) -> uint64_t {
         uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(n) + 1);
+        check(c, launch_entry_ub(m, ub, s), "entry ub");
         check(c, scan_excl_u64(ub, ub, n, stmp, ub + n, s), "scan");
         const uint64_t T = n ? read_u64(c, ub + n) : 0;
+        uint32_t* orow;
+        uint64_t* oval;
         if (to_astar) {  // room for this level's columns at their upper bound
             arow = buf_keep<uint32_t>(c, "astar.row", used + T, used);
             aval = buf_keep<uint64_t>(c, "astar.val", used + T, used);
@@ -396,7 +428,10 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
             orow = arow;
             oval = aval;
             base = used;
-        } else {
+        } else {  // M21 sized for the upper bound; nnz is set once the heads are counted
+            m21 = csr_buf(c, "m21", S2, S1, T);
+            orow = m21.col;
+            oval = m21.val;
             base = 0;
         }
         uint32_t* hrow = buf<uint32_t>(c, "pe.hrow", T);
@@ -419,50 +454,29 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
             c->rank_used++;
             c->rank_entries += (int64_t)T;
         }
-        if (!to_astar) {  // M21 sized for the upper bound; nnz is set once the heads are counted
-            m21 = csr_buf(c, "m21", S2, S1, T);
-            orow = m21.col;
-            oval = m21.val;
-        }
         uint64_t* htmp = buf<uint64_t>(c, "pe.htmp", head_scan_tmp_elems(T));
         check(c, launch_head_scan_emit(head, T, hrow, hval, base, orow, oval, hp, htmp, s), "head scan");
         return T;
     };
-    while (r > 0) {
-        MergeLaunch m{ready[cur], r, (const uint64_t*)At.rowptr, At.col, At.val, (const uint64_t*)Bt.rowptr, Bt.col,
-                      Bt.val, aoff, alen, arow, aval, 0, 1, 1};
-        uint32_t* orow;
-        uint64_t* oval;
+    for (uint64_t L = 0; L < nlev; L++) {
+        MergeLaunch m{nullptr, lvl[L + 1] - lvl[L], (const uint64_t*)At.rowptr, At.col, At.val,
+                      (const uint64_t*)Bt.rowptr, Bt.col, Bt.val, aoff, alen, arow, aval, 0, 1, 1, (uint32_t)lvl[L]};
         uint64_t base;
         uint64_t* hp;
-        const uint64_t T = level(m, ubs[cur], r, true, orow, oval, base, hp);
-        check(c, launch_entry_cols(m, ubs[cur], hp, base, aoff, alen, nullptr, s), "entry cols");
+        const uint64_t T = level(m, m.n, true, base, hp);
+        check(c, launch_entry_cols(m, ub, hp, base, aoff, alen, nullptr, s), "entry cols");
         used += T;
         products += T;
-        processed += r;
-        levels++;
-        check(c, hipMemsetAsync(d_n, 0, 8, s), "memset");
-        check(c, launch_release(ready[cur], r, (const uint64_t*)B.rowptr, B.col, indeg, ready[1 - cur], d_n, d_err,
-                                (const uint64_t*)At.rowptr, (const uint64_t*)Bt.rowptr, Bt.col, alen, ubs[1 - cur], s),
-              "release");
-        r = readback(c, (const uint64_t*)d_n, 1)[0];
-        cur = 1 - cur;
-        if ((uint64_t)levels > J + 1) fail(c, MS_ERR_INTERNAL, "path counting did not terminate");
     }
-    if (processed != J) fail(c, MS_ERR_INTERNAL, "the junction graph has a cycle");
     // P columns, written as M21 (rows 2-saddles) in canonical order
     MergeLaunch mp{nullptr, S2, (const uint64_t*)Dt.rowptr, Dt.col, Dt.val, (const uint64_t*)Bst.rowptr, Bst.col,
                    Bst.val, aoff, alen, arow, aval, 0, 1, 1};
-    uint64_t* ubp = ubs[0];
-    check(c, launch_entry_ub(mp, ubp, s), "entry ub");
-    uint32_t* prow;
-    uint64_t* pval;
     uint64_t pbase;
     uint64_t* hp;
-    const uint64_t T = level(mp, ubp, S2, false, prow, pval, pbase, hp);
+    const uint64_t T = level(mp, S2, false, pbase, hp);
     m21.nnz = (int64_t)read_u64(c, hp + T);
     if (S2 == 0) check(c, hipMemsetAsync(m21.rowptr, 0, sizeof(int64_t), s), "memset");
-    check(c, launch_entry_cols(mp, ubp, hp, 0, nullptr, nullptr, (uint64_t*)m21.rowptr, s), "entry cols");
+    check(c, launch_entry_cols(mp, ub, hp, 0, nullptr, nullptr, (uint64_t*)m21.rowptr, s), "entry cols");
     check_err_flag(c, d_err, "path counting");
     out->m21 = m21;
     transpose(c, out->m21, "m21t", out->m21t);
@@ -470,7 +484,7 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     uint64_t* sum = buf<uint64_t>(c, "pe.asum", J + 1);
     uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(J) + 1);
     check(c, scan_excl_u32_to_u64(alen, sum, J, stmp, sum + J, s), "scan");
-    st.spgemm_iters = levels;
+    st.spgemm_iters = (int64_t)nlev;
     st.nnz_astar = J ? (int64_t)read_u64(c, sum + J) : 0;
     st.products = (int64_t)(products + T);
     if (c->timing) c->rank_heads += st.nnz_astar + m21.nnz;

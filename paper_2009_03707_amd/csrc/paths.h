@@ -24,6 +24,7 @@ struct MergeLaunch {
     uint32_t light_ub;  // columns with at most this many inputs (and <= 8 lists) merge in one thread
     uint32_t chunk;     // other columns merge in chunks of at most this many entries (1..4096)
     uint32_t wave_blocks;  // workgroups of the wave-path launch (each wave strides over its queue)
+    uint32_t col0 = 0;     // with cols null: the columns are col0 .. col0 + n - 1
 };
 
 // Upper bound (input entries) per output column into ub, a path flag per
@@ -66,6 +67,12 @@ hipError_t launch_release(const uint32_t* ready, uint64_t n, const uint64_t* brp
                           uint32_t* indeg, uint32_t* next, unsigned long long* nnext, int* err, const uint64_t* base_rp,
                           const uint64_t* prp, const uint32_t* pcol, const uint32_t* alen, uint64_t* ub_next,
                           hipStream_t s);
+// Topological numbering: the junctions with zero in-degree appended to out
+// (count in *n, which must be zero on entry); inv[order[i]] = i; x[i] =
+// map[x[i]] in place.
+hipError_t launch_sources(const uint32_t* indeg, uint64_t J, uint32_t* out, unsigned long long* n, hipStream_t s);
+hipError_t launch_invert(const uint32_t* order, uint64_t n, uint32_t* inv, hipStream_t s);
+hipError_t launch_relabel(uint32_t* x, uint64_t n, const uint32_t* map, hipStream_t s);
 // Exclusive scan of the head flags into hp (T + 1 entries, hp[T] = number of
 // heads) with each head's row and count written at base + hp[p]; tmp needs
 // head_scan_tmp_elems(T) entries.

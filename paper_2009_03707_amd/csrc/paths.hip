@@ -45,7 +45,8 @@ constexpr int WPB = BT / WAVE;     // waves per workgroup
 constexpr uint32_t NOROW = 0xFFFFFFFFu;
 
 struct MergeArgs {
-    const uint32_t* cols;  // output column ids (null: identity 0..n-1)
+    const uint32_t* cols;  // output column ids (null: col0 .. col0 + n - 1)
+    uint32_t col0;
     uint64_t n;
     const uint64_t* brp;   // base list per output column: CSR (row ids, values)
     const uint32_t* bcol;
@@ -60,6 +61,10 @@ struct MergeArgs {
     uint32_t light_ub;  // thread path: at most this many input entries
     uint32_t chunk;     // workgroup path: entries per chunk (<= CAP)
 };
+
+__device__ __forceinline__ uint32_t col_of(const MergeArgs& a, uint64_t i) {
+    return a.cols ? a.cols[i] : a.col0 + (uint32_t)i;
+}
 
 struct ListRef {
     const uint32_t* row;
@@ -103,7 +108,7 @@ __global__ __launch_bounds__(BT) void k_classify(MergeArgs a, uint64_t* __restri
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
     unsigned long long h = 0;  // low half: wave path, high half: workgroup path
     if (i < a.n) {
-        uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
+        uint32_t c = col_of(a, i);
         uint32_t k = num_lists(a, c);
         uint64_t u = a.brp[c + 1] - a.brp[c];
         for (uint32_t s = 1; s < k; s++) u += a.alen[a.pcol[a.prp[c] + (s - 1)]];
@@ -140,7 +145,7 @@ __global__ __launch_bounds__(BT) void k_merge_thread(MergeArgs a, const uint8_t*
                                                      uint32_t* __restrict__ col_len) {
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= a.n || flag[i]) return;
-    uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
+    uint32_t c = col_of(a, i);
     uint32_t k = num_lists(a, c);
     const uint32_t* rp[LIGHT_K];
     const uint64_t* vp[LIGHT_K];
@@ -261,7 +266,7 @@ __global__ __launch_bounds__(BT) void k_merge_wave(MergeArgs a, const uint32_t* 
     const uint64_t stride = (uint64_t)gridDim.x * WPB;
     for (uint64_t h = (uint64_t)blockIdx.x * WPB + w; h < nq; h += stride) {
         const uint32_t i = queue[h];
-        const uint32_t c = a.cols ? a.cols[i] : i;
+        const uint32_t c = col_of(a, i);
         const uint32_t k = num_lists(a, c);
         const uint32_t* lr = nullptr;
         uint32_t len = 0, pos = 0;
@@ -368,7 +373,7 @@ __global__ __launch_bounds__(BT) void k_merge_block(MergeArgs a, const uint32_t*
     const uint64_t nh = qn[1];
     for (uint64_t h = blockIdx.x; h < nh; h += gridDim.x) {
         const uint32_t i = heavy[h];
-        const uint32_t c = a.cols ? a.cols[i] : i;
+        const uint32_t c = col_of(a, i);
         const uint32_t k = num_lists(a, c);
         for (uint32_t s = tid; s < k; s += BT) {
             ListRef L = list_of(a, c, s);
@@ -582,6 +587,32 @@ __global__ __launch_bounds__(BT) void k_release(const uint32_t* __restrict__ rea
     }
 }
 
+// ---- topological numbering of the junctions ---------------------------------
+// Junctions without predecessors (in-degree from a histogram of B's columns)
+__global__ __launch_bounds__(BT) void k_sources(const uint32_t* __restrict__ indeg, uint64_t J,
+                                                uint32_t* __restrict__ out, unsigned long long* __restrict__ n) {
+    __shared__ unsigned long long sc[BT / WAVE + 1];
+    __shared__ unsigned long long base;
+    uint64_t j = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    unsigned long long is0 = (j < J && indeg[j] == 0u) ? 1ull : 0ull;
+    unsigned long long tot;
+    unsigned long long ex = block_excl_scan<unsigned long long, BT>(is0, sc, tot);
+    if (threadIdx.x == 0) base = tot ? atomicAdd(n, tot) : 0;
+    __syncthreads();
+    if (is0) out[base + ex] = (uint32_t)j;
+}
+
+__global__ __launch_bounds__(BT) void k_invert(const uint32_t* __restrict__ order, uint64_t n,
+                                               uint32_t* __restrict__ inv) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i < n) inv[order[i]] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(BT) void k_relabel(uint32_t* __restrict__ x, uint64_t n, const uint32_t* __restrict__ map) {
+    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    if (i < n) x[i] = map[x[i]];
+}
+
 // ---- entry-parallel merges ---------------------------------------------------
 // One thread per input entry of a level (the entries of all columns, column
 // by column, each column's lists back to back: base list, then predecessor
@@ -595,7 +626,7 @@ __global__ __launch_bounds__(BT) void k_release(const uint32_t* __restrict__ rea
 __global__ __launch_bounds__(BT) void k_entry_ub(MergeArgs a, uint64_t* __restrict__ ub) {
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= a.n) return;
-    uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
+    uint32_t c = col_of(a, i);
     uint32_t k = num_lists(a, c);
     uint64_t u = a.brp[c + 1] - a.brp[c];
     for (uint32_t s = 1; s < k; s++) u += a.alen[a.pcol[a.prp[c] + (s - 1)]];
@@ -664,7 +695,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
         kt[r] = 0;
         ct[r] = 0;
         if (t < nused) {
-            ct[r] = a.cols ? a.cols[i0 + t] : (uint32_t)(i0 + t);
+            ct[r] = col_of(a, i0 + t);
             kt[r] = num_lists(a, ct[r]);
         }
         ksum += kt[r];
@@ -738,7 +769,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
                 else ghi = mid;
             }
             e_glo[r] = glo;
-            const uint32_t c = a.cols ? a.cols[glo] : (uint32_t)glo;
+            const uint32_t c = col_of(a, glo);
             uint64_t local = e - off[glo];
             uint32_t q = 0;
             ListRef L = list_of(a, c, 0);
@@ -796,7 +827,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
             }
         } else {
             const uint64_t glo = e_glo[r];
-            const uint32_t c = a.cols ? a.cols[glo] : (uint32_t)glo;
+            const uint32_t c = col_of(a, glo);
             const uint32_t k = num_lists(a, c);
             start = off[glo];
             const ListRef L = list_of(a, c, s);
@@ -911,7 +942,7 @@ __global__ __launch_bounds__(BT) void k_entry_cols(MergeArgs a, const uint64_t* 
     if (i >= a.n) return;
     const uint64_t s0 = hp[off[i]], s1 = hp[off[i + 1]];
     if (col_off) {
-        const uint32_t c = a.cols ? a.cols[i] : (uint32_t)i;
+        const uint32_t c = col_of(a, i);
         col_off[c] = base + s0;
         col_len[c] = (uint32_t)(s1 - s0);
     }
@@ -924,6 +955,7 @@ __global__ __launch_bounds__(BT) void k_entry_cols(MergeArgs a, const uint64_t* 
 MergeArgs to_args(const MergeLaunch& m) {
     MergeArgs a;
     a.cols = m.cols;
+    a.col0 = m.col0;
     a.n = m.n;
     a.brp = m.brp;
     a.bcol = m.bcol;
@@ -997,6 +1029,24 @@ hipError_t launch_entry_emit(uint64_t T, const uint32_t* head, const uint64_t* h
     if (T == 0) return hipSuccess;
     hipLaunchKernelGGL(k_entry_emit, dim3(grid_blocks(T, BT)), dim3(BT), 0, s, T, head, hp, hrow, hval, base, orow,
                        oval);
+    return hipGetLastError();
+}
+
+hipError_t launch_sources(const uint32_t* indeg, uint64_t J, uint32_t* out, unsigned long long* n, hipStream_t s) {
+    if (J == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sources, dim3(grid_blocks(J, BT)), dim3(BT), 0, s, indeg, J, out, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert(const uint32_t* order, uint64_t n, uint32_t* inv, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_invert, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, order, n, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_relabel(uint32_t* x, uint64_t n, const uint32_t* map, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_relabel, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, x, n, map);
     return hipGetLastError();
 }
 

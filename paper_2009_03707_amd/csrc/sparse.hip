@@ -32,14 +32,35 @@ __global__ __launch_bounds__(BT) void k_hist(const uint32_t* __restrict__ keys, 
 }
 
 // rowptr[k] = first position of a key >= k in the sorted keys (n + 1
-// threads; thread e fills the keys between keys[e - 1] and keys[e])
+// threads; thread e fills the keys between keys[e - 1] and keys[e]).  Gaps
+// longer than GAP_INLINE are queued and filled by a whole workgroup each.
+constexpr uint64_t GAP_INLINE = 64;
+
 __global__ __launch_bounds__(BT) void k_key_bounds(const uint32_t* __restrict__ keys, uint64_t n, uint64_t nkeys,
-                                                   uint64_t* __restrict__ rowptr) {
+                                                   uint64_t* __restrict__ rowptr, uint64_t* __restrict__ gaps,
+                                                   unsigned long long* __restrict__ ngaps) {
     uint64_t e = (uint64_t)blockIdx.x * BT + threadIdx.x;
     if (e > n) return;
     const uint64_t lo = e == 0 ? 0 : (uint64_t)keys[e - 1] + 1;
     const uint64_t hi = e == n ? nkeys : (uint64_t)keys[e];
+    if (hi + 1 > lo + GAP_INLINE) {
+        const unsigned long long g = atomicAdd(ngaps, 1ull);
+        gaps[3 * g] = lo;
+        gaps[3 * g + 1] = hi;
+        gaps[3 * g + 2] = e;
+        return;
+    }
     for (uint64_t k = lo; k <= hi; k++) rowptr[k] = e;
+}
+
+__global__ __launch_bounds__(BT) void k_fill_gaps(const uint64_t* __restrict__ gaps,
+                                                  const unsigned long long* __restrict__ ngaps,
+                                                  uint64_t* __restrict__ rowptr) {
+    const uint64_t ng = *ngaps;
+    for (uint64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+        const uint64_t lo = gaps[3 * g], hi = gaps[3 * g + 1], v = gaps[3 * g + 2];
+        for (uint64_t k = lo + threadIdx.x; k <= hi; k += BT) rowptr[k] = v;
+    }
 }
 
 __global__ __launch_bounds__(BT) void k_gather_t(const uint32_t* __restrict__ perm, const uint32_t* __restrict__ rows,
@@ -128,8 +149,19 @@ int bit_width(uint64_t v) {
     return b < 1 ? 1 : b;
 }
 
-hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, uint64_t* rowptr, hipStream_t s) {
-    hipLaunchKernelGGL(k_key_bounds, dim3(grid_blocks(n + 1, BT)), dim3(BT), 0, s, keys, n, nkeys, rowptr);
+size_t key_bounds_tmp_elems(uint64_t n, uint64_t nkeys) { return 3 * ((nkeys + 1) / GAP_INLINE + 2) + 1; }
+
+// tmp: key_bounds_tmp_elems(n, nkeys) uint64 (gap list and its counter)
+hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, uint64_t* rowptr, uint64_t* tmp,
+                             hipStream_t s) {
+    unsigned long long* ng = (unsigned long long*)tmp;
+    hipError_t e = hipMemsetAsync(ng, 0, sizeof(uint64_t), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_key_bounds, dim3(grid_blocks(n + 1, BT)), dim3(BT), 0, s, keys, n, nkeys, rowptr, tmp + 1, ng);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fill_gaps, dim3(256), dim3(BT), 0, s, (const uint64_t*)(tmp + 1),
+                       (const unsigned long long*)ng, rowptr);
     return hipGetLastError();
 }
 

@@ -223,6 +223,37 @@ struct Unroll<0> {
     __device__ __forceinline__ static void run(F&&) {}
 };
 
+// Number of cells in the lower star of the vertex at fidx (the same test as
+// in lower_star below); used to give each wave vertices of similar work.
+template <class T>
+__device__ uint32_t lower_star_size(const uint32_t* fk, int fidx) {
+    constexpr int FX = T::FX, FY = T::FY;
+    uint32_t K[27];
+    Unroll<27>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        constexpr int o = off_x(j) + FX * (off_y(j) + FY * off_z(j));
+        K[j] = fk[fidx + o];
+    });
+    const uint32_t kc = K[CENTER];
+    uint32_t lower = 0;
+    Unroll<27>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (j != (int)CENTER) {
+            bool lw = (j < (int)CENTER) ? (K[j] <= kc) : (K[j] < kc);
+            lower |= (lw ? 1u : 0u) << j;
+        }
+    });
+    uint32_t LS = 1u << CENTER;
+    Unroll<27>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (j != (int)CENTER) {
+            constexpr uint32_t vm = vert_mask(j);
+            LS |= ((vm & ~lower) == 0 ? 1u : 0u) << j;
+        }
+    });
+    return (uint32_t)__builtin_popcount(LS);
+}
+
 template <class T>
 __device__ void lower_star(const uint32_t* fk, int fidx, const Star<T>& st, uint32_t* kk, int tid) {
     constexpr int FX = T::FX, FY = T::FY;
@@ -337,6 +368,9 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
     __shared__ uint32_t words[NW];
     __shared__ uint32_t kk[27 * THREADS];
     __shared__ Tables tab;
+    __shared__ uint8_t s_size[NPLS];
+    __shared__ uint16_t s_ord[NPLS];
+    __shared__ uint32_t s_cnt[32];
     const int tid = threadIdx.x;
     // Workgroups are dealt to the 8 XCDs round-robin; block b takes tile
     // (b % 8) * per + b / 8, so each XCD works through a contiguous slab of
@@ -384,10 +418,36 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
     for (int i = tid; i < NW; i += THREADS) words[i] = 0u;
     __syncthreads();
 
+    // The pairing loop's length grows with the lower star, and a wave runs as
+    // long as its largest one: order the tile's vertices by lower-star size
+    // (counting sort in LDS) so that each wave gets vertices of similar size.
+    // Nibbles are OR-ed into the word tile, so the order does not matter.
+    if (tid < 32) s_cnt[tid] = 0;
+    __syncthreads();
     for (int i = tid; i < NPLS; i += THREADS) {
         int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
         int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        if (x >= nx || y >= ny || z >= nz) continue;
+        uint32_t sz = 0;  // vertices outside the grid: size 0, skipped below
+        if (x < nx && y < ny && z < nz) sz = lower_star_size<T>(fk, (lx + 1) + FX * ((ly + 1) + FY * (lz + 1)));
+        s_size[i] = (uint8_t)sz;
+        atomicAdd(&s_cnt[sz], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b < 32; b++) {
+            uint32_t c = s_cnt[b];
+            s_cnt[b] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < NPLS; i += THREADS) s_ord[atomicAdd(&s_cnt[s_size[i]], 1u)] = (uint16_t)i;
+    __syncthreads();
+    for (int k = tid; k < NPLS; k += THREADS) {
+        const int i = s_ord[k];
+        if (s_size[i] == 0) continue;
+        int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
         Star<T> st{lx, ly, lz, words, &tab};
         int fidx = (lx + 1) + FX * ((ly + 1) + FY * (lz + 1));
         lower_star(fk, fidx, st, kk, tid);
@@ -410,6 +470,8 @@ using T0 = Tile<16, 8, 4>;
 using T1 = Tile<32, 4, 4>;
 using T2 = Tile<8, 8, 8>;
 using T3 = Tile<16, 16, 2>;
+using T4 = Tile<16, 8, 8>;
+using T5 = Tile<16, 16, 8>;
 
 template <class T>
 uint32_t tiles_of(const Grid& g) {
@@ -418,12 +480,14 @@ uint32_t tiles_of(const Grid& g) {
 
 }  // namespace
 
-// tiles of one field for tile shape `shape` (0..3)
+// tiles of one field for tile shape `shape` (0..5)
 uint32_t gradient_tiles(const Grid& g, int shape) {
     switch (shape) {
         case 1: return tiles_of<T1>(g);
         case 2: return tiles_of<T2>(g);
         case 3: return tiles_of<T3>(g);
+        case 4: return tiles_of<T4>(g);
+        case 5: return tiles_of<T5>(g);
         default: return tiles_of<T0>(g);
     }
 }
@@ -439,6 +503,8 @@ hipError_t launch_gradient(int shape, const float* f0, const float* const* fptr,
         case 1: hipLaunchKernelGGL(grad_lowerstar<T1>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
         case 2: hipLaunchKernelGGL(grad_lowerstar<T2>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
         case 3: hipLaunchKernelGGL(grad_lowerstar<T3>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
+        case 4: hipLaunchKernelGGL(grad_lowerstar<T4>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
+        case 5: hipLaunchKernelGGL(grad_lowerstar<T5>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
         default: hipLaunchKernelGGL(grad_lowerstar<T0>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
     }
     return hipGetLastError();

@@ -206,9 +206,13 @@ __global__ __launch_bounds__(BT) void k_minor_rows(const uint8_t* __restrict__ o
     uint32_t jv[4], sv[4];
     uint64_t jm[4], sm[4];
     uint32_t nj = 0, ns = 0;
+    // the four slots of source i: one 4-byte and one 16-byte load
+    const uint32_t t4 = ((const uint32_t*)out_t)[i];
+    const uint4 id4 = ((const uint4*)out_id)[i];
+    const uint32_t ids[4] = {id4.x, id4.y, id4.z, id4.w};
     for (int q = 0; q < 4; q++) {
-        uint8_t t = out_t[4 * i + q];
-        uint32_t id = out_id[4 * i + q];
+        uint8_t t = (uint8_t)(t4 >> (8 * q));
+        uint32_t id = ids[q];
         uint32_t* v = t == T_JUNC ? jv : sv;
         uint64_t* m = t == T_JUNC ? jm : sm;
         uint32_t& n = t == T_JUNC ? nj : ns;

@@ -102,8 +102,8 @@ enum {
     MS_OPT_MERGE_LIGHT = 2,
     MS_OPT_MERGE_CHUNK = 3,
     /* Gradient workgroup tile in vertices: 0 = 16x8x4 (default), 1 = 32x4x4,
-     * 2 = 8x8x8, 3 = 16x16x2, 4 = 16x8x8, 5 = 16x16x8.  Results never depend
-     * on it. */
+     * 2 = 8x8x8, 3 = 16x16x2, 4 = 16x8x8, 5 = 16x16x8, 6 = 32x16x8.  Results
+     * never depend on it. */
     MS_OPT_GRADIENT_TILE = 4
 };
 enum {

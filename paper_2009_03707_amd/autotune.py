@@ -24,7 +24,7 @@ import torch
 from . import msc
 
 DEFAULT = {"tile": 0, "schedule": msc.MS_PATHS_READY, "light": 32, "chunk": 4096}
-TILES = (0, 1, 2, 3, 4, 5)
+TILES = (0, 1, 2, 3, 4, 5, 6)
 SCHEDULES = (msc.MS_PATHS_READY, msc.MS_PATHS_ENTRY, msc.MS_PATHS_POWER)
 LIGHTS = (8, 16, 32, 64, 128)
 CHUNKS = (2048, 4096)

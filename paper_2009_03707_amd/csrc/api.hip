@@ -186,7 +186,7 @@ ms_status ms_ctx_set_option(ms_ctx* ctx, int option, int64_t value) {
         ctx->merge_chunk = (uint32_t)value;
         return MS_OK;
     }
-    if (option == MS_OPT_GRADIENT_TILE && value >= 0 && value <= 5) {
+    if (option == MS_OPT_GRADIENT_TILE && value >= 0 && value <= 6) {
         ctx->grad_tile = (int)value;
         return MS_OK;
     }

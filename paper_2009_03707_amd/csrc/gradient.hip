@@ -12,8 +12,10 @@
 // each side plus one extra vertex on the high side) is staged in LDS as
 // order-preserving integer keys; every vertex of the block and of its
 // high-side halo runs the lower-star pairing in registers with bitmask
-// queues; each cell's nibble is OR-ed into an LDS word tile (each nibble is
-// written by exactly one lower star), which is then stored coalesced.
+// queues, the vertices taken in order of lower-star size so that the lanes
+// of a wave do similar work; each lower star's nibbles are OR-ed into an LDS
+// word tile (each nibble is written by exactly one lower star), which is
+// then stored coalesced.
 #include "common.h"
 
 namespace msc {
@@ -91,19 +93,36 @@ __device__ __forceinline__ uint32_t float_key(uint32_t u) {
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
+template <int J>
+struct Unroll {
+    template <typename F>
+    __device__ __forceinline__ static void run(F&& fn) {
+        Unroll<J - 1>::run(fn);
+        fn(std::integral_constant<int, J - 1>());
+    }
+};
+template <>
+struct Unroll<0> {
+    template <typename F>
+    __device__ __forceinline__ static void run(F&&) {}
+};
+
+// The nibbles of one lower star are collected in registers (cell j at bits
+// 4j..4j+3 of a 128-bit accumulator) and OR-ed into the LDS word tile once
+// per destination word at the end (flush).
 template <class T>
 struct Star {
     static constexpr int OX = T::OX, OY = T::OY, OZ = T::OZ;
     int lx, ly, lz;          // position in the block (0..OX etc.)
     uint32_t* words;         // LDS word tile
     const Tables* tab;
-    __device__ void emit(uint32_t j, uint32_t nib) const {
-        uint32_t d = tab->desc[j];
-        int wx = lx - (int)(d & 1u), wy = ly - (int)((d >> 1) & 1u), wz = lz - (int)((d >> 2) & 1u);
-        if ((unsigned)wx < (unsigned)OX && (unsigned)wy < (unsigned)OY && (unsigned)wz < (unsigned)OZ)
-            atomicOr(&words[wx + OX * (wy + OY * wz)], nib << (4u * (d >> 3)));
+    uint64_t lo = 0, hi = 0;  // nibble of cell j: j < 16 in lo, else in hi
+    __device__ void emit(uint32_t j, uint32_t nib) {
+        const uint64_t v = (uint64_t)nib << (4u * (j & 15u));
+        if (j < 16u) lo |= v;
+        else hi |= v;
     }
-    __device__ void emit_pair(uint32_t a, uint32_t b) const {  // a facet, b cofacet
+    __device__ void emit_pair(uint32_t a, uint32_t b) {  // a facet, b cofacet
         int diff = (int)b - (int)a;
         int ad = diff < 0 ? -diff : diff;
         uint32_t axis = ad == 1 ? 0u : (ad == 3 ? 1u : 2u);
@@ -111,7 +130,23 @@ struct Star {
         emit(a, 1u + 2u * axis + neg);
         emit(b, 1u + 2u * axis + (1u - neg));
     }
-    __device__ void emit_crit(uint32_t j) const { emit(j, NB_CRIT + (tab->desc[j] & 7u)); }
+    __device__ void emit_crit(uint32_t j) { emit(j, NB_CRIT + (tab->desc[j] & 7u)); }
+    // star cell j goes to the word at corner desc(j) & 7, nibble desc(j) >> 3
+    __device__ void flush() {
+        uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        Unroll<27>::run([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr uint32_t d = dest_desc(j);
+            const uint32_t nib = (uint32_t)((j < 16 ? lo >> (4 * j) : hi >> (4 * (j - 16))) & 15u);
+            w[d & 7u] |= nib << (4u * (d >> 3));
+        });
+        Unroll<8>::run([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            const int wx = lx - (c & 1), wy = ly - ((c >> 1) & 1), wz = lz - ((c >> 2) & 1);
+            if (w[c] && (unsigned)wx < (unsigned)OX && (unsigned)wy < (unsigned)OY && (unsigned)wz < (unsigned)OZ)
+                atomicOr(&words[wx + OX * (wy + OY * wz)], w[c]);
+        });
+    }
 };
 
 __device__ __forceinline__ uint32_t ctz32(uint32_t x) { return (uint32_t)__builtin_ctz(x); }
@@ -184,16 +219,23 @@ __device__ __forceinline__ void rank_pair4(uint32_t ka0, uint32_t kb0, uint32_t&
         : "v"(ka0), "v"(kb0), "v"(ka1), "v"(kb1), "v"(ka2), "v"(kb2), "v"(ka3), "v"(kb3));
 }
 
-// argmin of the per-lane cell keys over the set bits of `m` (m != 0)
-__device__ __forceinline__ uint32_t argmin_key(uint32_t m, const uint32_t* kk, int tid) {
-    uint32_t best = 0, bk = 0xFFFFFFFFu;
-    while (m) {
-        uint32_t j = ctz32(m);
-        m &= m - 1;
-        uint32_t k = kk[j * THREADS + tid];
-        if (k < bk) { bk = k; best = j; }
-    }
-    return best;
+constexpr uint32_t ALLC = ((1u << 27) - 1u) & ~(1u << CENTER);  // every star cell but the centre
+
+// argmin of the cell keys over the set bits of m (m != 0, m within CANDS).
+// The keys are packed as (key << 5) | j (keys are below 2^26 and distinct
+// within a lower star), so the minimum also names the cell; the scan is
+// unrolled over the candidate cells with no branch and no memory access.
+template <uint32_t CANDS>
+__device__ __forceinline__ uint32_t argmin_key(uint32_t m, const uint32_t (&pk)[27]) {
+    uint32_t best = 0xFFFFFFFFu;
+    Unroll<27>::run([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (((CANDS >> j) & 1u) != 0) {
+            const uint32_t c = pk[j] | (((m >> j) & 1u) - 1u);  // all ones when j is not in m
+            best = best < c ? best : c;
+        }
+    });
+    return best & 31u;
 }
 
 // cofacets b of x (inside the lower star, unclassified) with exactly one
@@ -209,19 +251,7 @@ __device__ __forceinline__ uint32_t ready_cofacets(uint32_t x, uint32_t LS, uint
     return out;
 }
 
-template <int J>
-struct Unroll {
-    template <typename F>
-    __device__ __forceinline__ static void run(F&& fn) {
-        Unroll<J - 1>::run(fn);
-        fn(std::integral_constant<int, J - 1>());
-    }
-};
-template <>
-struct Unroll<0> {
-    template <typename F>
-    __device__ __forceinline__ static void run(F&&) {}
-};
+
 
 // Number of cells in the lower star of the vertex at fidx (the same test as
 // in lower_star below); used to give each wave vertices of similar work.
@@ -255,7 +285,7 @@ __device__ uint32_t lower_star_size(const uint32_t* fk, int fidx) {
 }
 
 template <class T>
-__device__ void lower_star(const uint32_t* fk, int fidx, const Star<T>& st, uint32_t* kk, int tid) {
+__device__ void lower_star(const uint32_t* fk, int fidx, Star<T>& st) {
     constexpr int FX = T::FX, FY = T::FY;
     uint32_t K[27];
     Unroll<27>::run([&](auto jc) {
@@ -283,6 +313,7 @@ __device__ void lower_star(const uint32_t* fk, int fidx, const Star<T>& st, uint
     });
     if ((LS & EDGES) == 0) {  // no lower neighbour: a minimum
         st.emit_crit(CENTER);
+        st.flush();
         return;
     }
     // rank of every neighbour in the vertex order (ties broken by id, which
@@ -306,6 +337,8 @@ __device__ void lower_star(const uint32_t* fk, int fidx, const Star<T>& st, uint
         constexpr int p = 13 * r + 12;
         rank_pair(K[kPairs.a[p]], K[kPairs.b[p]], rk[kPairs.a[p]], rk[kPairs.b[p]]);
     });
+    uint32_t pk[27];
+    pk[CENTER] = 0xFFFFFFFFu;
     // cell keys: bit set of the ranks of the cell's other vertices; comparing
     // them as integers is the lexicographic comparison of the descending
     // vertex lists with a proper prefix smaller
@@ -317,20 +350,20 @@ __device__ void lower_star(const uint32_t* fk, int fidx, const Star<T>& st, uint
                 constexpr int v = decltype(vc)::value;
                 if constexpr (((vert_mask(j) >> v) & 1u) != 0) key |= 1u << rk[v];
             });
-            kk[j * THREADS + tid] = key;
+            pk[j] = (key << 5) | (uint32_t)j;
         }
     });
     const Tables* tab = st.tab;
     uint32_t C = 1u << CENTER;  // classified cells
     uint32_t E = LS & EDGES;
-    uint32_t delta = argmin_key(E, kk, tid);
+    uint32_t delta = argmin_key<EDGES>(E, pk);
     st.emit_pair(CENTER, delta);
     C |= 1u << delta;
     uint32_t PZ = E & ~(1u << delta);
     uint32_t PO = ready_cofacets(delta, LS, C, tab);
     for (;;) {
         while (PO) {
-            uint32_t a = argmin_key(PO, kk, tid);
+            uint32_t a = argmin_key<ALLC & ~EDGES>(PO, pk);  // only quads and cubes enter PQone
             PO &= ~(1u << a);
             if (C & (1u << a)) continue;
             uint32_t uf = tab->fac[a] & LS & ~C;
@@ -346,12 +379,13 @@ __device__ void lower_star(const uint32_t* fk, int fidx, const Star<T>& st, uint
         }
         PZ &= ~C;
         if (!PZ) break;
-        uint32_t g = argmin_key(PZ, kk, tid);
+        uint32_t g = argmin_key<ALLC>(PZ, pk);
         PZ &= ~(1u << g);
         st.emit_crit(g);
         C |= 1u << g;
         PO |= ready_cofacets(g, LS, C, tab);
     }
+    st.flush();
 }
 
 // One workgroup per tile; tiles of all fields of a batch are numbered
@@ -366,7 +400,6 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
     constexpr int PX = T::PX, PY = T::PY, NPLS = T::NPLS;
     __shared__ uint32_t fk[NF];
     __shared__ uint32_t words[NW];
-    __shared__ uint32_t kk[27 * THREADS];
     __shared__ Tables tab;
     __shared__ uint8_t s_size[NPLS];
     __shared__ uint16_t s_ord[NPLS];
@@ -450,7 +483,7 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
         int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
         Star<T> st{lx, ly, lz, words, &tab};
         int fidx = (lx + 1) + FX * ((ly + 1) + FY * (lz + 1));
-        lower_star(fk, fidx, st, kk, tid);
+        lower_star(fk, fidx, st);
     }
     __syncthreads();
 
@@ -472,6 +505,7 @@ using T2 = Tile<8, 8, 8>;
 using T3 = Tile<16, 16, 2>;
 using T4 = Tile<16, 8, 8>;
 using T5 = Tile<16, 16, 8>;
+using T6 = Tile<32, 16, 8>;
 
 template <class T>
 uint32_t tiles_of(const Grid& g) {
@@ -480,7 +514,7 @@ uint32_t tiles_of(const Grid& g) {
 
 }  // namespace
 
-// tiles of one field for tile shape `shape` (0..5)
+// tiles of one field for tile shape `shape` (0..6)
 uint32_t gradient_tiles(const Grid& g, int shape) {
     switch (shape) {
         case 1: return tiles_of<T1>(g);
@@ -488,6 +522,7 @@ uint32_t gradient_tiles(const Grid& g, int shape) {
         case 3: return tiles_of<T3>(g);
         case 4: return tiles_of<T4>(g);
         case 5: return tiles_of<T5>(g);
+        case 6: return tiles_of<T6>(g);
         default: return tiles_of<T0>(g);
     }
 }
@@ -505,6 +540,7 @@ hipError_t launch_gradient(int shape, const float* f0, const float* const* fptr,
         case 3: hipLaunchKernelGGL(grad_lowerstar<T3>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
         case 4: hipLaunchKernelGGL(grad_lowerstar<T4>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
         case 5: hipLaunchKernelGGL(grad_lowerstar<T5>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
+        case 6: hipLaunchKernelGGL(grad_lowerstar<T6>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
         default: hipLaunchKernelGGL(grad_lowerstar<T0>, gd, bd, 0, s, f0, fptr, geo, tile_off, tt, grad, err); break;
     }
     return hipGetLastError();

@@ -10,8 +10,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=[0, 1, 2, 3, 4, 5],
-                ids=["tile16x8x4", "tile32x4x4", "tile8x8x8", "tile16x16x2", "tile16x8x8", "tile16x16x8"])
+@pytest.fixture(scope="module", params=[0, 1, 2, 3, 4, 5, 6],
+                ids=["tile16x8x4", "tile32x4x4", "tile8x8x8", "tile16x16x2", "tile16x8x8", "tile16x16x8",
+                     "tile32x16x8"])
 def ctx(request):
     """Every gradient workgroup tile shape the autotuner may pick."""
     from paper_2009_03707_amd import msc

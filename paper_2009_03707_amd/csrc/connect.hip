@@ -117,12 +117,10 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out) {
     uint32_t* vb = buf<uint32_t>(c, "tr.vb", nnz);
     uint64_t* tmp = buf<uint64_t>(c, "tr.tmp", radix_tmp_elems(nnz));
     check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, rows, c->stream), "expand rows");
-    bool in_b = false;
-    check(c, radix_sort_u32_from(in.col, ka, va, kb, vb, nnz, bit_width((uint64_t)in.ncols - 1), tmp, &in_b, c->stream),
+    const uint32_t* keys = nullptr;
+    check(c, radix_transpose_u32(in.col, rows, in.val, ka, va, kb, vb, nnz, bit_width((uint64_t)in.ncols - 1), tmp,
+                                 out.col, out.val, &keys, c->stream),
           "sort");
-    const uint32_t* keys = in_b ? kb : ka;
-    const uint32_t* perm = in_b ? vb : va;
-    check(c, launch_gather_t(perm, rows, in.val, out.col, out.val, nnz, c->stream), "gather");
     uint64_t* gtmp = buf<uint64_t>(c, "tr.gaps", key_bounds_tmp_elems(nnz, (uint64_t)in.ncols));
     check(c, launch_key_bounds(keys, nnz, (uint64_t)in.ncols, (uint64_t*)out.rowptr, gtmp, c->stream), "bounds");
 }

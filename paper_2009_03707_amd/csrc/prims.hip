@@ -74,83 +74,120 @@ constexpr int RT = 256;           // threads
 constexpr int RR = 16;            // rounds of RT keys per tile
 constexpr int RTILE = RT * RR;
 constexpr int RWAVES = RT / WAVE;
+constexpr int MAX_DB = 9;         // digit bits: 8, or 9 when that saves a pass
 
-template <typename K>
+template <typename K, int DB>
 __global__ __launch_bounds__(RT) void radix_hist(const K* __restrict__ keys, uint64_t n, int shift, uint64_t nblk,
                                                  uint64_t* __restrict__ hist) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    constexpr uint32_t NB = 1u << DB;
+    __shared__ uint32_t h[NB];
+    for (uint32_t d = threadIdx.x; d < NB; d += RT) h[d] = 0;
     __syncthreads();
     uint64_t base = (uint64_t)blockIdx.x * RTILE;
     for (int r = 0; r < RR; r++) {
         uint64_t j = base + (uint64_t)r * RT + threadIdx.x;
-        if (j < n) atomicAdd(&h[(uint32_t)(keys[j] >> shift) & 255u], 1u);
+        if (j < n) atomicAdd(&h[(uint32_t)(keys[j] >> shift) & (NB - 1u)], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    for (uint32_t d = threadIdx.x; d < NB; d += RT) hist[(uint64_t)d * nblk + blockIdx.x] = h[d];
 }
 
-// One pass of the stable LSD sort over a tile of RTILE keys.  Every key's
-// rank among the keys of the tile with the same digit is found round by
-// round (a round is RT keys in index order; peers by ballot, earlier waves
-// by per-wave digit counts).  The tile is then staged in LDS ordered by
-// (digit, rank), and written out so that the keys of one digit leave as one
-// contiguous run at that digit's global offset for this tile.
-template <typename K>
+// With rows set, the pass is the last one of a transpose: instead of the
+// payload (an entry index p) it writes ocol[g] = rows[p] and oval[g] = val[p].
+struct RadixGather {
+    const uint32_t* rows;
+    const uint64_t* val;
+    uint32_t* ocol;
+    uint64_t* oval;
+};
+
+// One pass of the stable LSD sort over a tile of RTILE keys.  Wave w owns
+// the contiguous quarter [w * RTILE / 4, (w + 1) * RTILE / 4) of the tile and
+// ranks its keys on its own, 64 at a time in index order: peers with the
+// same digit by ballot, earlier ones by the wave's running digit counts in
+// LDS (no workgroup barrier).  The waves' counts are then combined once
+// (keys of wave w follow those of the earlier waves, which keeps the sort
+// stable), the tile is staged in LDS ordered by (digit, rank), and written
+// out so that the keys of one digit leave as one contiguous run at that
+// digit's global offset for this tile.  vals null: the payload is the entry
+// index.
+template <typename K, int DB>
 __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                     K* __restrict__ okeys, uint32_t* __restrict__ ovals, uint64_t n,
-                                                    int shift, uint64_t nblk, const uint64_t* __restrict__ offs) {
-    __shared__ uint64_t gbase[256];
-    __shared__ uint32_t run[256];
-    __shared__ uint32_t tstart[256];
-    __shared__ uint32_t wcnt[RWAVES][256];
+                                                    int shift, uint64_t nblk, const uint64_t* __restrict__ offs,
+                                                    RadixGather fin) {
+    constexpr uint32_t NB = 1u << DB;
+    constexpr uint32_t DPT = NB / RT;       // digits owned by one thread in the tile scan
+    constexpr int WR = RTILE / RWAVES / WAVE;  // rounds of one wave (RR)
+    __shared__ uint64_t gbase[NB];
+    __shared__ uint32_t tstart[NB];
+    __shared__ uint32_t wcnt[RWAVES][NB];
     __shared__ K skey[RTILE];
     __shared__ uint32_t sval[RTILE];
     __shared__ uint32_t sc[RT / WAVE + 1];
     const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
-    gbase[tid] = offs[(uint64_t)tid * nblk + blockIdx.x];
-    run[tid] = 0;
+    for (uint32_t d = tid; d < NB; d += RT) gbase[d] = offs[(uint64_t)d * nblk + blockIdx.x];
+    for (uint32_t i = tid; i < RWAVES * NB; i += RT) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
     const uint64_t lt = (1ull << lane) - 1ull;
-    const uint64_t tbase = (uint64_t)blockIdx.x * RTILE;
-    K kr[RR];
-    uint32_t vr[RR], rk[RR];
+    const uint64_t wbase = (uint64_t)blockIdx.x * RTILE + (uint64_t)w * (RTILE / RWAVES);
+    uint32_t* cnt = wcnt[w];
+    K kr[WR];
+    uint32_t vr[WR], rk[WR];
 #pragma unroll
-    for (int r = 0; r < RR; r++) {
-        for (int i = tid; i < RWAVES * 256; i += RT) (&wcnt[0][0])[i] = 0;
-        __syncthreads();
-        const uint64_t j = tbase + (uint64_t)r * RT + tid;
+    for (int r = 0; r < WR; r++) {
+        const uint64_t j = wbase + (uint64_t)r * WAVE + lane;
         const bool valid = j < n;
         const K key = valid ? keys[j] : (K)0;
         kr[r] = key;
         vr[r] = valid ? (vals ? vals[j] : (uint32_t)j) : 0u;
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t d = (uint32_t)(key >> shift) & (NB - 1u);
         uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; b++) {
+        for (int b = 0; b < DB; b++) {
             uint64_t bb = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? bb : ~bb;
         }
         const uint32_t wrank = (uint32_t)__popcll(peers & lt);
-        if (valid && wrank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        uint32_t pos = run[d] + wrank;
-        for (int q = 0; q < w; q++) pos += wcnt[q][d];
-        rk[r] = pos;
-        __syncthreads();
-        uint32_t add = 0;
-        for (int q = 0; q < RWAVES; q++) add += wcnt[q][tid];
-        run[tid] += add;
-        __syncthreads();  // wcnt is cleared at the top of the next round
+        const uint32_t before = valid ? cnt[d] : 0u;  // every lane reads before any lane writes
+        __builtin_amdgcn_wave_barrier();
+        if (valid && wrank == 0) cnt[d] = before + (uint32_t)__popcll(peers);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        rk[r] = before + wrank;
+    }
+    __syncthreads();
+    // per digit: waves' counts -> exclusive offsets across waves, tile totals
+    uint32_t own = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < DPT; q++) {
+        const uint32_t d = tid * DPT + q;
+        uint32_t run = 0;
+        for (int x = 0; x < RWAVES; x++) {
+            const uint32_t c = wcnt[x][d];
+            wcnt[x][d] = run;
+            run += c;
+        }
+        tstart[d] = run;  // the digit's tile total for now
+        own += run;
     }
     uint32_t tot;
-    const uint32_t ex = block_excl_scan<uint32_t, RT>(run[tid], sc, tot);
-    tstart[tid] = ex;
+    uint32_t ex = block_excl_scan<uint32_t, RT>(own, sc, tot);
+#pragma unroll
+    for (uint32_t q = 0; q < DPT; q++) {
+        const uint32_t d = tid * DPT + q;
+        const uint32_t c = tstart[d];
+        tstart[d] = ex;
+        ex += c;
+    }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < RR; r++) {
-        const uint64_t j = tbase + (uint64_t)r * RT + tid;
+    for (int r = 0; r < WR; r++) {
+        const uint64_t j = wbase + (uint64_t)r * WAVE + lane;
         if (j < n) {
-            const uint32_t p = tstart[(uint32_t)(kr[r] >> shift) & 255u] + rk[r];
+            const uint32_t d = (uint32_t)(kr[r] >> shift) & (NB - 1u);
+            const uint32_t p = tstart[d] + cnt[d] + rk[r];
             skey[p] = kr[r];
             sval[p] = vr[r];
         }
@@ -158,40 +195,58 @@ __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, 
     __syncthreads();
     for (uint32_t i = (uint32_t)tid; i < tot; i += RT) {
         const K key = skey[i];
-        const uint32_t d = (uint32_t)(key >> shift) & 255u;
+        const uint32_t d = (uint32_t)(key >> shift) & (NB - 1u);
         const uint64_t g = gbase[d] + (i - tstart[d]);
         okeys[g] = key;
-        ovals[g] = sval[i];
+        if (fin.rows) {
+            const uint32_t p = sval[i];
+            fin.ocol[g] = fin.rows[p];
+            fin.oval[g] = fin.val[p];
+        } else {
+            ovals[g] = sval[i];
+        }
     }
+}
+
+template <typename K, int DB>
+hipError_t radix_pass(const K* src_k, const uint32_t* src_v, K* dst_k, uint32_t* dst_v, uint64_t n, int sh,
+                      uint64_t nblk, uint64_t* hist, uint64_t* stmp, const RadixGather& fin, hipStream_t s) {
+    hipLaunchKernelGGL((radix_hist<K, DB>), dim3((unsigned)nblk), dim3(RT), 0, s, src_k, n, sh, nblk, hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = scan_impl<uint64_t>(hist, hist, (uint64_t)(1u << DB) * nblk, stmp, (uint64_t*)nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((radix_scatter<K, DB>), dim3((unsigned)nblk), dim3(RT), 0, s, src_k, src_v, dst_k, dst_v, n, sh,
+                       nblk, (const uint64_t*)hist, fin);
+    return hipGetLastError();
 }
 
 // Stable LSD sort.  Pass 0 reads (keys0, vals0) -- vals0 null means the
 // payload is the entry index -- and the passes then alternate between the
-// (ka, va) and (kb, vb) buffers; *in_b tells where the result is.
+// (ka, va) and (kb, vb) buffers; *in_b tells where the result is.  Digits
+// are 8 bits, or 9 when that needs fewer passes.  With fin.rows set, the
+// last pass writes the gathered rows and values instead of the payload.
 template <typename K>
 hipError_t radix_impl(const K* keys0, const uint32_t* vals0, K* ka, uint32_t* va, K* kb, uint32_t* vb, uint64_t n,
-                      int bits, uint64_t* tmp, bool* in_b, hipStream_t s) {
+                      int bits, uint64_t* tmp, bool* in_b, hipStream_t s, RadixGather fin = {}) {
     *in_b = false;
     if (n == 0) return hipSuccess;
+    const int p8 = bits <= 0 ? 1 : (bits + 7) / 8;
+    const int p9 = bits <= 0 ? 1 : (bits + 8) / 9;
+    const bool nine = p9 < p8;
+    const int passes = nine ? p9 : p8;
     uint64_t nblk = (n + RTILE - 1) / RTILE;
     uint64_t* hist = tmp;
-    uint64_t* stmp = tmp + 256 * nblk;
+    uint64_t* stmp = tmp + (uint64_t)(1u << MAX_DB) * nblk;
     const K* src_k = keys0;
     const uint32_t* src_v = vals0;
     K* dst_k = ka;
     uint32_t* dst_v = va;
     bool dst_is_b = false;
-    const int passes = bits <= 0 ? 1 : (bits + 7) / 8;  // at least one pass: the result always lands in a buffer
     for (int p = 0; p < passes; p++) {
-        const int sh = 8 * p;
-        hipLaunchKernelGGL(radix_hist<K>, dim3((unsigned)nblk), dim3(RT), 0, s, src_k, n, sh, nblk, hist);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        e = scan_impl<uint64_t>(hist, hist, 256 * nblk, stmp, (uint64_t*)nullptr, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(radix_scatter<K>, dim3((unsigned)nblk), dim3(RT), 0, s, src_k, src_v, dst_k, dst_v, n, sh,
-                           nblk, (const uint64_t*)hist);
-        e = hipGetLastError();
+        const RadixGather f = p + 1 == passes ? fin : RadixGather{};
+        hipError_t e = nine ? radix_pass<K, 9>(src_k, src_v, dst_k, dst_v, n, 9 * p, nblk, hist, stmp, f, s)
+                            : radix_pass<K, 8>(src_k, src_v, dst_k, dst_v, n, 8 * p, nblk, hist, stmp, f, s);
         if (e != hipSuccess) return e;
         *in_b = dst_is_b;
         src_k = dst_k;
@@ -235,7 +290,7 @@ hipError_t scan_excl_u32_to_u64(const uint32_t* in, uint64_t* out, uint64_t n, u
 size_t radix_tmp_elems(uint64_t n) {
     uint64_t nblk = (n + RTILE - 1) / RTILE;
     if (nblk < 1) nblk = 1;
-    return 256 * nblk + scan_tmp_elems(256 * nblk);
+    return (1u << MAX_DB) * nblk + scan_tmp_elems((1u << MAX_DB) * nblk);
 }
 
 hipError_t radix_sort_u64(uint64_t* ka, uint32_t* va, uint64_t* kb, uint32_t* vb, uint64_t n, int bits,
@@ -256,6 +311,16 @@ hipError_t radix_sort_u32(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb
 hipError_t radix_sort_u32_from(const uint32_t* keys, uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb,
                                uint64_t n, int bits, uint64_t* tmp, bool* in_b, hipStream_t s) {
     return radix_impl<uint32_t>(keys, nullptr, ka, va, kb, vb, n, bits, tmp, in_b, s);
+}
+
+hipError_t radix_transpose_u32(const uint32_t* keys, const uint32_t* rows, const uint64_t* val, uint32_t* ka,
+                               uint32_t* va, uint32_t* kb, uint32_t* vb, uint64_t n, int bits, uint64_t* tmp,
+                               uint32_t* ocol, uint64_t* oval, const uint32_t** sorted_keys, hipStream_t s) {
+    bool in_b = false;
+    hipError_t e = radix_impl<uint32_t>(keys, nullptr, ka, va, kb, vb, n, bits, tmp, &in_b, s,
+                                        RadixGather{rows, val, ocol, oval});
+    *sorted_keys = in_b ? kb : ka;
+    return e;
 }
 
 }  // namespace msc

@@ -588,18 +588,38 @@ __global__ __launch_bounds__(BT) void k_release(const uint32_t* __restrict__ rea
 }
 
 // ---- topological numbering of the junctions ---------------------------------
-// Junctions without predecessors (in-degree from a histogram of B's columns)
+// Junctions without predecessors (in-degree from a histogram of B's
+// columns); a workgroup covers SRC_PER_BLOCK junctions and appends them with
+// one atomic (appends to a single counter serialise, so they are kept few)
+constexpr int SRC_ROUNDS = 8;
+constexpr uint64_t SRC_PER_BLOCK = (uint64_t)BT * SRC_ROUNDS;
+
 __global__ __launch_bounds__(BT) void k_sources(const uint32_t* __restrict__ indeg, uint64_t J,
                                                 uint32_t* __restrict__ out, unsigned long long* __restrict__ n) {
     __shared__ unsigned long long sc[BT / WAVE + 1];
     __shared__ unsigned long long base;
-    uint64_t j = (uint64_t)blockIdx.x * BT + threadIdx.x;
-    unsigned long long is0 = (j < J && indeg[j] == 0u) ? 1ull : 0ull;
+    const int lane = lane_id();
+    const uint64_t j0 = (uint64_t)blockIdx.x * SRC_PER_BLOCK + (uint64_t)(threadIdx.x / WAVE) * (WAVE * SRC_ROUNDS);
+    uint64_t mask[SRC_ROUNDS];
+    unsigned long long cnt = 0;
+#pragma unroll
+    for (int r = 0; r < SRC_ROUNDS; r++) {  // a wave covers WAVE * SRC_ROUNDS consecutive junctions
+        const uint64_t j = j0 + (uint64_t)r * WAVE + lane;
+        mask[r] = __ballot(j < J && indeg[j] == 0u);
+        cnt += (unsigned long long)__popcll(mask[r]);
+    }
+    // cnt is the wave's total on every lane; let lane 0 carry it into the block scan
     unsigned long long tot;
-    unsigned long long ex = block_excl_scan<unsigned long long, BT>(is0, sc, tot);
+    const unsigned long long ex = block_excl_scan<unsigned long long, BT>(lane == 0 ? cnt : 0ull, sc, tot);
     if (threadIdx.x == 0) base = tot ? atomicAdd(n, tot) : 0;
     __syncthreads();
-    if (is0) out[base + ex] = (uint32_t)j;
+    unsigned long long o = base + __shfl(ex, 0, WAVE);
+#pragma unroll
+    for (int r = 0; r < SRC_ROUNDS; r++) {
+        const uint64_t j = j0 + (uint64_t)r * WAVE + lane;
+        if ((mask[r] >> lane) & 1ull) out[o + (uint64_t)__popcll(mask[r] & ((1ull << lane) - 1ull))] = (uint32_t)j;
+        o += (unsigned long long)__popcll(mask[r]);
+    }
 }
 
 __global__ __launch_bounds__(BT) void k_invert(const uint32_t* __restrict__ order, uint64_t n,
@@ -1034,7 +1054,8 @@ hipError_t launch_entry_emit(uint64_t T, const uint32_t* head, const uint64_t* h
 
 hipError_t launch_sources(const uint32_t* indeg, uint64_t J, uint32_t* out, unsigned long long* n, hipStream_t s) {
     if (J == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sources, dim3(grid_blocks(J, BT)), dim3(BT), 0, s, indeg, J, out, n);
+    hipLaunchKernelGGL(k_sources, dim3((unsigned)((J + SRC_PER_BLOCK - 1) / SRC_PER_BLOCK)), dim3(BT), 0, s, indeg, J,
+                       out, n);
     return hipGetLastError();
 }
 

@@ -55,68 +55,98 @@ __device__ __forceinline__ bool quad_edge_partner(const Grid& g, uint32_t qw, ui
     return true;
 }
 
+// Expands one frontier node: its out-edges (new targets into t, visited
+// bits set), out-degree and, for a node with one out-edge, that edge's step.
+__device__ __forceinline__ void bfs_node(uint32_t e, const uint32_t* __restrict__ grad, const Geo& geo,
+                                         uint32_t* __restrict__ vis, uint32_t t[4], uint32_t& nt, uint32_t& outdeg,
+                                         uint32_t& step) {
+    uint32_t w = e >> 3, k = e & 7u;
+    uint32_t a = (uint32_t)__builtin_ctz(k);
+    uint32_t fld = geo.field_of(w);
+    const Grid g = geo.grid(fld);
+    uint32_t c[3];
+    g.coords(w - geo.base(fld), c);
+    CellRef v;
+    bool hv = paired_quad(g, w, k, nib_of(grad[w], k), c, a, v);
+    for (uint32_t b = 0; b < 3; b++) {
+        if (b == a) continue;
+        for (int s = -1; s <= 1; s += 2) {
+            CellRef q;
+            if (!cell_step(g, w, k, c, (int)b, s, q.w, q.k)) continue;
+            if (hv && q.w == v.w && q.k == v.k) continue;
+            uint32_t nq = nib_of(grad[q.w], q.k);
+            if (nq >= NB_CRIT) {
+                outdeg++;
+                step = (2u * b + (s > 0 ? 1u : 0u)) | (nq << 3);
+                continue;
+            }
+            CellRef e2;
+            if (!quad_edge_partner(g, q.w, q.k, nq, e2)) continue;
+            outdeg++;
+            step = (2u * b + (s > 0 ? 1u : 0u)) | (nq << 3);
+            uint32_t bit = 1u << (8u * (e2.w & 3u) + e2.k);
+            uint32_t old = atomicOr(&vis[e2.w >> 2], bit);
+            if (!(old & bit)) t[nt++] = 8u * e2.w + e2.k;
+        }
+    }
+}
+
+// A workgroup expands BFS_NPT * BT frontier nodes (thread: nodes
+// blockIdx * BFS_NPT * BT + r * BT + tid) and appends all their new targets
+// and junctions with one atomic on a packed counter (low 32 bits: frontier,
+// high 32 bits: junctions); appends to one counter serialise, so they are
+// kept few.
+constexpr int BFS_NPT = 4;
+
 __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ cur, uint64_t ncur, int level0,
                                                    const uint32_t* __restrict__ grad, Geo geo,
                                                    uint32_t* __restrict__ vis, uint32_t* __restrict__ next,
                                                    unsigned long long* __restrict__ counts,
                                                    uint32_t* __restrict__ label, uint32_t* __restrict__ jlist) {
-    uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
-    bool valid = i < ncur;
-    uint32_t t[4];
-    uint32_t nt = 0, outdeg = 0, step = 0;
-    uint32_t e = 0;
-    if (valid) {
-        e = cur[i];
-        uint32_t w = e >> 3, k = e & 7u;
-        uint32_t a = (uint32_t)__builtin_ctz(k);
-        uint32_t fld = geo.field_of(w);
-        const Grid g = geo.grid(fld);
-        uint32_t c[3];
-        g.coords(w - geo.base(fld), c);
-        CellRef v;
-        bool hv = paired_quad(g, w, k, nib_of(grad[w], k), c, a, v);
-        for (uint32_t b = 0; b < 3; b++) {
-            if (b == a) continue;
-            for (int s = -1; s <= 1; s += 2) {
-                CellRef q;
-                if (!cell_step(g, w, k, c, (int)b, s, q.w, q.k)) continue;
-                if (hv && q.w == v.w && q.k == v.k) continue;
-                uint32_t nq = nib_of(grad[q.w], q.k);
-                if (nq >= NB_CRIT) {
-                    outdeg++;
-                    step = (2u * b + (s > 0 ? 1u : 0u)) | (nq << 3);
-                    continue;
-                }
-                CellRef e2;
-                if (!quad_edge_partner(g, q.w, q.k, nq, e2)) continue;
-                outdeg++;
-                step = (2u * b + (s > 0 ? 1u : 0u)) | (nq << 3);
-                uint32_t bit = 1u << (8u * (e2.w & 3u) + e2.k);
-                uint32_t old = atomicOr(&vis[e2.w >> 2], bit);
-                if (!(old & bit)) t[nt++] = 8u * e2.w + e2.k;
-            }
+    uint32_t t[BFS_NPT][4];
+    uint32_t nt[BFS_NPT], isj[BFS_NPT], lab[BFS_NPT], e[BFS_NPT];
+    uint32_t snt = 0, sj = 0;
+#pragma unroll
+    for (int r = 0; r < BFS_NPT; r++) {
+        const uint64_t i = ((uint64_t)blockIdx.x * BFS_NPT + r) * BT + threadIdx.x;
+        nt[r] = 0;
+        isj[r] = 0;
+        lab[r] = NOT_JUNCTION;
+        e[r] = 0;
+        if (i < ncur) {
+            uint32_t outdeg = 0, step = 0;
+            e[r] = cur[i];
+            bfs_node(e[r], grad, geo, vis, t[r], nt[r], outdeg, step);
+            isj[r] = (!level0 && outdeg > 1) ? 1u : 0u;
+            lab[r] = level0 ? 0u : (outdeg == 1 ? (SUCC_FLAG | step) : NOT_JUNCTION);
+            if (level0) e[r] = 0xFFFFFFFFu;  // 1-saddles take no label
+        } else {
+            e[r] = 0xFFFFFFFFu;
         }
+        snt += nt[r];
+        sj += isj[r];
     }
-    // append the newly visited edges and number the junctions with one
-    // atomic per workgroup on a packed counter (low 32 bits: frontier,
-    // high 32 bits: junctions)
     __shared__ unsigned long long sc[BT / WAVE + 1];
     __shared__ unsigned long long base;
-    uint32_t isj = (valid && !level0 && outdeg > 1) ? 1u : 0u;
-    unsigned long long packed = (unsigned long long)nt | ((unsigned long long)isj << 32);
+    unsigned long long packed = (unsigned long long)snt | ((unsigned long long)sj << 32);
     unsigned long long tot;
     unsigned long long ex = block_excl_scan<unsigned long long, BT>(packed, sc, tot);
     if (threadIdx.x == 0) base = tot ? atomicAdd(counts, tot) : 0ull;
     __syncthreads();
     uint64_t o = (base & 0xFFFFFFFFull) + (ex & 0xFFFFFFFFull);
-    for (uint32_t q = 0; q < nt; q++) next[o + q] = t[q];
-    if (valid && !level0) {
-        if (isj) {
-            uint32_t jid = (uint32_t)((base >> 32) + (ex >> 32));
-            label[e] = jid;
-            jlist[jid] = e;
-        } else {
-            label[e] = outdeg == 1 ? (SUCC_FLAG | step) : NOT_JUNCTION;
+    uint32_t jid = (uint32_t)((base >> 32) + (ex >> 32));
+#pragma unroll
+    for (int r = 0; r < BFS_NPT; r++) {
+        for (uint32_t q = 0; q < nt[r]; q++) next[o + q] = t[r][q];
+        o += nt[r];
+        if (e[r] != 0xFFFFFFFFu) {
+            if (isj[r]) {
+                label[e[r]] = jid;
+                jlist[jid] = e[r];
+                jid++;
+            } else {
+                label[e[r]] = lab[r];
+            }
         }
     }
 }
@@ -263,7 +293,8 @@ hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, co
                              uint32_t* vis, uint32_t* next, unsigned long long* counts, uint32_t* label,
                              uint32_t* jlist, hipStream_t s) {
     if (ncur == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_blocks(ncur, BT)), dim3(BT), 0, s, cur, ncur, level0 ? 1 : 0, grad, g,
+    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_blocks(ncur, (unsigned)(BT * BFS_NPT))), dim3(BT), 0, s, cur, ncur,
+                       level0 ? 1 : 0, grad, g,
                        vis, next, counts, label, jlist);
     return hipGetLastError();
 }

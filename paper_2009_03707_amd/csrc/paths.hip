@@ -655,8 +655,8 @@ __global__ __launch_bounds__(BT) void k_entry_ub(MergeArgs a, uint64_t* __restri
 
 constexpr int EPT = 4;           // entries per thread of a rank block
 constexpr int EPB = BT * EPT;     // entries per rank block
-constexpr int CW = 512;           // columns per LDS window of a rank block
-constexpr int LCAP = 768;         // list descriptors per LDS window
+constexpr int CW = 256;           // columns per LDS window of a rank block
+constexpr int LCAP = 512;         // list descriptors per LDS window
 
 // bstart[b] = the column holding entry b * EPB: every non-empty column i
 // claims the rank blocks whose first entry lies in [off[i], off[i + 1]).
@@ -686,7 +686,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
     __shared__ uint32_t s_lbase[CW + 1];
     __shared__ uint64_t s_lo[LCAP];  // list start: in the base arrays (list 0) or the A* storage
     __shared__ uint32_t s_len[LCAP];
-    __shared__ uint64_t s_mul[LCAP];
+    __shared__ uint32_t s_mul[LCAP];  // minor multiplicities (at most 4 paths leave a source)
     __shared__ uint32_t s_x[EPB];
     __shared__ uint32_t s_sc[BT / WAVE + 1];
     __shared__ uint32_t s_nused;
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
                     const uint32_t p = a.pcol[pq];
                     s_lo[lb + q] = a.aoff[p];
                     s_len[lb + q] = a.alen[p];
-                    s_mul[lb + q] = a.pval[pq];
+                    s_mul[lb + q] = (uint32_t)a.pval[pq];
                 }
             }
         }

@@ -94,6 +94,11 @@ struct Geo {
 
 __device__ inline uint32_t nib_of(uint32_t word, uint32_t k) { return (word >> (4u * k)) & 15u; }
 
+// Slot of cell (w, k) in the per-cell label array of edges and quads
+// (1 <= k <= 6): one plane of nv words per cell type k, so labels of
+// neighbouring cells of one type share cache lines.
+__device__ inline uint64_t label_slot(uint32_t w, uint32_t k, uint32_t nv) { return (uint64_t)(k - 1u) * nv + w; }
+
 // p[i] for a pointer known to address device memory but taken from a table
 // (the compiler cannot infer that itself and would use generic loads).
 template <typename T>

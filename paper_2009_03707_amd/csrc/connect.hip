@@ -504,7 +504,7 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
     // ---- saddle-extremum arcs ------------------------------------------------
     uint32_t* Pv = buf<uint32_t>(c, "pv", g.nv);
     uint32_t* Pc = buf<uint32_t>(c, "pc", g.nv);
-    uint32_t* label = buf<uint32_t>(c, "cell_label", (uint64_t)8 * g.nv);
+    uint32_t* label = buf<uint32_t>(c, "cell_label", (uint64_t)6 * g.nv);  // planes of edges and quads
     check(c, launch_pj_init(grad, g, Pv, Pc, d_err, s), "pj init");
     check(c, launch_label(crit, cnt, grad, g, Pv, Pc, label, d_err, s), "label");
     check_err_flag(c, d_err, "critical list labelling");

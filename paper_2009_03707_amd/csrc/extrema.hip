@@ -87,7 +87,7 @@ __global__ __launch_bounds__(BT) void k_label(const uint32_t* __restrict__ crit,
     uint32_t rank = (uint32_t)(i - start);
     if (idx == 0) Pv[w] = ROOT_FLAG | rank;
     else if (idx == 3) Pc[w] = ROOT_FLAG | rank;
-    else if (idx == 2) label[id] = rank;
+    else if (idx == 2) label[label_slot(w, k, g.nv)] = rank;
 }
 
 // One jump for every unfinished pointer.  `changed` holds 64 words; a

@@ -141,11 +141,11 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
         o += nt[r];
         if (e[r] != 0xFFFFFFFFu) {
             if (isj[r]) {
-                label[e[r]] = jid;
+                label[label_slot(e[r] >> 3, e[r] & 7u, geo.nv)] = jid;
                 jlist[jid] = e[r];
                 jid++;
             } else {
-                label[e[r]] = lab[r];
+                label[label_slot(e[r] >> 3, e[r] & 7u, geo.nv)] = lab[r];
             }
         }
     }
@@ -188,12 +188,12 @@ __global__ __launch_bounds__(BT) void k_minor_trace(const uint32_t* __restrict__
             }
             if (nq >= NB_CRIT) {
                 typ = T_S2;
-                id = label[8u * q.w + q.k];
+                id = label[label_slot(q.w, q.k, geo.nv)];
                 break;
             }
             CellRef e2;
             if (!quad_edge_partner(g, q.w, q.k, nq, e2)) break;  // paired with a cube: dead end
-            const uint32_t lab = label[8u * e2.w + e2.k];
+            const uint32_t lab = label[label_slot(e2.w, e2.k, geo.nv)];
             if (!(lab & SUCC_FLAG)) {
                 typ = T_JUNC;
                 id = lab;
@@ -233,57 +233,67 @@ __global__ __launch_bounds__(BT) void k_minor_rows(const uint8_t* __restrict__ o
                                                    uint32_t* __restrict__ colBs, uint64_t* __restrict__ valBs) {
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= NS) return;
-    uint32_t jv[4], sv[4];
-    uint64_t jm[4], sm[4];
-    uint32_t nj = 0, ns = 0;
     // the four slots of source i: one 4-byte and one 16-byte load
     const uint32_t t4 = ((const uint32_t*)out_t)[i];
     const uint4 id4 = ((const uint4*)out_id)[i];
     const uint32_t ids[4] = {id4.x, id4.y, id4.z, id4.w};
+    // keys (type, id), empty slots last, sorted by a five-comparator network:
+    // equal targets become runs, junction targets precede 2-saddle targets,
+    // and ids ascend within each
+    uint64_t kk[4];
+#pragma unroll
     for (int q = 0; q < 4; q++) {
-        uint8_t t = (uint8_t)(t4 >> (8 * q));
-        uint32_t id = ids[q];
-        uint32_t* v = t == T_JUNC ? jv : sv;
-        uint64_t* m = t == T_JUNC ? jm : sm;
-        uint32_t& n = t == T_JUNC ? nj : ns;
-        if (t == T_NONE) continue;
-        // insert keeping ascending order and merging repeats
-        uint32_t p = 0;
-        while (p < n && v[p] < id) p++;
-        if (p < n && v[p] == id) {
-            m[p] += 1;
-            continue;
+        const uint32_t t = (t4 >> (8 * q)) & 0xffu;
+        kk[q] = t == T_NONE ? ~0ull : ((uint64_t)t << 32) | ids[q];
+    }
+    auto cswap = [&](int x, int y) {
+        const uint64_t lo = kk[x] < kk[y] ? kk[x] : kk[y];
+        const uint64_t hi = kk[x] < kk[y] ? kk[y] : kk[x];
+        kk[x] = lo;
+        kk[y] = hi;
+    };
+    cswap(0, 1);
+    cswap(2, 3);
+    cswap(0, 2);
+    cswap(1, 3);
+    cswap(1, 2);
+    uint32_t nj = 0, ns = 0;
+    uint32_t *cJ = nullptr, *cS = nullptr;
+    uint64_t *vJ = nullptr, *vS = nullptr;
+    uint64_t oJ = 0, oS = 0;
+    if (FILL) {
+        if (i < S1) {
+            cJ = colA; vJ = valA; oJ = rpA[i];
+            cS = colD; vS = valD; oS = rpD[i];
+        } else {
+            cJ = colB; vJ = valB; oJ = rpB[i - S1];
+            cS = colBs; vS = valBs; oS = rpBs[i - S1];
         }
-        for (uint32_t r = n; r > p; r--) {
-            v[r] = v[r - 1];
-            m[r] = m[r - 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        if (kk[q] == ~0ull || (q > 0 && kk[q] == kk[q - 1])) continue;  // empty, or not a run's first
+        uint64_t m = 0;
+#pragma unroll
+        for (int r = q; r < 4; r++) m += kk[r] == kk[q] ? 1u : 0u;
+        const uint32_t id = (uint32_t)kk[q];
+        if ((uint32_t)(kk[q] >> 32) == T_JUNC) {
+            if (FILL) {
+                cJ[oJ + nj] = id;
+                vJ[oJ + nj] = m;
+            }
+            nj++;
+        } else {
+            if (FILL) {
+                cS[oS + ns] = id;
+                vS[oS + ns] = m;
+            }
+            ns++;
         }
-        v[p] = id;
-        m[p] = 1;
-        n++;
     }
     if (!FILL) {
         cj[i] = nj;
         cs[i] = ns;
-        return;
-    }
-    uint32_t *cJ, *cS;
-    uint64_t *vJ, *vS;
-    uint64_t oJ, oS;
-    if (i < S1) {
-        cJ = colA; vJ = valA; oJ = rpA[i];
-        cS = colD; vS = valD; oS = rpD[i];
-    } else {
-        cJ = colB; vJ = valB; oJ = rpB[i - S1];
-        cS = colBs; vS = valBs; oS = rpBs[i - S1];
-    }
-    for (uint32_t q = 0; q < nj; q++) {
-        cJ[oJ + q] = jv[q];
-        vJ[oJ + q] = jm[q];
-    }
-    for (uint32_t q = 0; q < ns; q++) {
-        cS[oS + q] = sv[q];
-        vS[oS + q] = sm[q];
     }
 }
 

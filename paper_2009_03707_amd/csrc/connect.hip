@@ -115,11 +115,13 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out) {
     uint32_t* kb = buf<uint32_t>(c, "tr.kb", nnz);
     uint32_t* va = buf<uint32_t>(c, "tr.va", nnz);
     uint32_t* vb = buf<uint32_t>(c, "tr.vb", nnz);
+    uint64_t* wa = buf<uint64_t>(c, "tr.wa", nnz);
+    uint64_t* wb = buf<uint64_t>(c, "tr.wb", nnz);
     uint64_t* tmp = buf<uint64_t>(c, "tr.tmp", radix_tmp_elems(nnz));
     check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, rows, c->stream), "expand rows");
     const uint32_t* keys = nullptr;
-    check(c, radix_transpose_u32(in.col, rows, in.val, ka, va, kb, vb, nnz, bit_width((uint64_t)in.ncols - 1), tmp,
-                                 out.col, out.val, &keys, c->stream),
+    check(c, radix_transpose_u32(in.col, rows, (const uint64_t*)in.val, ka, va, kb, vb, wa, wb, nnz,
+                                 bit_width((uint64_t)in.ncols - 1), tmp, out.col, (uint64_t*)out.val, &keys, c->stream),
           "sort");
     uint64_t* gtmp = buf<uint64_t>(c, "tr.gaps", key_bounds_tmp_elems(nnz, (uint64_t)in.ncols));
     check(c, launch_key_bounds(keys, nnz, (uint64_t)in.ncols, (uint64_t*)out.rowptr, gtmp, c->stream), "bounds");

@@ -67,11 +67,13 @@ hipError_t radix_sort_u32(uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b, 
                           int bits, uint64_t* tmp, bool* result_in_b, hipStream_t s);
 // Transpose of a CSR by a stable sort of its column ids `keys` (left
 // intact): the sorted keys land in (a) or (b) (*sorted_keys), and for the
-// entry p at sorted position g the last pass writes ocol[g] = rows[p] (the
-// entry's row) and oval[g] = val[p].
+// entry p at sorted position g, ocol[g] = rows[p] (the entry's row) and
+// oval[g] = val[p].  Rows and values move with the keys through every pass
+// (wa, wb: n uint64 each), so every pass reads and writes in streams.
 hipError_t radix_transpose_u32(const uint32_t* keys, const uint32_t* rows, const uint64_t* val, uint32_t* ka,
-                               uint32_t* va, uint32_t* kb, uint32_t* vb, uint64_t n, int bits, uint64_t* tmp,
-                               uint32_t* ocol, uint64_t* oval, const uint32_t** sorted_keys, hipStream_t s);
+                               uint32_t* va, uint32_t* kb, uint32_t* vb, uint64_t* wa, uint64_t* wb, uint64_t n,
+                               int bits, uint64_t* tmp, uint32_t* ocol, uint64_t* oval, const uint32_t** sorted_keys,
+                               hipStream_t s);
 // Same, reading the keys from `keys` (left intact) with the entry index as
 // payload; the result lands in (a) or (b).
 hipError_t radix_sort_u32_from(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,

@@ -92,13 +92,11 @@ __global__ __launch_bounds__(RT) void radix_hist(const K* __restrict__ keys, uin
     for (uint32_t d = threadIdx.x; d < NB; d += RT) hist[(uint64_t)d * nblk + blockIdx.x] = h[d];
 }
 
-// With rows set, the pass is the last one of a transpose: instead of the
-// payload (an entry index p) it writes ocol[g] = rows[p] and oval[g] = val[p].
-struct RadixGather {
-    const uint32_t* rows;
-    const uint64_t* val;
-    uint32_t* ocol;
-    uint64_t* oval;
+// An optional 64-bit side payload permuted along with the keys (the values
+// of a transposed matrix): read from win, written to wout.
+struct Wide {
+    const uint64_t* win;
+    uint64_t* wout;
 };
 
 // One pass of the stable LSD sort over a tile of RTILE keys.  Wave w owns
@@ -110,20 +108,24 @@ struct RadixGather {
 // stable), the tile is staged in LDS ordered by (digit, rank), and written
 // out so that the keys of one digit leave as one contiguous run at that
 // digit's global offset for this tile.  vals null: the payload is the entry
-// index.
+// index.  With a side payload (wd.win set) the same LDS then stages the
+// 64-bit side values, read again in the input order, and writes them in
+// the same runs.
 template <typename K, int DB>
 __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                     K* __restrict__ okeys, uint32_t* __restrict__ ovals, uint64_t n,
                                                     int shift, uint64_t nblk, const uint64_t* __restrict__ offs,
-                                                    RadixGather fin) {
+                                                    Wide wd) {
     constexpr uint32_t NB = 1u << DB;
     constexpr uint32_t DPT = NB / RT;       // digits owned by one thread in the tile scan
     constexpr int WR = RTILE / RWAVES / WAVE;  // rounds of one wave (RR)
     __shared__ uint64_t gbase[NB];
     __shared__ uint32_t tstart[NB];
     __shared__ uint32_t wcnt[RWAVES][NB];
-    __shared__ K skey[RTILE];
-    __shared__ uint32_t sval[RTILE];
+    // staged keys and payloads; reused for the side payload as RTILE uint64
+    __shared__ uint64_t sstage[RTILE * (sizeof(K) + 4) / 8];
+    K* skey = (K*)sstage;
+    uint32_t* sval = (uint32_t*)(skey + RTILE);
     __shared__ uint32_t sc[RT / WAVE + 1];
     const int tid = threadIdx.x, lane = lane_id(), w = tid / WAVE;
     for (uint32_t d = tid; d < NB; d += RT) gbase[d] = offs[(uint64_t)d * nblk + blockIdx.x];
@@ -134,13 +136,20 @@ __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, 
     uint32_t* cnt = wcnt[w];
     K kr[WR];
     uint32_t vr[WR], rk[WR];
+    // all of the wave's loads first: the ranking below is ordered by fences,
+    // which would otherwise hold each round's load until the previous round
 #pragma unroll
     for (int r = 0; r < WR; r++) {
         const uint64_t j = wbase + (uint64_t)r * WAVE + lane;
         const bool valid = j < n;
-        const K key = valid ? keys[j] : (K)0;
-        kr[r] = key;
+        kr[r] = valid ? keys[j] : (K)0;
         vr[r] = valid ? (vals ? vals[j] : (uint32_t)j) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < WR; r++) {
+        const uint64_t j = wbase + (uint64_t)r * WAVE + lane;
+        const bool valid = j < n;
+        const K key = kr[r];
         const uint32_t d = (uint32_t)(key >> shift) & (NB - 1u);
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -198,37 +207,56 @@ __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, 
         const uint32_t d = (uint32_t)(key >> shift) & (NB - 1u);
         const uint64_t g = gbase[d] + (i - tstart[d]);
         okeys[g] = key;
-        if (fin.rows) {
-            const uint32_t p = sval[i];
-            fin.ocol[g] = fin.rows[p];
-            fin.oval[g] = fin.val[p];
-        } else {
-            ovals[g] = sval[i];
+        ovals[g] = sval[i];
+    }
+    if (!wd.win) return;  // uniform
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < WR; r++) {
+        const uint64_t j = wbase + (uint64_t)r * WAVE + lane;
+        if (j < n) {
+            const uint32_t d = (uint32_t)(kr[r] >> shift) & (NB - 1u);
+            sstage[tstart[d] + cnt[d] + rk[r]] = wd.win[j];
         }
+    }
+    __syncthreads();
+    for (uint32_t i = (uint32_t)tid; i < tot; i += RT) {
+        // the digit of staged slot i: the last digit whose tile start is <= i
+        uint32_t lo = 0, hi = NB;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (tstart[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        // (empty digits share their start with the next one: take the last of them)
+        wd.wout[gbase[lo] + (i - tstart[lo])] = sstage[i];
     }
 }
 
 template <typename K, int DB>
 hipError_t radix_pass(const K* src_k, const uint32_t* src_v, K* dst_k, uint32_t* dst_v, uint64_t n, int sh,
-                      uint64_t nblk, uint64_t* hist, uint64_t* stmp, const RadixGather& fin, hipStream_t s) {
+                      uint64_t nblk, uint64_t* hist, uint64_t* stmp, const Wide& wd, hipStream_t s) {
     hipLaunchKernelGGL((radix_hist<K, DB>), dim3((unsigned)nblk), dim3(RT), 0, s, src_k, n, sh, nblk, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = scan_impl<uint64_t>(hist, hist, (uint64_t)(1u << DB) * nblk, stmp, (uint64_t*)nullptr, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((radix_scatter<K, DB>), dim3((unsigned)nblk), dim3(RT), 0, s, src_k, src_v, dst_k, dst_v, n, sh,
-                       nblk, (const uint64_t*)hist, fin);
+                       nblk, (const uint64_t*)hist, wd);
     return hipGetLastError();
 }
 
 // Stable LSD sort.  Pass 0 reads (keys0, vals0) -- vals0 null means the
 // payload is the entry index -- and the passes then alternate between the
-// (ka, va) and (kb, vb) buffers; *in_b tells where the result is.  Digits
-// are 8 bits, or 9 when that needs fewer passes.  With fin.rows set, the
-// last pass writes the gathered rows and values instead of the payload.
+// (ka, va) and (kb, vb) buffers; *in_b tells where the keys end.  Digits
+// are 8 bits, or 9 when that needs fewer passes.  With w0 set, a 64-bit
+// side payload moves along, from w0 through (wa, wb).  With last_v set, the
+// last pass writes the payload to last_v and the side payload to last_w.
 template <typename K>
 hipError_t radix_impl(const K* keys0, const uint32_t* vals0, K* ka, uint32_t* va, K* kb, uint32_t* vb, uint64_t n,
-                      int bits, uint64_t* tmp, bool* in_b, hipStream_t s, RadixGather fin = {}) {
+                      int bits, uint64_t* tmp, bool* in_b, hipStream_t s, const uint64_t* w0 = nullptr,
+                      uint64_t* wa = nullptr, uint64_t* wb = nullptr, uint32_t* last_v = nullptr,
+                      uint64_t* last_w = nullptr) {
     *in_b = false;
     if (n == 0) return hipSuccess;
     const int p8 = bits <= 0 ? 1 : (bits + 7) / 8;
@@ -240,19 +268,25 @@ hipError_t radix_impl(const K* keys0, const uint32_t* vals0, K* ka, uint32_t* va
     uint64_t* stmp = tmp + (uint64_t)(1u << MAX_DB) * nblk;
     const K* src_k = keys0;
     const uint32_t* src_v = vals0;
+    const uint64_t* src_w = w0;
     K* dst_k = ka;
     uint32_t* dst_v = va;
+    uint64_t* dst_w = wa;
     bool dst_is_b = false;
     for (int p = 0; p < passes; p++) {
-        const RadixGather f = p + 1 == passes ? fin : RadixGather{};
-        hipError_t e = nine ? radix_pass<K, 9>(src_k, src_v, dst_k, dst_v, n, 9 * p, nblk, hist, stmp, f, s)
-                            : radix_pass<K, 8>(src_k, src_v, dst_k, dst_v, n, 8 * p, nblk, hist, stmp, f, s);
+        const bool last = p + 1 == passes;
+        uint32_t* pv = last && last_v ? last_v : dst_v;
+        const Wide wd{src_w, last && last_w ? last_w : dst_w};
+        hipError_t e = nine ? radix_pass<K, 9>(src_k, src_v, dst_k, pv, n, 9 * p, nblk, hist, stmp, wd, s)
+                            : radix_pass<K, 8>(src_k, src_v, dst_k, pv, n, 8 * p, nblk, hist, stmp, wd, s);
         if (e != hipSuccess) return e;
         *in_b = dst_is_b;
         src_k = dst_k;
         src_v = dst_v;
+        src_w = w0 ? dst_w : nullptr;
         dst_k = dst_is_b ? ka : kb;
         dst_v = dst_is_b ? va : vb;
+        dst_w = dst_is_b ? wa : wb;
         dst_is_b = !dst_is_b;
     }
     return hipSuccess;
@@ -314,11 +348,11 @@ hipError_t radix_sort_u32_from(const uint32_t* keys, uint32_t* ka, uint32_t* va,
 }
 
 hipError_t radix_transpose_u32(const uint32_t* keys, const uint32_t* rows, const uint64_t* val, uint32_t* ka,
-                               uint32_t* va, uint32_t* kb, uint32_t* vb, uint64_t n, int bits, uint64_t* tmp,
-                               uint32_t* ocol, uint64_t* oval, const uint32_t** sorted_keys, hipStream_t s) {
+                               uint32_t* va, uint32_t* kb, uint32_t* vb, uint64_t* wa, uint64_t* wb, uint64_t n,
+                               int bits, uint64_t* tmp, uint32_t* ocol, uint64_t* oval, const uint32_t** sorted_keys,
+                               hipStream_t s) {
     bool in_b = false;
-    hipError_t e = radix_impl<uint32_t>(keys, nullptr, ka, va, kb, vb, n, bits, tmp, &in_b, s,
-                                        RadixGather{rows, val, ocol, oval});
+    hipError_t e = radix_impl<uint32_t>(keys, rows, ka, va, kb, vb, n, bits, tmp, &in_b, s, val, wa, wb, ocol, oval);
     *sorted_keys = in_b ? kb : ka;
     return e;
 }

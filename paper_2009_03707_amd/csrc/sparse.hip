@@ -33,8 +33,11 @@ __global__ __launch_bounds__(BT) void k_hist(const uint32_t* __restrict__ keys, 
 
 // rowptr[k] = first position of a key >= k in the sorted keys (n + 1
 // threads; thread e fills the keys between keys[e - 1] and keys[e]).  Gaps
-// longer than GAP_INLINE are queued and filled by a whole workgroup each.
+// longer than GAP_INLINE are queued in chunks of at most GAP_CHUNK keys,
+// each filled by one wave.
 constexpr uint64_t GAP_INLINE = 64;
+constexpr uint64_t GAP_CHUNK = 4096;
+constexpr unsigned GAP_BLOCKS = 1024;
 
 __global__ __launch_bounds__(BT) void k_key_bounds(const uint32_t* __restrict__ keys, uint64_t n, uint64_t nkeys,
                                                    uint64_t* __restrict__ rowptr, uint64_t* __restrict__ gaps,
@@ -44,10 +47,15 @@ __global__ __launch_bounds__(BT) void k_key_bounds(const uint32_t* __restrict__ 
     const uint64_t lo = e == 0 ? 0 : (uint64_t)keys[e - 1] + 1;
     const uint64_t hi = e == n ? nkeys : (uint64_t)keys[e];
     if (hi + 1 > lo + GAP_INLINE) {
-        const unsigned long long g = atomicAdd(ngaps, 1ull);
-        gaps[3 * g] = lo;
-        gaps[3 * g + 1] = hi;
-        gaps[3 * g + 2] = e;
+        // hi - lo + 1 > GAP_INLINE keys: at most (hi - lo + 1) / GAP_INLINE chunks
+        const uint64_t nch = (hi - lo + GAP_CHUNK) / GAP_CHUNK;
+        const unsigned long long g = atomicAdd(ngaps, (unsigned long long)nch);
+        for (uint64_t c = 0; c < nch; c++) {
+            const uint64_t a = lo + c * GAP_CHUNK;
+            gaps[3 * (g + c)] = a;
+            gaps[3 * (g + c) + 1] = a + GAP_CHUNK - 1 < hi ? a + GAP_CHUNK - 1 : hi;
+            gaps[3 * (g + c) + 2] = e;
+        }
         return;
     }
     for (uint64_t k = lo; k <= hi; k++) rowptr[k] = e;
@@ -57,9 +65,12 @@ __global__ __launch_bounds__(BT) void k_fill_gaps(const uint64_t* __restrict__ g
                                                   const unsigned long long* __restrict__ ngaps,
                                                   uint64_t* __restrict__ rowptr) {
     const uint64_t ng = *ngaps;
-    for (uint64_t g = blockIdx.x; g < ng; g += gridDim.x) {
+    const uint64_t waves = (uint64_t)gridDim.x * (BT / WAVE);
+    const uint64_t gw = (uint64_t)blockIdx.x * (BT / WAVE) + threadIdx.x / WAVE;
+    const uint32_t lane = threadIdx.x % WAVE;
+    for (uint64_t g = gw; g < ng; g += waves) {
         const uint64_t lo = gaps[3 * g], hi = gaps[3 * g + 1], v = gaps[3 * g + 2];
-        for (uint64_t k = lo + threadIdx.x; k <= hi; k += BT) rowptr[k] = v;
+        for (uint64_t k = lo + lane; k <= hi; k += WAVE) rowptr[k] = v;
     }
 }
 
@@ -160,7 +171,7 @@ hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, u
     hipLaunchKernelGGL(k_key_bounds, dim3(grid_blocks(n + 1, BT)), dim3(BT), 0, s, keys, n, nkeys, rowptr, tmp + 1, ng);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fill_gaps, dim3(256), dim3(BT), 0, s, (const uint64_t*)(tmp + 1),
+    hipLaunchKernelGGL(k_fill_gaps, dim3(GAP_BLOCKS), dim3(BT), 0, s, (const uint64_t*)(tmp + 1),
                        (const unsigned long long*)ng, rowptr);
     return hipGetLastError();
 }

@@ -40,7 +40,12 @@ hipError_t launch_esc_expand(const uint32_t* xrow, const uint32_t* xcol, const u
 hipError_t launch_count_sat(const uint64_t* v, uint64_t n, unsigned long long* out, hipStream_t s);
 hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Geo& g,
                              uint32_t* vis, uint32_t* next, unsigned long long* counts, uint32_t* label,
-                             uint32_t* jlist, hipStream_t s);
+                             hipStream_t s);
+size_t junction_blocks(uint64_t nv);
+hipError_t launch_junc_count(const uint32_t* vis, const uint32_t* label, uint64_t nv, uint64_t* bcount,
+                             hipStream_t s);
+hipError_t launch_junc_emit(const uint32_t* vis, uint32_t* label, uint64_t nv, const uint64_t* boff, uint32_t* jlist,
+                            hipStream_t s);
 hipError_t launch_minor_trace(const uint32_t* s1, uint64_t S1, const uint32_t* jlist, uint64_t J, const uint32_t* grad,
                               const Geo& g, const uint32_t* label, uint64_t max_steps, uint64_t S2, uint8_t* out_t,
                               uint32_t* out_id, int* err, hipStream_t s);
@@ -568,10 +573,9 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
         while (ncur > 0) {
             uint32_t* cur = buf<uint32_t>(c, cur_name, ncur);
             uint32_t* nxt = buf<uint32_t>(c, nxt_name, 4 * ncur);
-            uint32_t* jlist = buf_keep<uint32_t>(c, "jlist", J + ncur + 1, J);
             uint64_t init = J << 32;
             check(c, hipMemcpyAsync(d_cnt, &init, 8, hipMemcpyHostToDevice, s), "counter init");
-            check(c, launch_bfs_expand(cur, ncur, level0, grad, g, vis, nxt, d_cnt, label, jlist, s), "bfs expand");
+            check(c, launch_bfs_expand(cur, ncur, level0, grad, g, vis, nxt, d_cnt, label, s), "bfs expand");
             uint64_t h = readback(c, (const uint64_t*)d_cnt, 1)[0];
             uint64_t nn = h & 0xFFFFFFFFull;
             J = h >> 32;
@@ -587,10 +591,21 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
     st.reachable = (int64_t)reach;
     st.junctions = (int64_t)J;
 
+    // junctions numbered in cell order (jlist: id -> cell; their labels get the ids)
+    uint32_t* jlist = buf<uint32_t>(c, "jlist", J + 1);
+    {
+        const uint64_t nb = junction_blocks(g.nv);
+        uint64_t* bc = buf<uint64_t>(c, "junc_blocks", nb + 1);
+        uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(nb) + 1);
+        check(c, launch_junc_count(vis, label, g.nv, bc, s), "junction count");
+        check(c, scan_excl_u64(bc, bc, nb, stmp, bc + nb, s), "scan");
+        if (read_u64(c, bc + nb) != J) fail(c, MS_ERR_INTERNAL, "junction count differs from the search's");
+        check(c, launch_junc_emit(vis, label, g.nv, bc, jlist, s), "junction numbering");
+    }
+
     mark(c, 4);
     // ---- DAG minor ----------------------------------------------------------
     const uint64_t NS = S1 + J;
-    uint32_t* jlist = buf<uint32_t>(c, "jlist", J + 1);
     uint8_t* out_t = buf<uint8_t>(c, "minor_t", 4 * NS);
     uint32_t* out_id = buf<uint32_t>(c, "minor_id", 4 * NS);
     check(c, launch_minor_trace(s1, S1, jlist, J, grad, g, label, max_nodes, S2, out_t, out_id, d_err, s), "minor trace");

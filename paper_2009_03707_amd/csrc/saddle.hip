@@ -102,7 +102,7 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
                                                    const uint32_t* __restrict__ grad, Geo geo,
                                                    uint32_t* __restrict__ vis, uint32_t* __restrict__ next,
                                                    unsigned long long* __restrict__ counts,
-                                                   uint32_t* __restrict__ label, uint32_t* __restrict__ jlist) {
+                                                   uint32_t* __restrict__ label) {
     uint32_t t[BFS_NPT][4];
     uint32_t nt[BFS_NPT], isj[BFS_NPT], lab[BFS_NPT], e[BFS_NPT];
     uint32_t snt = 0, sj = 0;
@@ -134,18 +134,77 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
     if (threadIdx.x == 0) base = tot ? atomicAdd(counts, tot) : 0ull;
     __syncthreads();
     uint64_t o = (base & 0xFFFFFFFFull) + (ex & 0xFFFFFFFFull);
-    uint32_t jid = (uint32_t)((base >> 32) + (ex >> 32));
 #pragma unroll
     for (int r = 0; r < BFS_NPT; r++) {
         for (uint32_t q = 0; q < nt[r]; q++) next[o + q] = t[r][q];
         o += nt[r];
-        if (e[r] != 0xFFFFFFFFu) {
-            if (isj[r]) {
-                label[label_slot(e[r] >> 3, e[r] & 7u, geo.nv)] = jid;
-                jlist[jid] = e[r];
-                jid++;
-            } else {
-                label[label_slot(e[r] >> 3, e[r] & 7u, geo.nv)] = lab[r];
+        // a junction is marked with id 0 here; junctions are numbered in
+        // cell order once the search is complete
+        if (e[r] != 0xFFFFFFFFu) label[label_slot(e[r] >> 3, e[r] & 7u, geo.nv)] = isj[r] ? 0u : lab[r];
+    }
+}
+
+// Junction numbering in cell order, so that the sources of the DAG minor
+// (1-saddles, then junctions) are both in cell order and the tracing from
+// neighbouring sources shares cache lines.  A junction is a visited edge
+// (every visited cell is a non-critical edge) whose label is below
+// SUCC_FLAG.  One thread per word of the visited bits (4 vertices, 12 edge
+// cells, all their label loads issued together); k_junc_count counts per
+// workgroup, k_junc_emit (with the counts scanned) writes jlist and the
+// final ids.
+constexpr uint32_t JVPT = 4;  // vertices per thread (one visited word)
+
+// bit 3 * v + (slot of k) for vertex 4 * t + v and edge type k = 1, 2, 4
+__device__ __forceinline__ uint32_t junction_bits(const uint32_t* __restrict__ vis,
+                                                  const uint32_t* __restrict__ label, uint32_t nv, uint32_t t) {
+    const uint32_t vw = vis[t];
+    uint32_t lab[JVPT][3];
+#pragma unroll
+    for (uint32_t v = 0; v < JVPT; v++) {
+        const uint32_t w = JVPT * t + v;
+#pragma unroll
+        for (uint32_t q = 0; q < 3; q++) {
+            const uint32_t k = 1u << q;
+            lab[v][q] = w < nv && ((vw >> (8u * v + k)) & 1u) ? label[label_slot(w, k, nv)] : SUCC_FLAG;
+        }
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (uint32_t v = 0; v < JVPT; v++)
+#pragma unroll
+        for (uint32_t q = 0; q < 3; q++)
+            if (lab[v][q] < SUCC_FLAG) m |= 1u << (3u * v + q);
+    return m;
+}
+
+__global__ __launch_bounds__(BT) void k_junc_count(const uint32_t* __restrict__ vis, const uint32_t* __restrict__ label,
+                                                   uint32_t nv, uint64_t* __restrict__ bcount) {
+    __shared__ uint32_t sc[BT / WAVE + 1];
+    const uint64_t t = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    const uint32_t c = JVPT * t < nv ? (uint32_t)__popc(junction_bits(vis, label, nv, (uint32_t)t)) : 0u;
+    uint32_t tot;
+    block_excl_scan<uint32_t, BT>(c, sc, tot);
+    if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(BT) void k_junc_emit(const uint32_t* __restrict__ vis, uint32_t* __restrict__ label,
+                                                  uint32_t nv, const uint64_t* __restrict__ boff,
+                                                  uint32_t* __restrict__ jlist) {
+    __shared__ uint32_t sc[BT / WAVE + 1];
+    const uint64_t t = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    const uint32_t m = JVPT * t < nv ? junction_bits(vis, label, nv, (uint32_t)t) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<uint32_t, BT>((uint32_t)__popc(m), sc, tot);
+    uint64_t pos = boff[blockIdx.x] + ex;
+#pragma unroll
+    for (uint32_t v = 0; v < JVPT; v++) {
+#pragma unroll
+        for (uint32_t q = 0; q < 3; q++) {
+            if ((m >> (3u * v + q)) & 1u) {
+                const uint32_t w = JVPT * (uint32_t)t + v, k = 1u << q;
+                jlist[pos] = 8u * w + k;
+                label[label_slot(w, k, nv)] = (uint32_t)pos;
+                pos++;
             }
         }
     }
@@ -301,11 +360,28 @@ __global__ __launch_bounds__(BT) void k_minor_rows(const uint8_t* __restrict__ o
 
 hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Geo& g,
                              uint32_t* vis, uint32_t* next, unsigned long long* counts, uint32_t* label,
-                             uint32_t* jlist, hipStream_t s) {
+                             hipStream_t s) {
     if (ncur == 0) return hipSuccess;
     hipLaunchKernelGGL(k_bfs_expand, dim3(grid_blocks(ncur, (unsigned)(BT * BFS_NPT))), dim3(BT), 0, s, cur, ncur,
-                       level0 ? 1 : 0, grad, g,
-                       vis, next, counts, label, jlist);
+                       level0 ? 1 : 0, grad, g, vis, next, counts, label);
+    return hipGetLastError();
+}
+
+size_t junction_blocks(uint64_t nv) { return (size_t)((nv + (uint64_t)BT * JVPT - 1) / ((uint64_t)BT * JVPT)); }
+
+hipError_t launch_junc_count(const uint32_t* vis, const uint32_t* label, uint64_t nv, uint64_t* bcount,
+                             hipStream_t s) {
+    if (nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_junc_count, dim3((unsigned)junction_blocks(nv)), dim3(BT), 0, s, vis, label, (uint32_t)nv,
+                       bcount);
+    return hipGetLastError();
+}
+
+hipError_t launch_junc_emit(const uint32_t* vis, uint32_t* label, uint64_t nv, const uint64_t* boff, uint32_t* jlist,
+                            hipStream_t s) {
+    if (nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_junc_emit, dim3((unsigned)junction_blocks(nv)), dim3(BT), 0, s, vis, label, (uint32_t)nv,
+                       boff, jlist);
     return hipGetLastError();
 }
 

@@ -90,18 +90,27 @@ __global__ __launch_bounds__(BT) void k_label(const uint32_t* __restrict__ crit,
     else if (idx == 2) label[label_slot(w, k, g.nv)] = rank;
 }
 
-// One jump for every unfinished pointer.  `changed` holds 64 words; a
-// workgroup with an unfinished pointer stores 1 into one of them (spread so
-// that the stores do not queue on a single address).
+// PJ_HOPS jumps for every unfinished pointer: P[i] <- P[P[P[P[i]]]] for
+// three (pointers are updated in place, so a jump may already use a pointer
+// shortened in this round; every pointer always leads to the same root).
+// A round at least quadruples the distance a pointer covers, so fewer
+// rounds, and fewer full passes over P, are needed than with one jump.
+// `changed` holds 64 words; a workgroup with an unfinished pointer stores 1
+// into one of them (spread so that the stores do not queue on a single
+// address).
+constexpr int PJ_HOPS = 3;
+
 __global__ __launch_bounds__(BT) void k_pj_round(uint32_t* __restrict__ P, uint32_t n, int* __restrict__ changed) {
     uint32_t i = blockIdx.x * BT + threadIdx.x;
     int active = 0;
     if (i < n) {
         uint32_t p = P[i];
         if (!(p & ROOT_FLAG)) {
-            uint32_t q = P[p];
-            P[i] = q;
-            active = !(q & ROOT_FLAG);
+#pragma unroll
+            for (int h = 0; h < PJ_HOPS; h++)
+                if (!(p & ROOT_FLAG)) p = P[p];
+            P[i] = p;
+            active = !(p & ROOT_FLAG);
         }
     }
     if (__syncthreads_or(active) && threadIdx.x == 0) changed[blockIdx.x & 63u] = 1;

@@ -382,17 +382,27 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     check(c, hipMemsetAsync(d_n, 0, 24, s), "memset");
     check(c, launch_hist(B.col, (uint64_t)B.nnz, indeg, s), "in-degrees");
     check(c, launch_sources(indeg, J, order, d_n, s), "sources");
+    // levels on the device, SWEEP_BATCH per host round trip (d_n[0]: everything appended so far)
     std::vector<uint64_t> lvl{0};
-    uint64_t r = J ? readback(c, (const uint64_t*)d_n, 1)[0] : 0;
-    while (r > 0) {
-        const uint64_t pos = lvl.back();
-        lvl.push_back(pos + r);
-        check(c, hipMemsetAsync(d_n, 0, 8, s), "memset");
-        check(c, launch_release(order + pos, r, (const uint64_t*)B.rowptr, B.col, indeg, order + pos + r, d_n, d_err,
-                                nullptr, nullptr, nullptr, nullptr, nullptr, s),
-              "release");
-        r = readback(c, (const uint64_t*)d_n, 1)[0];
-        if (lvl.size() > J + 2) fail(c, MS_ERR_INTERNAL, "path counting did not terminate");
+    if (J > 0) {
+        constexpr uint64_t SWEEP_BATCH = 16;
+        uint64_t* lv = buf_keep<uint64_t>(c, "pr.lv", SWEEP_BATCH + 2, 0);
+        check(c, hipMemsetAsync(lv, 0, sizeof(uint64_t), s), "memset");
+        uint64_t L = 0;
+        for (bool done = false; !done;) {
+            const uint64_t L0 = L;
+            lv = buf_keep<uint64_t>(c, "pr.lv", L0 + SWEEP_BATCH + 2, L0 + 1);
+            for (; L < L0 + SWEEP_BATCH; L++)
+                check(c, launch_sweep_level(order, lv, L, (const uint64_t*)B.rowptr, B.col, indeg, d_n, d_err, s),
+                      "sweep");
+            // lv[L0 + 1 .. L]: the boundaries sealed in this batch
+            const uint64_t* h = readback(c, lv + L0 + 1, SWEEP_BATCH);
+            for (uint64_t q = 0; q < SWEEP_BATCH && !done; q++) {
+                if (h[q] == lvl.back()) done = true;  // an empty level: the sweep is complete
+                else lvl.push_back(h[q]);
+            }
+            if (lvl.size() > J + 2) fail(c, MS_ERR_INTERNAL, "path counting did not terminate");
+        }
     }
     if (lvl.back() != J) fail(c, MS_ERR_INTERNAL, "the junction graph has a cycle");
     const uint64_t nlev = lvl.size() - 1;

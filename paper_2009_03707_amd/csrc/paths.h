@@ -63,6 +63,12 @@ hipError_t launch_ready_init(const uint64_t* prp, uint64_t J, uint32_t* indeg, u
                              unsigned long long* nready, const uint64_t* base_rp, uint64_t* ub, hipStream_t s);
 // ub_next optional (with base_rp, prp, pcol, alen): the input counts of
 // the released columns, in the order of `next`
+// One level of the device-driven topological sweep: seals lv[L + 1] = *tail,
+// then releases the successors of order[lv[L], lv[L + 1]) (appended at
+// *tail).  lv[0] and *tail (the sources in order[0, *tail)) are set by the
+// caller.
+hipError_t launch_sweep_level(uint32_t* order, uint64_t* lv, uint64_t L, const uint64_t* brp, const uint32_t* bcol,
+                              uint32_t* indeg, unsigned long long* tail, int* err, hipStream_t s);
 hipError_t launch_release(const uint32_t* ready, uint64_t n, const uint64_t* brp, const uint32_t* bcol,
                           uint32_t* indeg, uint32_t* next, unsigned long long* nnext, int* err, const uint64_t* base_rp,
                           const uint64_t* prp, const uint32_t* pcol, const uint32_t* alen, uint64_t* ub_next,

@@ -587,6 +587,52 @@ __global__ __launch_bounds__(BT) void k_release(const uint32_t* __restrict__ rea
     }
 }
 
+// ---- topological sweep without host round trips -------------------------------
+// Level L's frontier is order[lv[L], lv[L + 1]); k_sweep_seal fixes
+// lv[L + 1] = *tail (everything appended so far) before level L is
+// released, and k_sweep_level appends the junctions whose last predecessor
+// it releases at *tail.  The host enqueues levels in batches and reads the
+// boundaries back once per batch; levels enqueued past the last one are
+// empty and do nothing.  The release grid is fixed and strides over the
+// frontier, whose size only the device knows.
+constexpr unsigned SWEEP_BLOCKS = 1024;
+
+__global__ void k_sweep_seal(uint64_t* __restrict__ lv, uint64_t L, const unsigned long long* __restrict__ tail) {
+    if (threadIdx.x == 0) lv[L + 1] = *tail;
+}
+
+__global__ __launch_bounds__(BT) void k_sweep_level(uint32_t* __restrict__ order, const uint64_t* __restrict__ lv,
+                                                    uint64_t L, const uint64_t* __restrict__ brp,
+                                                    const uint32_t* __restrict__ bcol, uint32_t* __restrict__ indeg,
+                                                    unsigned long long* __restrict__ tail, int* __restrict__ err) {
+    __shared__ unsigned long long sc[BT / WAVE + 1];
+    __shared__ unsigned long long base;
+    const uint64_t b0 = lv[L], n = lv[L + 1] - b0;
+    for (uint64_t blk = (uint64_t)blockIdx.x * BT; blk < n; blk += (uint64_t)gridDim.x * BT) {  // uniform
+        const uint64_t i = blk + threadIdx.x;
+        uint32_t out[3];
+        unsigned long long m = 0;
+        if (i < n) {
+            const uint32_t j = order[b0 + i];
+            uint64_t b = brp[j], e = brp[j + 1];
+            if (e - b > 3) {
+                atomicOr(err, 64);
+                e = b + 3;
+            }
+            for (uint64_t q = b; q < e; q++) {
+                const uint32_t t = bcol[q];
+                if (atomicSub(&indeg[t], 1u) == 1u) out[m++] = t;
+            }
+        }
+        unsigned long long tot;
+        const unsigned long long ex = block_excl_scan<unsigned long long, BT>(m, sc, tot);
+        if (threadIdx.x == 0) base = tot ? atomicAdd(tail, tot) : 0;
+        __syncthreads();
+        for (unsigned long long t = 0; t < m; t++) order[base + ex + t] = out[t];
+        __syncthreads();  // base is rewritten by the next pass
+    }
+}
+
 // ---- topological numbering of the junctions ---------------------------------
 // Junctions without predecessors (in-degree from a histogram of B's
 // columns); a workgroup covers SRC_PER_BLOCK junctions and appends them with
@@ -1110,6 +1156,16 @@ hipError_t launch_ready_init(const uint64_t* prp, uint64_t J, uint32_t* indeg, u
     if (J == 0) return hipSuccess;
     hipLaunchKernelGGL(k_ready_init, dim3(grid_blocks(J, BT)), dim3(BT), 0, s, prp, J, indeg, ready, nready, base_rp,
                        ub);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep_level(uint32_t* order, uint64_t* lv, uint64_t L, const uint64_t* brp, const uint32_t* bcol,
+                              uint32_t* indeg, unsigned long long* tail, int* err, hipStream_t s) {
+    hipLaunchKernelGGL(k_sweep_seal, dim3(1), dim3(WAVE), 0, s, lv, L, (const unsigned long long*)tail);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sweep_level, dim3(SWEEP_BLOCKS), dim3(BT), 0, s, order, (const uint64_t*)lv, L, brp, bcol,
+                       indeg, tail, err);
     return hipGetLastError();
 }
 

@@ -96,6 +96,62 @@ def roofline(kernel, source, bytes_per_launch, avg_launch_ms):
             "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": round(avg_launch_ms, 4)}
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """GB/s of a plain device-to-device copy (bytes read + bytes written)."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * 4 * n / (ms / 1e3) / 1e9
+
+
+def transfer_bench(ctx, f, torch, msc, reps=3):
+    """The same call with the field copied in from pinned host memory and the
+    critical list and the six arc matrices copied back (the gradient stays on
+    the device): whole-job rate including PCIe, for context only."""
+    import ctypes as C
+    fh = torch.from_numpy(f).pin_memory()
+    fd = torch.empty(fh.shape, dtype=fh.dtype, device="cuda")
+    fd.copy_(fh, non_blocking=True)
+    r = ctx.complex_raw(fd)
+    torch.cuda.synchronize()
+
+    def outputs(r):
+        n = int(sum(r.count))
+        out = [(r.crit.id, 4 * n), (r.crit.index, n), (r.crit.value, 4 * n), (r.crit.vmax, 4 * n)]
+        for name in ("m10", "m10t", "m21", "m21t", "m32", "m32t"):
+            m = getattr(r.arcs, name)
+            out += [(m.rowptr, 8 * (m.nrows + 1)), (m.col, 4 * m.nnz), (m.val, 8 * m.nnz)]
+        return [(p, b) for p, b in out if p and b > 0]
+
+    d2h = sum(b for _, b in outputs(r))
+    host = torch.empty(d2h, dtype=torch.uint8, pin_memory=True)
+    hip = msc._hip_rt()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fd.copy_(fh, non_blocking=True)
+        r = ctx.complex_raw(fd)
+        o = 0
+        for p, b in outputs(r):
+            rc = hip.hipMemcpyAsync(C.c_void_p(host.data_ptr() + o), C.c_void_p(p), b, 2, msc._stream_handle())
+            if rc != 0:
+                raise RuntimeError(f"hipMemcpyAsync failed ({rc})")
+            o += b
+        torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    return {"ms_per_step": round(ms, 2), "mvox_s": round(f.size / ms / 1e3, 2), "h2d_bytes": int(fh.numel() * 4),
+            "d2h_bytes": int(d2h)}
+
+
 def batch_bench(args, torch, msc):
     """The same kernels on the uneven 64-field batch: one field per call in
     sequence (plain) versus one ms_complex_batch call (batched)."""
@@ -149,6 +205,8 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=200,
                     help="timesteps of the served advected-field stream (0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=3)
+    ap.add_argument("--no-transfers", dest="transfers", action="store_false",
+                    help="skip the run that includes the host-device copies")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel for "
                          "scaling hardware traffic counters)")
@@ -211,6 +269,13 @@ def main():
     else:
         main_roof = grad_roof
     stages = {k.replace("_ms", ""): round(v / calls, 3) for k, v in tm.items() if k.endswith("_ms") and k != "rank_ms"}
+    ctx.set_timing(False)
+    copy_gbs = copy_bandwidth(torch)
+    for roof in (main_roof, grad_roof):
+        roof["copy_gbs"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+    log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
+    transfers = transfer_bench(ctx, f, torch, msc) if args.transfers else None
     out = {
         "metric": "MS-complex Mvoxels/s at 512^3 (plain vs batched), %HBM peak; p50/p99 latency",
         "value": round(value, 2),
@@ -232,6 +297,8 @@ def main():
         "stats": stats,
         "launch_params": tuned,
     }
+    if transfers:
+        out["with_transfers"] = transfers
     ctx.close()
     del fd
     torch.cuda.empty_cache()

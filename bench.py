@@ -261,8 +261,8 @@ def main():
     grad_roof = roofline("grad_lowerstar", "gradient.hip", grad_bytes, grad_ms)
     if tm["rank_launches"] > 0:
         # path-count ranking: per input entry 4 B row + 8 B count read and a
-        # 4 B head flag written; per run head 4 B row + 8 B sum written
-        rank_bytes = 16 * tm["rank_entries"] + 12 * tm["rank_heads"]
+        # 1 B head flag written; per run head 4 B row + 8 B sum written
+        rank_bytes = 13 * tm["rank_entries"] + 12 * tm["rank_heads"]
         main_roof = roofline("k_entry_rank", "paths.hip", rank_bytes / tm["rank_launches"],
                              tm["rank_ms"] / tm["rank_launches"])
         main_roof["launches_per_step"] = tm["rank_launches"] // calls

@@ -451,7 +451,7 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
         }
         uint32_t* hrow = buf<uint32_t>(c, "pe.hrow", T);
         uint64_t* hval = buf<uint64_t>(c, "pe.hval", T);
-        uint32_t* head = buf<uint32_t>(c, "pe.head", T);
+        uint8_t* head = buf<uint8_t>(c, "pe.head", T);
         hp = buf<uint64_t>(c, "pe.hp", T + 1);
         uint32_t* bstart = buf<uint32_t>(c, "pe.bstart", rank_blocks(T));
         const bool timed = c->timing && T > 0;

@@ -42,17 +42,17 @@ hipError_t launch_merge(const MergeLaunch& m, const uint8_t* flag, const uint32_
                         uint64_t* oval, uint32_t* cnt, uint64_t* col_off, uint32_t* col_len, hipStream_t s);
 // Entry-parallel merges (one thread per input entry): input counts per
 // column into ub; then, with off the exclusive scan of ub (n + 1 entries,
-// off[n] = T), the ranked run heads (head flags, rows, summed values at
-// their merged positions); then, with hp the exclusive scan of the head
-// flags (T + 1 entries), the compacted output at base + hp[p] and each
-// column's range (col_off/col_len by column id and/or a CSR row pointer).
+// off[n] = T), the ranked run heads (head flag bytes: bit 0 run head, bit 1
+// a column's first position; rows and summed values at their merged
+// positions); then the compacted output at base + (heads before p) with
+// that prefix in hp at every column's first position and at T; then each
+// column's range (col_off/col_len by column id and/or a CSR row pointer)
+// from hp[off[i]].
 hipError_t launch_entry_ub(const MergeLaunch& m, uint64_t* ub, hipStream_t s);
 // bstart: scratch of rank_blocks(T) entries (the first column of each rank block)
 size_t rank_blocks(uint64_t T);
 hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* bstart, uint32_t* hrow,
-                             uint64_t* hval, uint32_t* head, hipStream_t s);
-hipError_t launch_entry_emit(uint64_t T, const uint32_t* head, const uint64_t* hp, const uint32_t* hrow,
-                             const uint64_t* hval, uint64_t base, uint32_t* orow, uint64_t* oval, hipStream_t s);
+                             uint64_t* hval, uint8_t* head, hipStream_t s);
 hipError_t launch_entry_cols(const MergeLaunch& m, const uint64_t* off, const uint64_t* hp, uint64_t base,
                              uint64_t* col_off, uint32_t* col_len, uint64_t* rowptr, hipStream_t s);
 // Copies column i from src_off[i] to dst_off[i] (dst_off: n + 1 entries).
@@ -79,11 +79,13 @@ hipError_t launch_release(const uint32_t* ready, uint64_t n, const uint64_t* brp
 hipError_t launch_sources(const uint32_t* indeg, uint64_t J, uint32_t* out, unsigned long long* n, hipStream_t s);
 hipError_t launch_invert(const uint32_t* order, uint64_t n, uint32_t* inv, hipStream_t s);
 hipError_t launch_relabel(uint32_t* x, uint64_t n, const uint32_t* map, hipStream_t s);
-// Exclusive scan of the head flags into hp (T + 1 entries, hp[T] = number of
-// heads) with each head's row and count written at base + hp[p]; tmp needs
-// head_scan_tmp_elems(T) entries.
+// Exclusive scan of the run-head bits: each head's row and count written at
+// base + (heads before it); hp (T + 1 entries) gets that prefix at the
+// positions flagged as column starts and hp[T] = number of heads (other
+// entries of hp are left untouched); tmp needs head_scan_tmp_elems(T)
+// entries.
 size_t head_scan_tmp_elems(uint64_t T);
-hipError_t launch_head_scan_emit(const uint32_t* head, uint64_t T, const uint32_t* hrow, const uint64_t* hval,
+hipError_t launch_head_scan_emit(const uint8_t* head, uint64_t T, const uint32_t* hrow, const uint64_t* hval,
                                  uint64_t base, uint32_t* orow, uint64_t* oval, uint64_t* hp, uint64_t* tmp,
                                  hipStream_t s);
 

@@ -727,7 +727,7 @@ __global__ __launch_bounds__(BT) void k_block_start(const uint64_t* __restrict__
 // off: exclusive scan of ub (n + 1 entries, off[n] = T).
 __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* __restrict__ off, uint64_t T,
                                                    const uint32_t* __restrict__ bstart, uint32_t* __restrict__ hrow,
-                                                   uint64_t* __restrict__ hval, uint32_t* __restrict__ head) {
+                                                   uint64_t* __restrict__ hval, uint8_t* __restrict__ head) {
     __shared__ uint64_t s_off[CW + 1];
     __shared__ uint32_t s_lbase[CW + 1];
     __shared__ uint64_t s_lo[LCAP];  // list start: in the base arrays (list 0) or the A* storage
@@ -913,7 +913,8 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
             }
         }
         const uint64_t p = start + rank;
-        head[p] = is_head ? 1u : 0u;
+        // bit 0: run head; bit 1: the column's first position (its offset is read back per column)
+        head[p] = (uint8_t)((is_head ? 1u : 0u) | (rank == 0 ? 2u : 0u));
         if (is_head) {
             hrow[p] = xs;
             hval[p] = sum;
@@ -921,21 +922,12 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
     }
 }
 
-// hp: exclusive scan of head (T + 1 entries)
-__global__ __launch_bounds__(BT) void k_entry_emit(uint64_t T, const uint32_t* __restrict__ head,
-                                                   const uint64_t* __restrict__ hp, const uint32_t* __restrict__ hrow,
-                                                   const uint64_t* __restrict__ hval, uint64_t base,
-                                                   uint32_t* __restrict__ orow, uint64_t* __restrict__ oval) {
-    const uint64_t p = (uint64_t)blockIdx.x * BT + threadIdx.x;
-    if (p >= T || !head[p]) return;
-    const uint64_t d = base + hp[p];
-    orow[d] = hrow[p];
-    oval[d] = hval[p];
-}
 
 // Run heads per tile of the head flags, then (with the tile offsets
-// scanned) the exclusive prefix of every position into hp and each head's
-// row and count written at base + hp[p].  A tile is 2048 positions; wave w
+// scanned) each head's row and count written at base + (heads before it),
+// and that prefix into hp at every column's first position (the only
+// positions read back; an empty column's offset is the next column's, or
+// T, whose prefix the scan writes).  A tile is 2048 positions; wave w
 // of its workgroup covers positions [512 w, 512 w + 512) in 8 rounds of 64
 // consecutive positions, so every access is coalesced and the prefix of a
 // 0/1 flag inside a round is a popcount of the round's ballot.
@@ -943,7 +935,7 @@ constexpr int HT_R = 8;                   // rounds per wave
 constexpr int HT_WAVE = HT_R * WAVE;      // positions per wave
 constexpr int HT_TILE = (BT / WAVE) * HT_WAVE;
 
-__global__ __launch_bounds__(BT) void k_head_tiles(const uint32_t* __restrict__ head, uint64_t T,
+__global__ __launch_bounds__(BT) void k_head_tiles(const uint8_t* __restrict__ head, uint64_t T,
                                                    uint64_t* __restrict__ part) {
     __shared__ uint32_t wsum[BT / WAVE];
     const int lane = lane_id(), w = (int)threadIdx.x / WAVE;
@@ -952,7 +944,7 @@ __global__ __launch_bounds__(BT) void k_head_tiles(const uint32_t* __restrict__ 
 #pragma unroll
     for (int r = 0; r < HT_R; r++) {
         const uint64_t j = b0 + (uint64_t)r * WAVE + lane;
-        cnt += (uint32_t)__popcll(__ballot(j < T && head[j] != 0u));
+        cnt += (uint32_t)__popcll(__ballot(j < T && (head[j] & 1u)));
     }
     if (lane == 0) wsum[w] = cnt;
     __syncthreads();
@@ -963,7 +955,7 @@ __global__ __launch_bounds__(BT) void k_head_tiles(const uint32_t* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(BT) void k_head_emit(const uint32_t* __restrict__ head, uint64_t T,
+__global__ __launch_bounds__(BT) void k_head_emit(const uint8_t* __restrict__ head, uint64_t T,
                                                   const uint64_t* __restrict__ part,
                                                   const uint32_t* __restrict__ hrow, const uint64_t* __restrict__ hval,
                                                   uint64_t base, uint32_t* __restrict__ orow,
@@ -973,11 +965,13 @@ __global__ __launch_bounds__(BT) void k_head_emit(const uint32_t* __restrict__ h
     const uint64_t lt = (1ull << lane) - 1ull;
     const uint64_t b0 = (uint64_t)blockIdx.x * HT_TILE + (uint64_t)w * HT_WAVE;
     uint64_t mask[HT_R];
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, first = 0;  // first: bit r set when position r of this lane starts a column
 #pragma unroll
     for (int r = 0; r < HT_R; r++) {
         const uint64_t j = b0 + (uint64_t)r * WAVE + lane;
-        mask[r] = __ballot(j < T && head[j] != 0u);
+        const uint32_t h = j < T ? head[j] : 0u;
+        mask[r] = __ballot(h & 1u);
+        first |= (h >> 1 & 1u) << r;
         cnt += (uint32_t)__popcll(mask[r]);
     }
     if (lane == 0) wsum[w] = cnt;
@@ -989,7 +983,7 @@ __global__ __launch_bounds__(BT) void k_head_emit(const uint32_t* __restrict__ h
         const uint64_t j = b0 + (uint64_t)r * WAVE + lane;
         const uint64_t p = ex + (uint64_t)__popcll(mask[r] & lt);
         if (j < T) {
-            hp[j] = p;
+            if ((first >> r) & 1u) hp[j] = p;  // only column starts are read back
             if ((mask[r] >> lane) & 1ull) {
                 orow[base + p] = hrow[j];
                 oval[base + p] = hval[j];
@@ -1080,21 +1074,13 @@ hipError_t launch_entry_ub(const MergeLaunch& m, uint64_t* ub, hipStream_t s) {
 size_t rank_blocks(uint64_t T) { return (T + EPB - 1) / EPB; }
 
 hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* bstart, uint32_t* hrow,
-                             uint64_t* hval, uint32_t* head, hipStream_t s) {
+                             uint64_t* hval, uint8_t* head, hipStream_t s) {
     if (T == 0) return hipSuccess;
     hipLaunchKernelGGL(k_block_start, dim3(grid_blocks(m.n, BT)), dim3(BT), 0, s, off, m.n, bstart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_entry_rank, dim3(grid_blocks(T, EPB)), dim3(BT), 0, s, to_args(m), off, T,
                        (const uint32_t*)bstart, hrow, hval, head);
-    return hipGetLastError();
-}
-
-hipError_t launch_entry_emit(uint64_t T, const uint32_t* head, const uint64_t* hp, const uint32_t* hrow,
-                             const uint64_t* hval, uint64_t base, uint32_t* orow, uint64_t* oval, hipStream_t s) {
-    if (T == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_entry_emit, dim3(grid_blocks(T, BT)), dim3(BT), 0, s, T, head, hp, hrow, hval, base, orow,
-                       oval);
     return hipGetLastError();
 }
 
@@ -1119,7 +1105,7 @@ hipError_t launch_relabel(uint32_t* x, uint64_t n, const uint32_t* map, hipStrea
 
 size_t head_scan_tmp_elems(uint64_t T) { return (T + HT_TILE - 1) / HT_TILE + 1 + scan_tmp_elems((T + HT_TILE - 1) / HT_TILE + 1); }
 
-hipError_t launch_head_scan_emit(const uint32_t* head, uint64_t T, const uint32_t* hrow, const uint64_t* hval,
+hipError_t launch_head_scan_emit(const uint8_t* head, uint64_t T, const uint32_t* hrow, const uint64_t* hval,
                                  uint64_t base, uint32_t* orow, uint64_t* oval, uint64_t* hp, uint64_t* tmp,
                                  hipStream_t s) {
     if (T == 0) return hipMemsetAsync(hp, 0, sizeof(uint64_t), s);

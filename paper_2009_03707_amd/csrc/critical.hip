@@ -61,12 +61,20 @@ __global__ void crit_totals(const uint64_t* __restrict__ excl, uint64_t nb, cons
     }
 }
 
+// Records of a tile are staged in LDS by (index, id) and written out as four
+// contiguous runs (one per index segment); a tile with more than CCAP
+// critical cells writes its records directly.
+constexpr uint32_t CCAP = 2048;
+
 __global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f0, const float* const* __restrict__ fptr,
                                                    const uint32_t* __restrict__ grad, Geo geo,
                                                    const uint64_t* __restrict__ excl,
                                                    uint32_t* __restrict__ o_id, uint8_t* __restrict__ o_index,
                                                    float* __restrict__ o_value, uint32_t* __restrict__ o_vmax) {
     __shared__ uint64_t sc[CT / WAVE + 1];
+    __shared__ uint32_t s_id[CCAP];
+    __shared__ float s_val[CCAP];
+    __shared__ uint32_t s_vmax[CCAP];
     const uint64_t nv = geo.nv;
     const uint64_t nb = gridDim.x;
     uint64_t base = (uint64_t)blockIdx.x * CTILE + (uint64_t)threadIdx.x * CWPT;
@@ -79,10 +87,17 @@ __global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f0,
     }
     uint64_t tot;
     uint64_t ex = block_excl_scan<uint64_t, CT>(s, sc, tot);
-    if (tot == 0) return;
+    if (tot == 0) return;  // uniform
+    uint32_t seg[5];       // tile-local start of each index segment
+    seg[0] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) seg[k + 1] = seg[k] + (uint32_t)((tot >> (16 * k)) & 0xFFFFu);
+    const uint32_t n = seg[4];
+    const bool staged = n <= CCAP;  // uniform
     uint64_t pos[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) pos[k] = excl[(uint64_t)k * nb + blockIdx.x] + ((ex >> (16 * k)) & 0xFFFFu);
+    for (int k = 0; k < 4; k++)
+        pos[k] = (staged ? (uint64_t)seg[k] : excl[(uint64_t)k * nb + blockIdx.x]) + ((ex >> (16 * k)) & 0xFFFFu);
 #pragma unroll
     for (int i = 0; i < CWPT; i++) {
         uint32_t word = w[i];
@@ -99,12 +114,29 @@ __global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f0,
             uint32_t vm = v + ((d & 1u) ? g.stride[0] : 0u) + ((d & 2u) ? g.stride[1] : 0u) +
                           ((d & 4u) ? g.stride[2] : 0u);
             const float* f = fptr ? fptr[fld] : f0;
+            const float val = load_global(f, vm - geo.base(fld));
             uint64_t p = pos[idx]++;
-            o_id[p] = 8u * v + k;
-            o_index[p] = (uint8_t)idx;
-            o_value[p] = load_global(f, vm - geo.base(fld));
-            o_vmax[p] = vm;
+            if (staged) {
+                s_id[p] = 8u * v + k;
+                s_val[p] = val;
+                s_vmax[p] = vm;
+            } else {
+                o_id[p] = 8u * v + k;
+                o_index[p] = (uint8_t)idx;
+                o_value[p] = val;
+                o_vmax[p] = vm;
+            }
         }
+    }
+    if (!staged) return;  // uniform
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < n; i += CT) {
+        const uint32_t k = (i >= seg[1] ? 1u : 0u) + (i >= seg[2] ? 1u : 0u) + (i >= seg[3] ? 1u : 0u);
+        const uint64_t g = excl[(uint64_t)k * nb + blockIdx.x] + (i - seg[k]);
+        o_id[g] = s_id[i];
+        o_index[g] = (uint8_t)k;
+        o_value[g] = s_val[i];
+        o_vmax[g] = s_vmax[i];
     }
 }
 

@@ -114,3 +114,32 @@ def test_grf256_sampled(ctx):
     f = fields.grf_field((256, 256, 256), seed=0)
     got = _run_sampled(ctx, f)
     print("grf256 counts", got.count, "stats", got.stats, "saturated", got.n_saturated)
+
+
+@pytest.fixture(scope="module")
+def ctx_bench():
+    """A context in the configuration the benchmark runs at 512^3: the
+    entry-parallel path schedule (its device-driven topological sweep spans
+    well over one batch of levels here) and gradient tile 5."""
+    from paper_2009_03707_amd import msc
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = msc.Context()
+    c.set_path_schedule(msc.MS_PATHS_ENTRY)
+    c.set_option(msc.MS_OPT_GRADIENT_TILE, 5)
+    yield c
+    c.close()
+
+
+def test_blobs512_bench_configuration(ctx, ctx_bench):
+    """The benchmark's configuration against the oracle's samples, and every
+    output identical to the default configuration's (ready schedule, tile 0),
+    whose path counts are formed by different kernels."""
+    from gpu_util import same_complex, to_dev
+    from paper_2009_03707_amd import msc
+    f = fields.blob_field((512, 512, 512), nblobs=2000, seed=0)
+    got = _run_sampled(ctx_bench, f, seed=1)
+    print("blobs512 (entry schedule) stats", got.stats)
+    assert got.stats["spgemm_iters"] > 16  # several batches of the sweep
+    ref = msc.complex_(to_dev(f), ctx)
+    same_complex(got, ref)

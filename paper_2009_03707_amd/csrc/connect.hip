@@ -19,7 +19,8 @@ hipError_t launch_m10(bool fill, const uint32_t* s1, uint64_t S1, const Geo& g, 
 hipError_t launch_m32t(bool fill, const uint32_t* s2, uint64_t S2, const Geo& g, const uint32_t* Pc, uint32_t* cnt,
                        const uint64_t* rowptr, uint32_t* col, uint64_t* val, int* err, hipStream_t s);
 int bit_width(uint64_t v);
-hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, uint32_t* rows, hipStream_t s);
+hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, const uint32_t* map, uint32_t* rows,
+                              hipStream_t s);
 hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s);
 hipError_t launch_hist(const uint32_t* keys, uint64_t n, uint32_t* h, hipStream_t s);
 size_t key_bounds_tmp_elems(uint64_t n, uint64_t nkeys);
@@ -108,7 +109,9 @@ uint64_t counts_to_rowptr(ms_ctx* c, const uint32_t* cnt, uint64_t n, uint64_t* 
 // Transpose: a stable radix sort of the column ids (read in place, entry
 // index as payload), a gather of rows and values, and the row pointer of
 // the result from the boundaries between equal keys.
-void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out) {
+// With row_map set, the transposed matrix's column ids are row_map[row]
+// (the input's rows renumbered while they are expanded, read in order).
+void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const uint32_t* row_map = nullptr) {
     uint64_t nnz = (uint64_t)in.nnz;
     out = csr_buf(c, name, (uint64_t)in.ncols, (uint64_t)in.nrows, nnz);
     if (nnz == 0) {
@@ -123,7 +126,8 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out) {
     uint64_t* wa = buf<uint64_t>(c, "tr.wa", nnz);
     uint64_t* wb = buf<uint64_t>(c, "tr.wb", nnz);
     uint64_t* tmp = buf<uint64_t>(c, "tr.tmp", radix_tmp_elems(nnz));
-    check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, rows, c->stream), "expand rows");
+    check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, row_map, rows, c->stream),
+          "expand rows");
     const uint32_t* keys = nullptr;
     check(c, radix_transpose_u32(in.col, rows, (const uint64_t*)in.val, ka, va, kb, vb, wa, wb, nnz,
                                  bit_width((uint64_t)in.ncols - 1), tmp, out.col, (uint64_t*)out.val, &keys, c->stream),
@@ -209,7 +213,8 @@ Coo csr_as_coo(ms_ctx* c, const ms_csr& m, const char* rows_name) {
     o.row = buf<uint32_t>(c, rows_name, o.n);
     o.col = m.col;
     o.val = m.val;
-    check(c, launch_expand_rows((const uint64_t*)m.rowptr, (uint64_t)m.nrows, o.row, c->stream), "expand rows");
+    check(c, launch_expand_rows((const uint64_t*)m.rowptr, (uint64_t)m.nrows, nullptr, o.row, c->stream),
+          "expand rows");
     return o;
 }
 
@@ -411,12 +416,10 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     check(c, launch_relabel(A.col, (uint64_t)A.nnz, newid, s), "relabel");
     check(c, launch_relabel(B.col, (uint64_t)B.nnz, newid, s), "relabel");
     ms_csr At, Bt, Bst, Dt;
-    transpose(c, A, "At", At);     // junction x 1-saddle
-    transpose(c, B, "Bt", Bt);     // junction x predecessor junction
-    transpose(c, Bs, "Bst", Bst);  // 2-saddle x junction
-    transpose(c, D, "Dt", Dt);     // 2-saddle x 1-saddle
-    check(c, launch_relabel(Bt.col, (uint64_t)Bt.nnz, newid, s), "relabel");
-    check(c, launch_relabel(Bst.col, (uint64_t)Bst.nnz, newid, s), "relabel");
+    transpose(c, A, "At", At);             // junction x 1-saddle
+    transpose(c, B, "Bt", Bt, newid);      // junction x predecessor junction (sources renumbered)
+    transpose(c, Bs, "Bst", Bst, newid);   // 2-saddle x junction (renumbered)
+    transpose(c, D, "Dt", Dt);             // 2-saddle x 1-saddle
     // ---- levels --------------------------------------------------------------
     const uint64_t nmax = (J > S2 ? J : S2) + 1;
     uint64_t* ub = buf<uint64_t>(c, "pr.ub", nmax + 1);

@@ -14,11 +14,13 @@ namespace {
 
 constexpr int BT = 256;
 
+// rows[p] = the row of entry p, or map[row] when a map is given.
 __global__ __launch_bounds__(BT) void k_expand_rows(const uint64_t* __restrict__ rowptr, uint64_t nrows,
-                                                    uint32_t* __restrict__ rows) {
+                                                    const uint32_t* __restrict__ map, uint32_t* __restrict__ rows) {
     uint64_t r = (uint64_t)blockIdx.x * BT + threadIdx.x;
     if (r >= nrows) return;
-    for (uint64_t p = rowptr[r]; p < rowptr[r + 1]; p++) rows[p] = (uint32_t)r;
+    const uint32_t v = map ? map[r] : (uint32_t)r;
+    for (uint64_t p = rowptr[r]; p < rowptr[r + 1]; p++) rows[p] = v;
 }
 
 __global__ __launch_bounds__(BT) void k_iota(uint32_t* __restrict__ a, uint64_t n) {
@@ -176,9 +178,10 @@ hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, u
     return hipGetLastError();
 }
 
-hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, uint32_t* rows, hipStream_t s) {
+hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, const uint32_t* map, uint32_t* rows,
+                              hipStream_t s) {
     if (nrows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand_rows, dim3(grid_blocks(nrows, BT)), dim3(BT), 0, s, rowptr, nrows, rows);
+    hipLaunchKernelGGL(k_expand_rows, dim3(grid_blocks(nrows, BT)), dim3(BT), 0, s, rowptr, nrows, map, rows);
     return hipGetLastError();
 }
 hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s) {

@@ -22,6 +22,7 @@ int bit_width(uint64_t v);
 hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, const uint32_t* map, uint32_t* rows,
                               hipStream_t s);
 hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s);
+hipError_t launch_sum_u32(const uint32_t* a, uint64_t n, uint64_t* out, hipStream_t s);
 hipError_t launch_hist(const uint32_t* keys, uint64_t n, uint32_t* h, hipStream_t s);
 size_t key_bounds_tmp_elems(uint64_t n, uint64_t nkeys);
 hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, uint64_t* rowptr, uint64_t* tmp,
@@ -499,11 +500,10 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     out->m21 = m21;
     transpose(c, out->m21, "m21t", out->m21t);
     // exact nnz of A*: the sum of the column lengths
-    uint64_t* sum = buf<uint64_t>(c, "pe.asum", J + 1);
-    uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(J) + 1);
-    check(c, scan_excl_u32_to_u64(alen, sum, J, stmp, sum + J, s), "scan");
+    uint64_t* sum = buf<uint64_t>(c, "pe.asum", 1);
+    check(c, launch_sum_u32(alen, J, sum, s), "sum");
     st.spgemm_iters = (int64_t)nlev;
-    st.nnz_astar = J ? (int64_t)read_u64(c, sum + J) : 0;
+    st.nnz_astar = (int64_t)read_u64(c, sum);
     st.products = (int64_t)(products + T);
     if (c->timing) c->rank_heads += st.nnz_astar + m21.nnz;
 }

@@ -23,6 +23,17 @@ __global__ __launch_bounds__(BT) void k_expand_rows(const uint64_t* __restrict__
     for (uint64_t p = rowptr[r]; p < rowptr[r + 1]; p++) rows[p] = v;
 }
 
+// *out += the sum of a[0, n) (one atomic per workgroup; *out zeroed by the caller)
+__global__ __launch_bounds__(BT) void k_sum_u32(const uint32_t* __restrict__ a, uint64_t n,
+                                                unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long sc[BT / WAVE + 1];
+    unsigned long long v = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * BT) v += a[i];
+    unsigned long long tot;
+    block_excl_scan<unsigned long long, BT>(v, sc, tot);
+    if (threadIdx.x == 0 && tot) atomicAdd(out, tot);
+}
+
 __global__ __launch_bounds__(BT) void k_iota(uint32_t* __restrict__ a, uint64_t n) {
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
     if (i < n) a[i] = (uint32_t)i;
@@ -182,6 +193,13 @@ hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, const uint
                               hipStream_t s) {
     if (nrows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_expand_rows, dim3(grid_blocks(nrows, BT)), dim3(BT), 0, s, rowptr, nrows, map, rows);
+    return hipGetLastError();
+}
+hipError_t launch_sum_u32(const uint32_t* a, uint64_t n, uint64_t* out, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(out, 0, sizeof(uint64_t), s);
+    if (e != hipSuccess || n == 0) return e;
+    const unsigned nb = grid_blocks(n, BT) < 2048u ? grid_blocks(n, BT) : 2048u;
+    hipLaunchKernelGGL(k_sum_u32, dim3(nb), dim3(BT), 0, s, a, n, (unsigned long long*)out);
     return hipGetLastError();
 }
 hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s) {

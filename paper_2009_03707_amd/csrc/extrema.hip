@@ -19,10 +19,15 @@ namespace {
 
 constexpr int BT = 256;
 
-__global__ __launch_bounds__(BT) void k_pj_init(const uint32_t* __restrict__ grad, Geo geo, uint32_t* __restrict__ Pv,
-                                                uint32_t* __restrict__ Pc, int* __restrict__ err) {
-    uint32_t v = blockIdx.x * BT + threadIdx.x;
-    if (v >= geo.nv) return;
+// The pointer-jumping kernels give a thread PJ_EPT elements, BT apart
+// (coalesced per round, and independent chains in flight): with one element
+// per thread the launches are bound by the rate at which workgroups are
+// dispatched.
+constexpr int PJ_EPT = 4;
+
+__device__ __forceinline__ void pj_init_vertex(const uint32_t* __restrict__ grad, const Geo& geo,
+                                               uint32_t* __restrict__ Pv, uint32_t* __restrict__ Pc,
+                                               int* __restrict__ err, uint32_t v) {
     uint32_t fld = geo.field_of(v);
     const Grid g = geo.grid(fld);
     uint32_t w = grad[v];
@@ -60,6 +65,16 @@ __global__ __launch_bounds__(BT) void k_pj_init(const uint32_t* __restrict__ gra
         atomicOr(err, 1);
     }
     Pc[v] = pc;
+}
+
+// PJ_EPT vertices per thread, BT apart
+__global__ __launch_bounds__(BT) void k_pj_init(const uint32_t* __restrict__ grad, Geo geo, uint32_t* __restrict__ Pv,
+                                                uint32_t* __restrict__ Pc, int* __restrict__ err) {
+#pragma unroll
+    for (int r = 0; r < PJ_EPT; r++) {
+        const uint64_t v = ((uint64_t)blockIdx.x * PJ_EPT + r) * BT + threadIdx.x;
+        if (v < geo.nv) pj_init_vertex(grad, geo, Pv, Pc, err, (uint32_t)v);
+    }
 }
 
 // Labels roots with ranks and checks the critical list against the gradient
@@ -101,16 +116,26 @@ __global__ __launch_bounds__(BT) void k_label(const uint32_t* __restrict__ crit,
 constexpr int PJ_HOPS = 3;
 
 __global__ __launch_bounds__(BT) void k_pj_round(uint32_t* __restrict__ P, uint32_t n, int* __restrict__ changed) {
-    uint32_t i = blockIdx.x * BT + threadIdx.x;
+    uint32_t p[PJ_EPT];
+    uint32_t todo = 0;  // bit r: element r is in range and not yet at a root
     int active = 0;
-    if (i < n) {
-        uint32_t p = P[i];
-        if (!(p & ROOT_FLAG)) {
 #pragma unroll
-            for (int h = 0; h < PJ_HOPS; h++)
-                if (!(p & ROOT_FLAG)) p = P[p];
-            P[i] = p;
-            active = !(p & ROOT_FLAG);
+    for (int r = 0; r < PJ_EPT; r++) {
+        const uint64_t i = ((uint64_t)blockIdx.x * PJ_EPT + r) * BT + threadIdx.x;
+        p[r] = i < n ? P[i] : ROOT_FLAG;
+        if (!(p[r] & ROOT_FLAG)) todo |= 1u << r;
+    }
+#pragma unroll
+    for (int h = 0; h < PJ_HOPS; h++)
+#pragma unroll
+        for (int r = 0; r < PJ_EPT; r++)
+            if (!(p[r] & ROOT_FLAG)) p[r] = P[p[r]];
+#pragma unroll
+    for (int r = 0; r < PJ_EPT; r++) {
+        const uint64_t i = ((uint64_t)blockIdx.x * PJ_EPT + r) * BT + threadIdx.x;
+        if ((todo >> r) & 1u) {
+            P[i] = p[r];
+            active |= !(p[r] & ROOT_FLAG);
         }
     }
     if (__syncthreads_or(active) && threadIdx.x == 0) changed[blockIdx.x & 63u] = 1;
@@ -202,7 +227,7 @@ __global__ __launch_bounds__(BT) void k_m32t(const uint32_t* __restrict__ s2, ui
 }  // namespace
 
 hipError_t launch_pj_init(const uint32_t* grad, const Geo& g, uint32_t* Pv, uint32_t* Pc, int* err, hipStream_t s) {
-    hipLaunchKernelGGL(k_pj_init, dim3(grid_blocks(g.nv, BT)), dim3(BT), 0, s, grad, g, Pv, Pc, err);
+    hipLaunchKernelGGL(k_pj_init, dim3(grid_blocks(g.nv, (unsigned)(BT * PJ_EPT))), dim3(BT), 0, s, grad, g, Pv, Pc, err);
     return hipGetLastError();
 }
 
@@ -216,7 +241,7 @@ hipError_t launch_label(const uint32_t* crit, const int64_t cnt[4], const uint32
 }
 
 hipError_t launch_pj_round(uint32_t* P, uint32_t n, int* changed, hipStream_t s) {
-    hipLaunchKernelGGL(k_pj_round, dim3(grid_blocks(n, BT)), dim3(BT), 0, s, P, n, changed);
+    hipLaunchKernelGGL(k_pj_round, dim3(grid_blocks(n, (unsigned)(BT * PJ_EPT))), dim3(BT), 0, s, P, n, changed);
     return hipGetLastError();
 }
 

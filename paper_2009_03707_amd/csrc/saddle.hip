@@ -96,7 +96,7 @@ __device__ __forceinline__ void bfs_node(uint32_t e, const uint32_t* __restrict_
 // and junctions with one atomic on a packed counter (low 32 bits: frontier,
 // high 32 bits: junctions); appends to one counter serialise, so they are
 // kept few.
-constexpr int BFS_NPT = 4;
+constexpr int BFS_NPT = 2;
 
 __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ cur, uint64_t ncur, int level0,
                                                    const uint32_t* __restrict__ grad, Geo geo,

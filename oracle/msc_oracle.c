@@ -698,6 +698,49 @@ int orc_m32_col_lazy(const float* f, int64_t nx, int64_t ny, int64_t nz, int64_t
     return rc;
 }
 
+/* ---- ascending and descending 3-manifolds ----------------------------------- */
+
+#define ORC_NO_LABEL 0xFFFFFFFFu
+
+/* Section 3.4: the traversal that yields the saddle-extremum arcs also yields
+ * the ascending manifolds of the minima and the descending manifolds of the
+ * maxima, i.e. for every non-critical cell the extremum its gradient path
+ * ends at (Section 3.5 keeps these destinations in an extra array).
+ *   min_label[v] : rank (among minima, in id order) of the minimum that the
+ *                  (0,1) V-path from vertex v reaches;
+ *   max_label[w] : rank (among maxima) of the maximum that the (2,3) V-path
+ *                  from the cube whose lowest corner is vertex w reaches;
+ *                  ORC_NO_LABEL when that cube does not exist (w on a high
+ *                  face of the box) or when its path leaves the box through
+ *                  a boundary quad (such paths are discarded, Section 3.5).
+ * Each vertex and each cube is walked on its own, step by step. */
+int orc_manifolds(const uint32_t* grad, int64_t nx, int64_t ny, int64_t nz, const uint32_t* crit_id,
+                  const int64_t count[4], uint32_t* min_label, uint32_t* max_label) {
+    src_t s;
+    int rc = src_init(&s, NULL, grad, nx, ny, nz);
+    if (rc) return rc;
+    const uint32_t* mins = crit_id;
+    const uint32_t* maxs = crit_id + count[0] + count[1] + count[2];
+    for (int64_t v = 0; v < s.g.nv; v++) {
+        int64_t root = vertex_root(&s, v);
+        if (root < 0) return ORC_ERR_INTERNAL;
+        int64_t rank = lower_bound_u32(mins, count[0], (uint32_t)(8 * root));
+        if (rank >= count[0] || mins[rank] != (uint32_t)(8 * root)) return ORC_ERR_INTERNAL;
+        min_label[v] = (uint32_t)rank;
+    }
+    for (int64_t w = 0; w < s.g.nv; w++) {
+        max_label[w] = ORC_NO_LABEL;
+        if (!nibble_exists(&s.g, w, 7)) continue;
+        int64_t root = cube_root(&s, 8 * w + 7);
+        if (root == -1) return ORC_ERR_INTERNAL;
+        if (root == EXIT_ROOT) continue;
+        int64_t rank = lower_bound_u32(maxs, count[3], (uint32_t)root);
+        if (rank >= count[3] || maxs[rank] != (uint32_t)root) return ORC_ERR_INTERNAL;
+        max_label[w] = (uint32_t)rank;
+    }
+    return ORC_OK;
+}
+
 /* ---- 1-saddle / 2-saddle path counts ----------------------------------------- */
 
 /* Out-neighbours of an edge node in the DAG of 1-2 gradient pairs:

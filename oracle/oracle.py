@@ -49,6 +49,8 @@ def lib():
                                    _p(np.int64, flags="C"), C.POINTER(C.c_void_p)]
         L.orc_ss_rows_lazy.argtypes = [_p(np.float32, flags="C"), i64, i64, i64, _p(np.int64, flags="C"), i64,
                                        C.POINTER(C.c_void_p)]
+        L.orc_manifolds.argtypes = [_p(np.uint32, flags="C"), i64, i64, i64, _p(np.uint32, flags="C"),
+                                    _p(np.int64, flags="C"), _p(np.uint32, flags="C"), _p(np.uint32, flags="C")]
         L.orc_coo_free.argtypes = [C.c_void_p]
         L.orc_coo_nnz.argtypes = [C.c_void_p]
         L.orc_coo_nnz.restype = i64
@@ -152,6 +154,25 @@ def se_arcs(f: np.ndarray, grad: np.ndarray, crit: Critical):
     return m10, m32
 
 
+NO_LABEL = 0xFFFFFFFF
+
+
+def manifolds(f: np.ndarray, grad: np.ndarray, crit: Critical):
+    """(min_label, max_label), both uint32 of shape (nz, ny, nx).
+
+    min_label[v]: rank of the minimum whose ascending manifold holds vertex v.
+    max_label[w]: rank of the maximum whose descending manifold holds the cube
+    with lowest corner w, or NO_LABEL (no such cube, or its path leaves the
+    box)."""
+    grad = np.ascontiguousarray(grad, dtype=np.uint32)
+    cnt = crit.count.astype(np.int64)
+    lo = np.zeros(grad.shape, np.uint32)
+    hi = np.zeros(grad.shape, np.uint32)
+    ids = np.ascontiguousarray(crit.id if len(crit.id) else np.zeros(1, np.uint32))
+    _check(lib().orc_manifolds(grad, *_dims(grad), ids, cnt, lo, hi), "manifolds")
+    return lo, hi
+
+
 def _take_coo(h, shape):
     L = lib()
     n = L.orc_coo_nnz(h)
@@ -181,14 +202,17 @@ class Complex:
     m10: Coo
     m32: Coo
     p: Coo           # 1-saddle x 2-saddle path counts; M21 is its transpose
+    min_label: np.ndarray = None   # ascending manifolds of minima (per vertex)
+    max_label: np.ndarray = None   # descending manifolds of maxima (per cube)
 
 
-def complex_(f: np.ndarray) -> Complex:
+def complex_(f: np.ndarray, labels: bool = True) -> Complex:
     g = gradient(f)
     cr = critical(f, g)
     m10, m32 = se_arcs(f, g, cr)
     p = ss_paths(f, g, cr)
-    return Complex(g, cr, m10, m32, p)
+    lo, hi = manifolds(f, g, cr) if labels else (None, None)
+    return Complex(g, cr, m10, m32, p, lo, hi)
 
 
 # ---- lazy accessors (work from f alone; for sampled checks at large sizes) ----

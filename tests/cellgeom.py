@@ -112,12 +112,13 @@ def partner(G: Grid, grad, cid):
 
 # ---- invariants of a discrete gradient ------------------------------------------
 
-def check_gradient_valid(G: Grid, grad):
+def check_gradient_valid(G: Grid, grad, lower_star: bool = True):
     """Every existing cell is critical or in exactly one pair with a facet or
     cofacet; pairs are symmetric; both cells of a pair share their highest
     vertex (lower-star property); a critical cell's encoded corner is its
     highest vertex; cells that do not exist are marked as such; and no
-    (i, i+1) V-path closes a cycle."""
+    (i, i+1) V-path closes a cycle.  With lower_star=False the two checks
+    that involve field values are skipped (for hand-built gradients)."""
     g = grad.reshape(-1)
     existing = set(G.all_cells())
     for w in range(G.nv):
@@ -129,6 +130,8 @@ def check_gradient_valid(G: Grid, grad):
                 continue
             assert v != 0 and v != NOCELL, (cid, v)
             if v >= CRIT:
+                if not lower_star:
+                    continue
                 x, y, z = G.vxyz(w)
                 d = v - CRIT
                 top = G.vid(x + (d & 1), y + ((d >> 1) & 1), z + ((d >> 2) & 1))
@@ -136,7 +139,8 @@ def check_gradient_valid(G: Grid, grad):
             else:
                 p = partner(G, grad, cid)
                 assert partner(G, grad, p) == cid, (cid, p)
-                assert G.maxv(p) == G.maxv(cid), (cid, p)
+                if lower_star:
+                    assert G.maxv(p) == G.maxv(cid), (cid, p)
     # acyclicity of V-paths in each dimension pair, by Kahn's algorithm
     for i in range(3):
         nodes = [c for c in existing if G.dim(c) == i]
@@ -255,6 +259,53 @@ def vpath_counts(G: Grid, grad, crit):
         for s in crit[i + 1]:
             for a in G.facets(s):
                 walk(i, a, s, res[i])
+    return res
+
+
+# ---- exact path counts (arbitrary precision) -------------------------------------
+
+def dag_out(G: Grid, grad, e):
+    """Out-neighbours of edge e in the DAG of 1-2 gradient pairs (Section 3.1,
+    Figure 6 (d)): for each cofacet quad Q other than the quad e is paired
+    with, ("s2", Q) if Q is critical, ("e", e2) if Q is paired with edge e2;
+    quads paired with cubes give nothing."""
+    ve = partner(G, grad, e)
+    out = []
+    for q in G.cofacets(e):
+        if q == ve:
+            continue
+        p = partner(G, grad, q)
+        if p is None:
+            out.append(("s2", q))
+        elif G.dim(p) == 1:
+            out.append(("e", p))
+    return out
+
+
+def exact_path_counts(G: Grid, grad, sources):
+    """{(s1, s2): number of directed DAG paths} for the given 1-saddles, in
+    Python integers (no bound), by memoised recursion over the DAG."""
+    import sys
+    sys.setrecursionlimit(max(10000, sys.getrecursionlimit()))
+    memo = {}
+
+    def counts(e):
+        if e in memo:
+            return memo[e]
+        acc = {}
+        for kind, t in dag_out(G, grad, e):
+            if kind == "s2":
+                acc[t] = acc.get(t, 0) + 1
+            else:
+                for q, c in counts(t).items():
+                    acc[q] = acc.get(q, 0) + c
+        memo[e] = acc
+        return acc
+
+    res = {}
+    for s in sources:
+        for q, c in counts(s).items():
+            res[(s, q)] = c
     return res
 
 

@@ -78,10 +78,24 @@ typedef struct {
 
 typedef struct ms_ctx ms_ctx;
 
+/* Device allocator of a context's workspace, e.g. a framework's caching
+ * allocator.  `alloc` returns `bytes` of device memory usable by work queued
+ * on `stream` (a hipStream_t), or NULL when it cannot (the call in progress
+ * then fails with MS_ERR_OOM; the context stays usable and keeps what it
+ * holds).  `free` gives back a block with the size it was allocated with;
+ * the library drains the context's stream before it frees anything, so the
+ * block is idle.  Both receive the `user` pointer given to ms_ctx_create.
+ * Either may be called from any host thread that calls into the context. */
+typedef void* (*ms_alloc_fn)(void* user, size_t bytes, void* stream);
+typedef void (*ms_free_fn)(void* user, void* ptr, size_t bytes, void* stream);
+
 /* Creates a context bound to `stream` (a hipStream_t; NULL = the default
  * stream) on the current device.  The context owns its workspace, which grows
- * to the largest problem seen and is reused by later calls. */
-ms_status ms_ctx_create(ms_ctx** out, void* stream);
+ * to the largest problem seen and is reused by later calls.  Workspace memory
+ * comes from `alloc_fn` / `free_fn` (with `user`), or from hipMalloc /
+ * hipFree when both are NULL; giving only one of them is
+ * MS_ERR_INVALID_ARG.  Small host staging buffers are pinned host memory. */
+ms_status ms_ctx_create(ms_ctx** out, void* stream, ms_alloc_fn alloc_fn, ms_free_fn free_fn, void* user);
 void ms_ctx_destroy(ms_ctx* ctx);
 /* Rebinds the context to another stream (hipStream_t) of the same device. */
 ms_status ms_ctx_set_stream(ms_ctx* ctx, void* stream);
@@ -170,6 +184,7 @@ typedef struct {
     int64_t junctions;
     int64_t nnz_a, nnz_b, nnz_bstar, nnz_d;   /* DAG-minor matrices (Section 3.3) */
     int64_t spgemm_iters, nnz_astar, products;
+    int64_t nnz_p;                            /* entries of P = M21^T */
 } ms_stats;
 
 typedef struct {
@@ -178,6 +193,19 @@ typedef struct {
     ms_csr m32, m32t;  /* maximum x 2-saddle, and 2-saddle x maximum */
     int64_t n_saturated; /* entries of M21 equal to 2^64-1 (not an error) */
     ms_stats stats;
+    /* Ascending 3-manifolds of the minima and descending 3-manifolds of the
+     * maxima (Section 3.4: the traversal that gives the saddle-extremum arcs
+     * also gives, for every cell, the extremum its gradient path ends at;
+     * Section 3.5 keeps it in an extra array).  Device, context-owned, one
+     * uint32 per vertex, same layout as the field:
+     *   min_label[v] : rank of the minimum that the (0,1) gradient path from
+     *                  vertex v reaches (a minimum labels itself);
+     *   max_label[w] : rank of the maximum that the (2,3) gradient path from
+     *                  the cube with lowest corner w reaches, or 0xFFFFFFFF
+     *                  when there is no such cube (w on a high face) or the
+     *                  path leaves the grid through a boundary quad. */
+    uint32_t* min_label;
+    uint32_t* max_label;
 } ms_arcs;
 
 /* 1-skeleton (Sections 3.1-3.5): saddle-extremum arcs by pointer jumping;

@@ -30,6 +30,7 @@ hipError_t launch_crit_split(const uint32_t* id, const uint8_t* index, const flo
 hipError_t launch_csr_split(const uint64_t* rowptr, uint64_t nrows, const uint32_t* col, uint64_t nnz,
                             const uint64_t* roff, const uint64_t* coff, const uint64_t* eoff, uint32_t nf,
                             uint64_t* orp, uint32_t* ocol, hipStream_t s);
+hipError_t launch_manifold_labels(uint32_t* Pv, uint32_t* Pc, const Geo& g, const uint64_t* before, hipStream_t s);
 hipError_t launch_sat_per_field(const uint64_t* val, uint64_t nnz, const uint64_t* eoff, uint32_t nf,
                                 unsigned long long* out, hipStream_t s);
 
@@ -118,12 +119,16 @@ using namespace msc;
 
 extern "C" {
 
-ms_status ms_ctx_create(ms_ctx** out, void* stream) {
+ms_status ms_ctx_create(ms_ctx** out, void* stream, ms_alloc_fn alloc_fn, ms_free_fn free_fn, void* user) {
     if (!out) return MS_ERR_INVALID_ARG;
     *out = nullptr;
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) return MS_ERR_INVALID_ARG;
     ms_ctx* c = new (std::nothrow) ms_ctx();
     if (!c) return MS_ERR_OOM;
     c->stream = (hipStream_t)stream;
+    c->alloc_fn = alloc_fn;
+    c->free_fn = free_fn;
+    c->alloc_user = user;
     if (hipGetDevice(&c->device) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
@@ -145,8 +150,7 @@ ms_status ms_ctx_create(ms_ctx** out, void* stream) {
 void ms_ctx_destroy(ms_ctx* ctx) {
     if (!ctx) return;
     (void)hipStreamSynchronize(ctx->stream);
-    for (auto& kv : ctx->bufs)
-        if (kv.second.p) (void)hipFree(kv.second.p);
+    for (auto& kv : ctx->bufs) dev_free(ctx, kv.second.p, kv.second.cap);
     if (ctx->h_small) (void)hipHostFree(ctx->h_small);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -157,8 +161,7 @@ void ms_ctx_destroy(ms_ctx* ctx) {
 ms_status ms_ctx_release(ms_ctx* ctx) {
     if (!ctx) return MS_ERR_INVALID_ARG;
     (void)hipStreamSynchronize(ctx->stream);
-    for (auto& kv : ctx->bufs)
-        if (kv.second.p) (void)hipFree(kv.second.p);
+    for (auto& kv : ctx->bufs) dev_free(ctx, kv.second.p, kv.second.cap);
     ctx->bufs.clear();
     ctx->ws_bytes = 0;
     return MS_OK;
@@ -426,6 +429,7 @@ ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f
     check(ctx, hipMemcpyAsync(d_tab + 4, before.data(), 8 * 4 * (nf + 1), hipMemcpyHostToDevice, s), "table copy");
     check(ctx, hipMemcpyAsync(d_tab + 4 + 4 * (nf + 1), start.data(), 8 * 4 * nf, hipMemcpyHostToDevice, s),
           "table copy");
+    check(ctx, launch_manifold_labels(arcs.min_label, arcs.max_label, geo, d_tab + 4, s), "manifold labels");
     ms_crit fc;
     fc.id = buf<uint32_t>(ctx, "bx_crit_id", ncrit);
     fc.index = buf<uint8_t>(ctx, "bx_crit_index", ncrit);
@@ -445,6 +449,8 @@ ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f
         o.crit.capacity = (int64_t)(crit_off[f + 1] - crit_off[f]);
         for (int k = 0; k < 4; k++) o.count[k] = (int64_t)fk[4 * f + k];
         o.arcs.stats = arcs.stats;
+        o.arcs.min_label = arcs.min_label + voff[f];
+        o.arcs.max_label = arcs.max_label + voff[f];
     }
     // block-diagonal matrices -> per-field matrices
     struct M {

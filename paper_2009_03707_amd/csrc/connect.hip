@@ -18,6 +18,7 @@ hipError_t launch_m10(bool fill, const uint32_t* s1, uint64_t S1, const Geo& g, 
                       const uint64_t* rowptr, uint32_t* col, uint64_t* val, int* err, hipStream_t s);
 hipError_t launch_m32t(bool fill, const uint32_t* s2, uint64_t S2, const Geo& g, const uint32_t* Pc, uint32_t* cnt,
                        const uint64_t* rowptr, uint32_t* col, uint64_t* val, int* err, hipStream_t s);
+hipError_t launch_manifold_labels(uint32_t* Pv, uint32_t* Pc, const Geo& g, const uint64_t* before, hipStream_t s);
 int bit_width(uint64_t v);
 hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, const uint32_t* map, uint32_t* rows,
                               hipStream_t s);
@@ -563,6 +564,10 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
         check(c, launch_m32t(true, s2, S2, g, Pc, nullptr, (const uint64_t*)m32t.rowptr, m32t.col, m32t.val, d_err, s),
               "m32t fill");
         check_err_flag(c, d_err, "saddle-extremum arcs");
+        // a batch relabels with per-field ranks once its field counts are known
+        if (g.nf == 1) check(c, launch_manifold_labels(Pv, Pc, g, nullptr, s), "manifold labels");
+        out->min_label = Pv;
+        out->max_label = Pc;
         transpose(c, m10, "m10t", out->m10t);
         transpose(c, m32t, "m32", out->m32);
     }
@@ -660,6 +665,7 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
     check(c, hipMemsetAsync(d_sat, 0, 8, s), "memset");
     check(c, launch_count_sat(out->m21t.val, (uint64_t)out->m21t.nnz, d_sat, s), "count saturated");
     out->n_saturated = (int64_t)read_u64(c, (const uint64_t*)d_sat);
+    st.nnz_p = out->m21t.nnz;
 }
 
 }  // namespace msc

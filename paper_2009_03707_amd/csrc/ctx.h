@@ -19,6 +19,10 @@ constexpr size_t HOST_SCRATCH_WORDS = 8192;  // pinned readback area (uint64 wor
 struct ms_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
+    // device allocator of the workspace (hipMalloc / hipFree when null)
+    ms_alloc_fn alloc_fn = nullptr;
+    ms_free_fn free_fn = nullptr;
+    void* alloc_user = nullptr;
     std::string err;
     struct Buf {
         void* p = nullptr;
@@ -52,6 +56,28 @@ struct Fail {
     ms_status st;
 };
 
+// One workspace allocation through the context's allocator; null on failure.
+inline void* dev_alloc(ms_ctx* c, size_t bytes) {
+    void* p = nullptr;
+    if (c->alloc_fn) return c->alloc_fn(c->alloc_user, bytes, (void*)c->stream);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+// Returns a workspace allocation.  The stream is drained first, so that no
+// queued kernel still uses the memory whichever stream it was allocated on.
+inline void dev_free(ms_ctx* c, void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->free_fn)
+        c->free_fn(c->alloc_user, p, bytes, (void*)c->stream);
+    else
+        (void)hipFree(p);
+}
+
 // Device buffer `name` of at least `count` elements of T (grows, never shrinks).
 template <typename T>
 T* buf(ms_ctx* c, const char* name, size_t count) {
@@ -60,15 +86,14 @@ T* buf(ms_ctx* c, const char* name, size_t count) {
     ms_ctx::Buf& b = c->bufs[name];
     if (b.cap < bytes) {
         if (b.p) {
-            (void)hipStreamSynchronize(c->stream);
-            (void)hipFree(b.p);
+            dev_free(c, b.p, b.cap);
             c->ws_bytes -= (int64_t)b.cap;
             b.p = nullptr;
             b.cap = 0;
         }
         size_t want = bytes + bytes / 4 + 256;
-        if (hipMalloc(&b.p, want) != hipSuccess) {
-            (void)hipGetLastError();
+        b.p = dev_alloc(c, want);
+        if (!b.p) {
             c->err = std::string("device allocation of ") + std::to_string(want) + " bytes failed for " + name;
             throw Fail{MS_ERR_OOM};
         }
@@ -86,16 +111,14 @@ T* buf_keep(ms_ctx* c, const char* name, size_t count, size_t used) {
     ms_ctx::Buf& b = c->bufs[name];
     if (b.cap >= bytes) return (T*)b.p;
     size_t want = bytes + bytes / 2 + 256;
-    void* p = nullptr;
-    if (hipMalloc(&p, want) != hipSuccess) {
-        (void)hipGetLastError();
+    void* p = dev_alloc(c, want);
+    if (!p) {
         c->err = std::string("device allocation of ") + std::to_string(want) + " bytes failed for " + name;
         throw Fail{MS_ERR_OOM};
     }
     if (b.p) {
         if (used) (void)hipMemcpyAsync(p, b.p, used * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipFree(b.p);
+        dev_free(c, b.p, b.cap);
         c->ws_bytes -= (int64_t)b.cap;
     }
     b.p = p;

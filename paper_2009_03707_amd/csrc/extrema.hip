@@ -224,6 +224,32 @@ __global__ __launch_bounds__(BT) void k_m32t(const uint32_t* __restrict__ s2, ui
     }
 }
 
+// Converged pointers -> ascending and descending 3-manifolds (Section 3.4:
+// the traversal that finds the saddle-extremum arcs also gives every vertex
+// the minimum and every cube the maximum its gradient path reaches).  In
+// place: Pv[v] becomes the rank of v's minimum, Pc[w] the rank of the maximum
+// reached from the cube with lowest corner w, or EXIT_LABEL (no such cube, or
+// its path leaves the grid).  `before` (batch only; null for one field) holds
+// per field f the counts of minima (word 4f) and maxima (word 4f + 3) in
+// earlier fields, which turns batch-wide ranks into the field's own.
+__global__ __launch_bounds__(BT) void k_manifold_labels(uint32_t* __restrict__ Pv, uint32_t* __restrict__ Pc, Geo geo,
+                                                        const uint64_t* __restrict__ before) {
+#pragma unroll
+    for (int r = 0; r < PJ_EPT; r++) {
+        const uint64_t i = ((uint64_t)blockIdx.x * PJ_EPT + r) * BT + threadIdx.x;
+        if (i >= geo.nv) continue;
+        uint32_t a = Pv[i], b = Pc[i];
+        uint32_t omin = 0, omax = 0;
+        if (before) {
+            uint32_t f = geo.field_of((uint32_t)i);
+            omin = (uint32_t)before[4 * f];
+            omax = (uint32_t)before[4 * f + 3];
+        }
+        Pv[i] = (a & ~ROOT_FLAG) - omin;
+        Pc[i] = b == EXIT_LABEL ? EXIT_LABEL : (b & ~ROOT_FLAG) - omax;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_pj_init(const uint32_t* grad, const Geo& g, uint32_t* Pv, uint32_t* Pc, int* err, hipStream_t s) {
@@ -266,6 +292,13 @@ hipError_t launch_m32t(bool fill, const uint32_t* s2, uint64_t S2, const Geo& g,
     else
         hipLaunchKernelGGL(k_m32t<false>, dim3(grid_blocks(S2, BT)), dim3(BT), 0, s, s2, S2, g, Pc, cnt, rowptr, col,
                            val, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_manifold_labels(uint32_t* Pv, uint32_t* Pc, const Geo& g, const uint64_t* before, hipStream_t s) {
+    if (g.nv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_manifold_labels, dim3(grid_blocks(g.nv, (unsigned)(BT * PJ_EPT))), dim3(BT), 0, s, Pv, Pc, g,
+                       before);
     return hipGetLastError();
 }
 

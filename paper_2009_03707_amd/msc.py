@@ -50,12 +50,13 @@ class Csr(C.Structure):
 class Stats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("pj_rounds_vertex", "pj_rounds_cube", "bfs_levels", "reachable",
                                          "junctions", "nnz_a", "nnz_b", "nnz_bstar", "nnz_d", "spgemm_iters",
-                                         "nnz_astar", "products")]
+                                         "nnz_astar", "products", "nnz_p")]
 
 
 class Arcs(C.Structure):
     _fields_ = [("m10", Csr), ("m10t", Csr), ("m21", Csr), ("m21t", Csr), ("m32", Csr), ("m32t", Csr),
-                ("n_saturated", C.c_int64), ("stats", Stats)]
+                ("n_saturated", C.c_int64), ("stats", Stats), ("min_label", C.c_void_p),
+                ("max_label", C.c_void_p)]
 
 
 class Timing(C.Structure):
@@ -73,6 +74,27 @@ class Result(C.Structure):
     _fields_ = [("grad", C.c_void_p), ("crit", Crit), ("count", C.c_int64 * 4), ("arcs", Arcs)]
 
 
+# ms_alloc_fn / ms_free_fn (include/msc.h)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+def _torch_alloc(user, nbytes, stream):
+    """Workspace block from torch's caching allocator on the context's
+    stream (`user` carries the device ordinal); NULL when torch cannot."""
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), int(user or 0), int(stream or 0))
+    except Exception:  # noqa: BLE001 - any failure is reported to the library as NULL (MS_ERR_OOM)
+        return None
+
+
+def _torch_free(user, ptr, nbytes, stream):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# kept alive for the life of the module: the library holds these pointers
+TORCH_ALLOCATOR = (ALLOC_FN(_torch_alloc), FREE_FN(_torch_free))
+
 _LIB = None
 
 
@@ -84,7 +106,7 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
         L = C.CDLL(LIB_PATH)
         vp, i64 = C.c_void_p, C.c_int64
-        L.ms_ctx_create.argtypes = [C.POINTER(vp), vp]
+        L.ms_ctx_create.argtypes = [C.POINTER(vp), vp, ALLOC_FN, FREE_FN, vp]
         L.ms_ctx_destroy.argtypes = [vp]
         L.ms_ctx_destroy.restype = None
         L.ms_ctx_set_stream.argtypes = [vp, vp]
@@ -135,11 +157,24 @@ def _stream_handle():
 
 
 class Context:
-    """One ms_ctx bound to the current torch stream of the current device."""
+    """One ms_ctx bound to the current torch stream of the current device.
 
-    def __init__(self):
+    allocator: "torch" (default) takes the workspace from torch's caching
+    allocator; "hip" lets the library call hipMalloc / hipFree; or a pair
+    (alloc, free) of ALLOC_FN / FREE_FN callbacks, which the caller keeps
+    alive, with `user` passed through to them."""
+
+    def __init__(self, allocator="torch", user=None):
         self._h = C.c_void_p()
-        st = lib().ms_ctx_create(C.byref(self._h), _stream_handle())
+        if allocator == "torch":
+            fns, user = TORCH_ALLOCATOR, torch.cuda.current_device()
+        elif allocator == "hip":
+            fns = (ALLOC_FN(), FREE_FN())
+        else:
+            fns = allocator
+        self._fns = fns
+        st = lib().ms_ctx_create(C.byref(self._h), _stream_handle(), fns[0], fns[1],
+                                 C.c_void_p(user) if user else None)
         if st != MS_OK:
             raise MscError(st, "ms_ctx_create failed")
 
@@ -291,6 +326,9 @@ class Complex:
     m32t: CsrT
     n_saturated: int
     stats: dict
+    min_label: torch.Tensor  # int32 (uint32 values), shape of the field: rank of each vertex's minimum
+    max_label: torch.Tensor  # int32 (uint32 values): rank of the maximum of the cube at each lowest corner,
+    #                          0xFFFFFFFF (-1) when there is none or its path leaves the grid
 
 
 def _to_complex(r: Result, f: torch.Tensor) -> Complex:
@@ -309,6 +347,10 @@ def _to_complex(r: Result, f: torch.Tensor) -> Complex:
         m32=csr_to_torch(r.arcs.m32, dev), m32t=csr_to_torch(r.arcs.m32t, dev),
         n_saturated=int(r.arcs.n_saturated),
         stats={k: int(getattr(r.arcs.stats, k)) for k, _ in Stats._fields_},
+        min_label=_copy_dev(r.arcs.min_label or 0, 4 * nv if r.arcs.min_label else 0, torch.int32, nv,
+                            dev).view(f.shape),
+        max_label=_copy_dev(r.arcs.max_label or 0, 4 * nv if r.arcs.max_label else 0, torch.int32, nv,
+                            dev).view(f.shape),
     )
 
 

@@ -168,6 +168,20 @@ typedef struct {
 ms_status ms_critical(ms_ctx* ctx, const float* d_f, const uint32_t* d_grad, ms_dims dims,
                       const ms_crit* out, int64_t h_count[4]);
 
+/* ms_critical without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, outputs and errors as ms_critical; its
+ * pass scratch is a fixed 8 MiB device array per GPU, held by the library
+ * until the process ends (its address is taken when the first context on the
+ * device is created), so the field may hold at most about 2.6e8 vertices:
+ * larger fields give MS_ERR_TOO_LARGE before any device work.  Every call on
+ * one GPU, from any context or thread, shares that array: calls that overlap
+ * in time on one GPU (different streams or threads) race and must be
+ * serialised by the caller.  Nothing in the array needs clearing between
+ * calls: each pass writes what the next reads. */
+ms_status ms_critical_noalloc(ms_ctx* ctx, const float* d_f, const uint32_t* d_grad, ms_dims dims,
+                              const ms_crit* out, int64_t h_count[4]);
+
 /* A CSR matrix in device memory, context-owned. */
 typedef struct {
     int64_t nrows, ncols, nnz;

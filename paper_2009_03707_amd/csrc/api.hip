@@ -3,6 +3,8 @@
 // context's stream and converts failures into ms_status codes.
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "ctx.h"
@@ -60,10 +62,13 @@ void gradient_impl(ms_ctx* c, const float* f, const Grid& g, uint32_t* grad, int
           "gradient kernel launch");
 }
 
-// counts per index (host) after pass 1; optional scatter into `out`
+// counts per index (host) after pass 1; optional scatter into `out`.  The
+// pass scratch is `tmp` (crit_tmp_elems(nv) + 1 words) or, when null, the
+// context's "crit_tmp" buffer.
 void critical_impl(ms_ctx* c, const float* f, const float* const* fptr, const uint32_t* grad, const Geo& g,
-                   const ms_crit* out, int64_t h_count[4], const int* d_err, ms_status* nonfinite) {
-    uint64_t* tmp = buf<uint64_t>(c, "crit_tmp", crit_tmp_elems(g.nv) + 1);
+                   const ms_crit* out, int64_t h_count[4], const int* d_err, ms_status* nonfinite,
+                   uint64_t* tmp = nullptr) {
+    if (!tmp) tmp = buf<uint64_t>(c, "crit_tmp", crit_tmp_elems(g.nv) + 1);
     uint64_t* d_tot = nullptr;
     check(c, launch_crit_count(grad, g, tmp, &d_tot, c->stream), "critical count launch");
     uint64_t* flag_slot = tmp + crit_tmp_elems(g.nv);
@@ -93,6 +98,32 @@ void critical_impl(ms_ctx* c, const float* f, const float* const* fptr, const ui
     if (!out->id || !out->index || !out->value || !out->vmax) fail(c, MS_ERR_INVALID_ARG, "null critical output array");
     check(c, launch_crit_scatter(f, fptr, grad, g, tmp, out->id, out->index, out->value, out->vmax, c->stream),
           "critical scatter launch");
+}
+
+// ---- fixed device scratch of the allocation-free entry point ----------------
+//
+// One array per GPU, held until the process ends.  Host code never passes
+// `scratch` itself to a kernel (on the host it names a stand-in, not device
+// memory): each device's address is taken once with hipGetSymbolAddress, with
+// that device current, and kept in `scratch_addr`.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)8 << 20;
+__device__ __align__(256) uint64_t scratch[NOALLOC_SCRATCH_BYTES / sizeof(uint64_t)];
+
+std::mutex scratch_mu;
+std::map<int, uint64_t*> scratch_addr;
+
+// Address of the current device's scratch array; null if it cannot be found.
+uint64_t* scratch_for_device(int device) {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    auto it = scratch_addr.find(device);
+    if (it != scratch_addr.end()) return it->second;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    scratch_addr[device] = (uint64_t*)p;
+    return (uint64_t*)p;
 }
 
 }  // namespace msc
@@ -138,6 +169,12 @@ ms_status ms_ctx_create(ms_ctx** out, void* stream, ms_alloc_fn alloc_fn, ms_fre
         (void)hipGetLastError();
         delete c;
         return MS_ERR_OOM;
+    }
+    c->scratch = scratch_for_device(c->device);
+    if (!c->scratch) {
+        (void)hipHostFree(c->h_small);
+        delete c;
+        return MS_ERR_HIP;
     }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
@@ -253,6 +290,22 @@ ms_status ms_critical(ms_ctx* ctx, const float* d_f, const uint32_t* d_grad, ms_
     if (!d_f || !d_grad || !h_count) fail(ctx, MS_ERR_INVALID_ARG, "null argument");
     ms_status st = MS_OK;
     critical_impl(ctx, d_f, nullptr, d_grad, single(g), out, h_count, nullptr, &st);
+    if (st == MS_ERR_CAPACITY) fail(ctx, st, "critical output capacity too small");
+    API_END
+}
+
+ms_status ms_critical_noalloc(ms_ctx* ctx, const float* d_f, const uint32_t* d_grad, ms_dims dims,
+                              const ms_crit* out, int64_t h_count[4]) {
+    API_BEGIN
+    Grid g = check_dims(ctx, dims);
+    if (!d_f || !d_grad || !h_count) fail(ctx, MS_ERR_INVALID_ARG, "null argument");
+    const size_t need = (crit_tmp_elems(g.nv) + 1) * sizeof(uint64_t);
+    if (need > NOALLOC_SCRATCH_BYTES)
+        fail(ctx, MS_ERR_TOO_LARGE,
+             "field too large for the fixed scratch of ms_critical_noalloc (" + std::to_string(need) + " > " +
+                 std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes); use ms_critical");
+    ms_status st = MS_OK;
+    critical_impl(ctx, d_f, nullptr, d_grad, single(g), out, h_count, nullptr, &st, ctx->scratch);
     if (st == MS_ERR_CAPACITY) fail(ctx, st, "critical output capacity too small");
     API_END
 }

@@ -23,6 +23,7 @@ struct ms_ctx {
     ms_alloc_fn alloc_fn = nullptr;
     ms_free_fn free_fn = nullptr;
     void* alloc_user = nullptr;
+    uint64_t* scratch = nullptr;  // this device's fixed scratch (ms_critical_noalloc)
     std::string err;
     struct Buf {
         void* p = nullptr;

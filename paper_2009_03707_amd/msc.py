@@ -21,7 +21,7 @@ MS_OK, MS_ERR_INVALID_ARG, MS_ERR_NONFINITE, MS_ERR_TOO_LARGE, MS_ERR_CAPACITY, 
 
 EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_error", "ms_gradient",
             "ms_critical", "ms_connect", "ms_complex", "ms_ctx_set_timing", "ms_ctx_get_timing",
-            "ms_ctx_set_option", "ms_complex_batch", "ms_ctx_release"]
+            "ms_ctx_set_option", "ms_complex_batch", "ms_ctx_release", "ms_critical_noalloc"]
 
 MS_OPT_PATH_SCHEDULE, MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK, MS_OPT_GRADIENT_TILE = 1, 2, 3, 4
 MS_PATHS_READY, MS_PATHS_POWER, MS_PATHS_ENTRY = 0, 1, 2
@@ -114,6 +114,7 @@ def lib():
         L.ms_last_error.restype = C.c_char_p
         L.ms_gradient.argtypes = [vp, vp, Dims, vp]
         L.ms_critical.argtypes = [vp, vp, vp, Dims, C.POINTER(Crit), C.POINTER(i64)]
+        L.ms_critical_noalloc.argtypes = [vp, vp, vp, Dims, C.POINTER(Crit), C.POINTER(i64)]
         L.ms_connect.argtypes = [vp, vp, Dims, vp, C.POINTER(i64), C.POINTER(Arcs)]
         L.ms_complex.argtypes = [vp, vp, Dims, C.POINTER(Result)]
         L.ms_ctx_set_timing.argtypes = [vp, C.c_int]
@@ -245,6 +246,24 @@ class Context:
                                C.byref(cr), cnt)
         self._raise(st, "ms_critical")
         return ids[:n], idx[:n], val[:n], vm[:n], list(cnt)
+
+    def critical_noalloc(self, f: torch.Tensor, grad: torch.Tensor, out=None):
+        """ms_critical_noalloc: the library allocates no device memory (its
+        scratch is a fixed per-GPU array).  `out` = (id, index, value, vmax)
+        tensors to fill (capacity = the shortest), or None to query the counts
+        only.  Returns the counts per index; raises MscError (MS_ERR_CAPACITY,
+        MS_ERR_TOO_LARGE, ...) like the library."""
+        _check_field(f)
+        self._sync_stream()
+        cnt = (C.c_int64 * 4)()
+        cr = None
+        if out is not None:
+            cap = min(int(t.numel()) for t in out)
+            cr = C.byref(Crit(out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), out[3].data_ptr(), cap))
+        st = lib().ms_critical_noalloc(self._h, C.c_void_p(f.data_ptr()), C.c_void_p(grad.data_ptr()), _dims(f),
+                                       cr, cnt)
+        self._raise(st, "ms_critical_noalloc")
+        return list(cnt)
 
     def connect(self, grad: torch.Tensor, dims, crit_id: torch.Tensor, counts) -> "Arcs":
         self._sync_stream()

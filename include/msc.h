@@ -295,6 +295,91 @@ ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out
 ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f, const ms_dims* dims,
                            ms_result* outs);
 
+/* ---- Host MS-complex graph (Section 3.5, "Data structure") ---------------
+ *
+ * The 1-skeleton as a host data structure for queries: a vector of critical
+ * points (nodes) and, per node, its arcs in each direction with their
+ * multiplicities; every arc is stored at both of its ends.  Node i is the
+ * i-th entry of the critical list sorted by (index, cell id), i.e. node =
+ * (number of critical cells of lower index) + rank.  A graph is independent
+ * of the context once built; it is not thread-safe (one thread at a time). */
+typedef struct ms_graph ms_graph;
+
+typedef struct {
+    uint32_t cell;   /* critical cell id */
+    uint8_t index;   /* 0..3 */
+    uint8_t alive;   /* 0 once cancelled by ms_graph_simplify */
+    float value;     /* f at the cell's highest vertex */
+    uint32_t vmax;   /* id of that vertex */
+} ms_node;
+
+enum { MS_DOWN = 0, MS_UP = 1 }; /* arcs to index - 1 / to index + 1 */
+
+/* Builds the graph of a result of ms_complex or ms_complex_batch (one
+ * field): copies its critical list and its six arc matrices to host memory
+ * (synchronises the context's stream), then fills the arc lists, one worker
+ * thread per range of nodes and direction (nthreads >= 1, as the paper
+ * parallelises the population across critical points).  `dims` are the
+ * field's dims (they place the nodes for ms_graph_simplify's subgrids).
+ * Errors: MS_ERR_INVALID_ARG (null arguments, inconsistent sizes),
+ * MS_ERR_OOM (host memory), MS_ERR_HIP. */
+ms_status ms_graph_build(ms_ctx* ctx, const ms_result* result, ms_dims dims, int nthreads, ms_graph** out);
+/* The same from a result whose arrays (critical list and CSR arrays; grad
+ * and the labels are not read) are in host memory, e.g. copied back
+ * earlier; needs no device.  Errors as ms_graph_build; *out is NULL on
+ * failure and the reason is not recorded anywhere else. */
+ms_status ms_graph_build_host(const ms_result* result, ms_dims dims, int nthreads, ms_graph** out);
+void ms_graph_destroy(ms_graph* g);
+/* Number of nodes, cancelled ones included. */
+int64_t ms_graph_num_nodes(const ms_graph* g);
+const char* ms_graph_last_error(const ms_graph* g);
+/* Attributes of node `node` (0 <= node < ms_graph_num_nodes). */
+ms_status ms_graph_node(const ms_graph* g, int64_t node, ms_node* out);
+/* Node of critical cell `cell`; MS_ERR_INVALID_ARG if it is not critical. */
+ms_status ms_graph_find(const ms_graph* g, uint32_t cell, int64_t* node);
+/* Live arcs of a live node in direction `dir` (MS_DOWN or MS_UP), sorted by
+ * neighbour node: neighbour ids into nbr[] and multiplicities (numbers of
+ * gradient paths, saturating at 2^64-1) into mult[], at most `cap` of them
+ * (host arrays); *count receives the number of arcs.  MS_ERR_CAPACITY when
+ * *count > cap (the first cap are written).  A cancelled node has none. */
+ms_status ms_graph_arcs(const ms_graph* g, int64_t node, int dir, int64_t* nbr, uint64_t* mult, int64_t cap,
+                        int64_t* count);
+/* Live nodes per index and live arcs per index pair (1-0, 2-1, 3-2). */
+ms_status ms_graph_counts(const ms_graph* g, int64_t alive[4], int64_t arcs[3]);
+
+/* ---- Persistence-driven simplification (Section 2.1; Section 4) ----------
+ *
+ * Cancels critical pairs (p, q), index(p) = index(q) + 1, joined by exactly
+ * one gradient path (multiplicity 1; pairs joined by several paths would
+ * strangle and are never cancelled), whose persistence |f(p) - f(q)| (in
+ * double) is below `threshold`.  A cancellation reroutes p's descending
+ * arcs to the destinations of q's ascending arcs: every other upper
+ * neighbour s of q gains m(s,q) * m(p,r) paths to every other lower
+ * neighbour r of p; p, q and their arcs are deleted.
+ *   MS_SIMPLIFY_SERIAL : always cancel the valid arc that is least in the
+ *     order (persistence, upper node, lower node); deterministic.
+ *   MS_SIMPLIFY_SUBGRID: the paper's grid subdivision (Section 4.1-4.2):
+ *     the grid is cut into `nthreads` slabs along X, Y, Z and again with the
+ *     cuts shifted by half a slab; in each round the ends of arcs crossing a
+ *     cut are frozen and every slab cancels its own valid arcs in serial
+ *     order on its own thread (the slabs never share a node, so their
+ *     cancellations commute); a final serial round follows.  The result can
+ *     differ from the serial order's, as the paper notes; every cancellation
+ *     in it is valid at its place in ms_graph_cancellations' log.
+ * *ncancelled (may be NULL) receives the cancellations made by this call.
+ * Can be called again with a larger threshold. */
+enum { MS_SIMPLIFY_SERIAL = 0, MS_SIMPLIFY_SUBGRID = 1 };
+ms_status ms_graph_simplify(ms_graph* g, double threshold, int schedule, int nthreads, int64_t* ncancelled);
+
+/* The cancellations made so far, in an order in which they are valid one
+ * after the other (the hierarchy of the simplification). */
+typedef struct {
+    int64_t upper, lower;  /* nodes; index(upper) = index(lower) + 1 */
+    double persistence;
+} ms_cancellation;
+int64_t ms_graph_num_cancellations(const ms_graph* g);
+ms_status ms_graph_cancellations(const ms_graph* g, int64_t first, int64_t n, ms_cancellation* out);
+
 #ifdef __cplusplus
 }
 #endif

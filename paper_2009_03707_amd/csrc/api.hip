@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "graph.h"
 #include "prims.h"
 
 namespace msc {
@@ -553,6 +554,114 @@ ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f
     mark(ctx, 6);
     accumulate_timing(ctx);
     API_END
+}
+
+}  // extern "C"
+
+namespace msc {
+
+// Fills `in` from a result; `copy(dst, src, bytes)` moves one array to the
+// host.  Returns an error text, empty on success.
+template <typename Copy>
+std::string graph_input(const ms_result* r, ms_dims dims, GraphInput& in, Copy&& copy) {
+    in.dims[0] = dims.nx;
+    in.dims[1] = dims.ny;
+    in.dims[2] = dims.nz;
+    int64_t tot = 0;
+    for (int k = 0; k < 4; k++) {
+        if (r->count[k] < 0) return "negative critical count";
+        in.count[k] = r->count[k];
+        tot += r->count[k];
+    }
+    if (tot > 0 && (!r->crit.id || !r->crit.index || !r->crit.value || !r->crit.vmax))
+        return "null critical array in the result";
+    in.id.resize((size_t)tot);
+    in.index.resize((size_t)tot);
+    in.value.resize((size_t)tot);
+    in.vmax.resize((size_t)tot);
+    copy(in.id.data(), r->crit.id, 4 * (size_t)tot);
+    copy(in.index.data(), r->crit.index, (size_t)tot);
+    copy(in.value.data(), r->crit.value, 4 * (size_t)tot);
+    copy(in.vmax.data(), r->crit.vmax, 4 * (size_t)tot);
+    const ms_csr* src[6] = {&r->arcs.m10, &r->arcs.m10t, &r->arcs.m21, &r->arcs.m21t, &r->arcs.m32, &r->arcs.m32t};
+    HostCsr* dst[6] = {&in.m10, &in.m10t, &in.m21, &in.m21t, &in.m32, &in.m32t};
+    for (int i = 0; i < 6; i++) {
+        const ms_csr& m = *src[i];
+        if (m.nrows < 0 || m.ncols < 0 || m.nnz < 0) return "bad matrix sizes";
+        if (!m.rowptr && m.nrows > 0) return "null rowptr in the result";
+        if (m.nnz > 0 && (!m.col || !m.val)) return "null matrix array in the result";
+        HostCsr& h = *dst[i];
+        h.nrows = m.nrows;
+        h.ncols = m.ncols;
+        h.rowptr.assign((size_t)m.nrows + 1, 0);
+        h.col.resize((size_t)m.nnz);
+        h.val.resize((size_t)m.nnz);
+        if (m.rowptr) copy(h.rowptr.data(), m.rowptr, 8 * ((size_t)m.nrows + 1));
+        copy(h.col.data(), m.col, 4 * (size_t)m.nnz);
+        copy(h.val.data(), m.val, 8 * (size_t)m.nnz);
+    }
+    return "";
+}
+
+std::string graph_check_rowptrs(const GraphInput& in) {
+    for (const HostCsr* h : {&in.m10, &in.m10t, &in.m21, &in.m21t, &in.m32, &in.m32t}) {
+        if (h->rowptr[0] != 0 || h->rowptr.back() != (int64_t)h->col.size())
+            return "matrix rowptr does not match its nnz";
+        for (size_t i = 0; i + 1 < h->rowptr.size(); i++)
+            if (h->rowptr[i + 1] < h->rowptr[i]) return "matrix rowptr decreases";
+        for (uint32_t c : h->col)
+            if ((int64_t)c >= h->ncols) return "matrix column out of range";
+    }
+    return "";
+}
+
+}  // namespace msc
+
+extern "C" {
+
+ms_status ms_graph_build(ms_ctx* ctx, const ms_result* r, ms_dims dims, int nthreads, ms_graph** out) {
+    API_BEGIN
+    if (!r || !out || nthreads < 1 || nthreads > 1024) fail(ctx, MS_ERR_INVALID_ARG, "null argument or bad thread count");
+    *out = nullptr;
+    check_dims(ctx, dims);
+    GraphInput in;
+    std::string e;
+    try {
+        e = graph_input(r, dims, in, [&](void* dst, const void* src, size_t bytes) {
+            if (bytes) check(ctx, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, ctx->stream), "copy to host");
+        });
+    } catch (const std::bad_alloc&) {
+        fail(ctx, MS_ERR_OOM, "host allocation failed");
+    }
+    check(ctx, hipStreamSynchronize(ctx->stream), "stream synchronize");
+    if (e.empty()) e = graph_check_rowptrs(in);
+    if (!e.empty()) fail(ctx, MS_ERR_INVALID_ARG, e);
+    ms_graph* g = graph_from_host(in, nthreads, &e);
+    if (!g) fail(ctx, MS_ERR_INVALID_ARG, e);
+    *out = g;
+    API_END
+}
+
+ms_status ms_graph_build_host(const ms_result* r, ms_dims dims, int nthreads, ms_graph** out) {
+    if (!out) return MS_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!r || nthreads < 1 || nthreads > 1024 || dims.nx < 1 || dims.ny < 1 || dims.nz < 1) return MS_ERR_INVALID_ARG;
+    try {
+        GraphInput in;
+        std::string e = graph_input(r, dims, in, [](void* dst, const void* src, size_t bytes) {
+            if (bytes) memcpy(dst, src, bytes);
+        });
+        if (e.empty()) e = graph_check_rowptrs(in);
+        if (!e.empty()) return MS_ERR_INVALID_ARG;
+        ms_graph* g = graph_from_host(in, nthreads, &e);
+        if (!g) return MS_ERR_INVALID_ARG;
+        *out = g;
+    } catch (const std::bad_alloc&) {
+        return MS_ERR_OOM;
+    } catch (...) {
+        return MS_ERR_INTERNAL;
+    }
+    return MS_OK;
 }
 
 }  // extern "C"

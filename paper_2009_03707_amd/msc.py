@@ -21,7 +21,12 @@ MS_OK, MS_ERR_INVALID_ARG, MS_ERR_NONFINITE, MS_ERR_TOO_LARGE, MS_ERR_CAPACITY, 
 
 EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_error", "ms_gradient",
             "ms_critical", "ms_connect", "ms_complex", "ms_ctx_set_timing", "ms_ctx_get_timing",
-            "ms_ctx_set_option", "ms_complex_batch", "ms_ctx_release", "ms_critical_noalloc"]
+            "ms_ctx_set_option", "ms_complex_batch", "ms_ctx_release", "ms_critical_noalloc",
+            "ms_graph_build", "ms_graph_build_host", "ms_graph_destroy", "ms_graph_num_nodes", "ms_graph_last_error",
+            "ms_graph_node", "ms_graph_find", "ms_graph_arcs", "ms_graph_counts", "ms_graph_simplify",
+            "ms_graph_num_cancellations", "ms_graph_cancellations"]
+MS_DOWN, MS_UP = 0, 1
+MS_SIMPLIFY_SERIAL, MS_SIMPLIFY_SUBGRID = 0, 1
 
 MS_OPT_PATH_SCHEDULE, MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK, MS_OPT_GRADIENT_TILE = 1, 2, 3, 4
 MS_PATHS_READY, MS_PATHS_POWER, MS_PATHS_ENTRY = 0, 1, 2
@@ -74,6 +79,15 @@ class Result(C.Structure):
     _fields_ = [("grad", C.c_void_p), ("crit", Crit), ("count", C.c_int64 * 4), ("arcs", Arcs)]
 
 
+class Node(C.Structure):
+    _fields_ = [("cell", C.c_uint32), ("index", C.c_uint8), ("alive", C.c_uint8), ("value", C.c_float),
+                ("vmax", C.c_uint32)]
+
+
+class Cancellation(C.Structure):
+    _fields_ = [("upper", C.c_int64), ("lower", C.c_int64), ("persistence", C.c_double)]
+
+
 # ms_alloc_fn / ms_free_fn (include/msc.h)
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -122,6 +136,22 @@ def lib():
         L.ms_ctx_set_option.argtypes = [vp, C.c_int, C.c_int64]
         L.ms_complex_batch.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(Dims), C.POINTER(Result)]
         L.ms_ctx_release.argtypes = [vp]
+        L.ms_graph_build.argtypes = [vp, C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
+        L.ms_graph_build_host.argtypes = [C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
+        L.ms_graph_destroy.argtypes = [vp]
+        L.ms_graph_destroy.restype = None
+        L.ms_graph_num_nodes.argtypes = [vp]
+        L.ms_graph_num_nodes.restype = i64
+        L.ms_graph_last_error.argtypes = [vp]
+        L.ms_graph_last_error.restype = C.c_char_p
+        L.ms_graph_node.argtypes = [vp, i64, C.POINTER(Node)]
+        L.ms_graph_find.argtypes = [vp, C.c_uint32, C.POINTER(i64)]
+        L.ms_graph_arcs.argtypes = [vp, i64, C.c_int, vp, vp, i64, C.POINTER(i64)]
+        L.ms_graph_counts.argtypes = [vp, C.POINTER(i64), C.POINTER(i64)]
+        L.ms_graph_simplify.argtypes = [vp, C.c_double, C.c_int, C.c_int, C.POINTER(i64)]
+        L.ms_graph_num_cancellations.argtypes = [vp]
+        L.ms_graph_num_cancellations.restype = i64
+        L.ms_graph_cancellations.argtypes = [vp, i64, i64, C.POINTER(Cancellation)]
         for n in EXPORTED:
             getattr(L, n)
         _LIB = L
@@ -399,3 +429,95 @@ def complex_batch(fs, ctx: Context | None = None):
     finally:
         if own:
             ctx.close()
+
+
+# -- host MS-complex graph and simplification ----------------------------------
+
+class Graph:
+    """ms_graph: the 1-skeleton as a host graph (nodes = critical points in
+    the order of the critical list, arcs in both directions with
+    multiplicities) and its persistence-driven simplification."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def from_result(cls, ctx: "Context", result: Result, dims, nthreads: int = 8) -> "Graph":
+        """From a (device) result of ms_complex / ms_complex_batch; dims =
+        (nx, ny, nz) of the field."""
+        h = C.c_void_p()
+        ctx._sync_stream()
+        st = lib().ms_graph_build(ctx._h, C.byref(result), Dims(*dims), int(nthreads), C.byref(h))
+        ctx._raise(st, "ms_graph_build")
+        return cls(h)
+
+    @classmethod
+    def from_host(cls, result: Result, dims, nthreads: int = 8) -> "Graph":
+        """From a result whose critical list and CSR arrays are host memory."""
+        h = C.c_void_p()
+        st = lib().ms_graph_build_host(C.byref(result), Dims(*dims), int(nthreads), C.byref(h))
+        if st != MS_OK:
+            raise MscError(st, "ms_graph_build_host")
+        return cls(h)
+
+    def close(self):
+        if self._h:
+            lib().ms_graph_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ok(self, st, what):
+        if st != MS_OK:
+            msg = lib().ms_graph_last_error(self._h)
+            raise MscError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    def num_nodes(self) -> int:
+        return int(lib().ms_graph_num_nodes(self._h))
+
+    def node(self, i: int) -> dict:
+        n = Node()
+        self._ok(lib().ms_graph_node(self._h, int(i), C.byref(n)), "ms_graph_node")
+        return {k: getattr(n, k) for k, _ in Node._fields_}
+
+    def find(self, cell: int) -> int:
+        out = C.c_int64()
+        self._ok(lib().ms_graph_find(self._h, int(cell), C.byref(out)), "ms_graph_find")
+        return out.value
+
+    def arcs(self, i: int, direction: int):
+        """(neighbour nodes int64[], multiplicities uint64[]) of a node."""
+        import numpy as np
+        cnt = C.c_int64()
+        st = lib().ms_graph_arcs(self._h, int(i), int(direction), None, None, 0, C.byref(cnt))
+        if st not in (MS_OK, MS_ERR_CAPACITY):
+            self._ok(st, "ms_graph_arcs")
+        n = cnt.value
+        nbr = np.zeros(max(n, 1), np.int64)
+        mult = np.zeros(max(n, 1), np.uint64)
+        self._ok(lib().ms_graph_arcs(self._h, int(i), int(direction), nbr.ctypes.data, mult.ctypes.data, n,
+                                     C.byref(cnt)), "ms_graph_arcs")
+        return nbr[:n], mult[:n]
+
+    def counts(self):
+        alive = (C.c_int64 * 4)()
+        arcs = (C.c_int64 * 3)()
+        self._ok(lib().ms_graph_counts(self._h, alive, arcs), "ms_graph_counts")
+        return list(alive), list(arcs)
+
+    def simplify(self, threshold: float, schedule: int = MS_SIMPLIFY_SERIAL, nthreads: int = 1) -> int:
+        n = C.c_int64()
+        self._ok(lib().ms_graph_simplify(self._h, float(threshold), int(schedule), int(nthreads), C.byref(n)),
+                 "ms_graph_simplify")
+        return n.value
+
+    def cancellations(self):
+        """[(upper, lower, persistence)] in the order they were made."""
+        n = int(lib().ms_graph_num_cancellations(self._h))
+        buf = (Cancellation * max(n, 1))()
+        self._ok(lib().ms_graph_cancellations(self._h, 0, n, buf), "ms_graph_cancellations")
+        return [(buf[i].upper, buf[i].lower, buf[i].persistence) for i in range(n)]

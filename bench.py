@@ -202,6 +202,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=160, help="side of the oracle crop (0 = skip)")
     ap.add_argument("--batch", type=int, default=64, help="fields in the batched comparison (0 = skip)")
     ap.add_argument("--no-autotune", action="store_true", help="use the default launch parameters")
+    ap.add_argument("--params", default=None,
+                    help='fixed launch parameters instead of autotuning, e.g. \'{"tile": 5, "schedule": 2}\'')
     ap.add_argument("--serve-steps", type=int, default=200,
                     help="timesteps of the served advected-field stream (0 = skip)")
     ap.add_argument("--serve-slots", type=int, default=3)
@@ -235,7 +237,11 @@ def main():
     fd = torch.from_numpy(f).cuda()
     ctx = msc.Context()
     tuned = None
-    if not args.no_autotune:
+    if args.params:
+        from paper_2009_03707_amd import autotune
+        tuned = dict(autotune.DEFAULT, **json.loads(args.params))
+        autotune.apply(ctx, tuned)
+    elif not args.no_autotune:
         from paper_2009_03707_amd import autotune
         tuned = autotune.tune(ctx, [fd], log=log)
     for i in range(args.warmup):

@@ -153,13 +153,14 @@ __device__ __forceinline__ uint32_t ctz32(uint32_t x) { return (uint32_t)__built
 
 // Rank count over the 26 neighbours: for every pair a < b of star indices
 // (centre excluded), d = [K[a] > K[b]] (b precedes a) moves one unit from
-// rk[b] to rk[a].  d is a clamped (saturating) subtract and a min with 1;
-// with the two updates that is four plain VALU operations per pair.  They
-// are written out so that the compiler neither turns d back into a compare
-// (whose lane mask would have to be read back after wait states) nor keeps
-// many d values live to re-associate the sums.  The 325 pairs are taken in
-// the 25 rounds of a round-robin schedule (13 disjoint pairs per round), four
-// disjoint pairs per block, so one block never updates a rank twice.
+// rk[b] to rk[a].  d is a compare into a lane mask that is consumed at once
+// as the carry-in of an add and the borrow-in of a subtract: three plain
+// VALU operations per pair.  The 325 pairs are taken in the 25 rounds of a
+// round-robin schedule (13 disjoint pairs per round), four disjoint pairs
+// per block with their masks in separate SGPR pairs, so one block never
+// updates a rank twice and the compares of a block are issued before the
+// adds that read them (at least three instructions later, more than the two
+// wait states gfx950 needs between a VALU write of an SGPR and a VALU read).
 struct PairSchedule {
     uint8_t a[325], b[325];
 };
@@ -183,12 +184,12 @@ __host__ __device__ constexpr PairSchedule make_schedule() {
 constexpr PairSchedule kPairs = make_schedule();
 
 __device__ __forceinline__ void rank_pair(uint32_t ka, uint32_t kb, uint32_t& ra, uint32_t& rb) {
-    uint32_t d;
-    asm("v_sub_u32_e64 %2, %3, %4 clamp\n\t"
-        "v_min_u32_e32 %2, 1, %2\n\t"
-        "v_add_u32_e32 %0, %0, %2\n\t"
-        "v_sub_u32_e32 %1, %1, %2"
-        : "+v"(ra), "+v"(rb), "=&v"(d)
+    uint64_t m, junk;
+    asm("v_cmp_gt_u32_e64 %2, %4, %5\n\t"
+        "s_nop 1\n\t"  // two wait states before a VALU reads an SGPR a VALU wrote
+        "v_addc_co_u32_e64 %0, %3, %0, 0, %2\n\t"
+        "v_subb_co_u32_e64 %1, %3, %1, 0, %2"
+        : "+v"(ra), "+v"(rb), "=&s"(m), "=&s"(junk)
         : "v"(ka), "v"(kb));
 }
 
@@ -197,25 +198,21 @@ __device__ __forceinline__ void rank_pair4(uint32_t ka0, uint32_t kb0, uint32_t&
                                            uint32_t kb1, uint32_t& ra1, uint32_t& rb1, uint32_t ka2, uint32_t kb2,
                                            uint32_t& ra2, uint32_t& rb2, uint32_t ka3, uint32_t kb3, uint32_t& ra3,
                                            uint32_t& rb3) {
-    uint32_t d0, d1, d2, d3;
-    asm("v_sub_u32_e64 %8, %12, %13 clamp\n\t"
-        "v_sub_u32_e64 %9, %14, %15 clamp\n\t"
-        "v_sub_u32_e64 %10, %16, %17 clamp\n\t"
-        "v_sub_u32_e64 %11, %18, %19 clamp\n\t"
-        "v_min_u32_e32 %8, 1, %8\n\t"
-        "v_min_u32_e32 %9, 1, %9\n\t"
-        "v_min_u32_e32 %10, 1, %10\n\t"
-        "v_min_u32_e32 %11, 1, %11\n\t"
-        "v_add_u32_e32 %0, %0, %8\n\t"
-        "v_sub_u32_e32 %1, %1, %8\n\t"
-        "v_add_u32_e32 %2, %2, %9\n\t"
-        "v_sub_u32_e32 %3, %3, %9\n\t"
-        "v_add_u32_e32 %4, %4, %10\n\t"
-        "v_sub_u32_e32 %5, %5, %10\n\t"
-        "v_add_u32_e32 %6, %6, %11\n\t"
-        "v_sub_u32_e32 %7, %7, %11"
-        : "+v"(ra0), "+v"(rb0), "+v"(ra1), "+v"(rb1), "+v"(ra2), "+v"(rb2), "+v"(ra3), "+v"(rb3), "=&v"(d0),
-          "=&v"(d1), "=&v"(d2), "=&v"(d3)
+    uint64_t m0, m1, m2, m3, junk;
+    asm("v_cmp_gt_u32_e64 %8, %13, %14\n\t"
+        "v_cmp_gt_u32_e64 %9, %15, %16\n\t"
+        "v_cmp_gt_u32_e64 %10, %17, %18\n\t"
+        "v_cmp_gt_u32_e64 %11, %19, %20\n\t"
+        "v_addc_co_u32_e64 %0, %12, %0, 0, %8\n\t"
+        "v_subb_co_u32_e64 %1, %12, %1, 0, %8\n\t"
+        "v_addc_co_u32_e64 %2, %12, %2, 0, %9\n\t"
+        "v_subb_co_u32_e64 %3, %12, %3, 0, %9\n\t"
+        "v_addc_co_u32_e64 %4, %12, %4, 0, %10\n\t"
+        "v_subb_co_u32_e64 %5, %12, %5, 0, %10\n\t"
+        "v_addc_co_u32_e64 %6, %12, %6, 0, %11\n\t"
+        "v_subb_co_u32_e64 %7, %12, %7, 0, %11"
+        : "+v"(ra0), "+v"(rb0), "+v"(ra1), "+v"(rb1), "+v"(ra2), "+v"(rb2), "+v"(ra3), "+v"(rb3), "=&s"(m0),
+          "=&s"(m1), "=&s"(m2), "=&s"(m3), "=&s"(junk)
         : "v"(ka0), "v"(kb0), "v"(ka1), "v"(kb1), "v"(ka2), "v"(kb2), "v"(ka3), "v"(kb3));
 }
 

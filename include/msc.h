@@ -118,7 +118,13 @@ enum {
     /* Gradient workgroup tile in vertices: 0 = 16x8x4 (default), 1 = 32x4x4,
      * 2 = 8x8x8, 3 = 16x16x2, 4 = 16x8x8, 5 = 16x16x8, 6 = 32x16x8.  Results
      * never depend on it. */
-    MS_OPT_GRADIENT_TILE = 4
+    MS_OPT_GRADIENT_TILE = 4,
+    /* ms_complex_batch: 1 (default) captures the fixed-shape front of a
+     * batch (gradient, critical counts, their scan and totals) in a HIP
+     * graph per set of dims and replays it while the dims and the context's
+     * buffers stay the same; 0 launches it eagerly.  The graph is also
+     * bypassed while timing is on.  Results never depend on it. */
+    MS_OPT_BATCH_GRAPH = 5
 };
 enum {
     /* Default.  A* is the solution of A* = A + A* B; its columns are formed by
@@ -265,6 +271,9 @@ typedef struct {
      * entries ranked and run heads written. */
     double rank_ms;
     int64_t rank_launches, rank_entries, rank_heads;
+    /* graphs of the batch front captured / replayed by this context since it
+     * was created (not reset by enabling timing) */
+    int64_t graph_captures, graph_replays;
 } ms_timing;
 
 /* Enables (1) or disables (0) timing; enabling resets the accumulators. */

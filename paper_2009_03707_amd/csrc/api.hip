@@ -16,6 +16,7 @@ uint32_t gradient_tiles(const Grid& g, int shape);
 hipError_t launch_gradient(int shape, const float* f0, const float* const* fptr, const Geo& geo,
                            const uint32_t* tile_off, uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s);
 size_t crit_tmp_elems(uint64_t nv);
+const uint64_t* crit_totals_ptr(const uint64_t* tmp, uint64_t nv);
 hipError_t launch_crit_count(const uint32_t* grad, const Geo& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s);
 hipError_t launch_crit_scatter(const float* f0, const float* const* fptr, const uint32_t* grad, const Geo& g,
                                const uint64_t* tmp, uint32_t* id, uint8_t* index, float* value, uint32_t* vmax,
@@ -55,9 +56,24 @@ Grid check_dims(ms_ctx* c, ms_dims d) {
     return Grid::make(d.nx, d.ny, d.nz);
 }
 
+// The non-finite flag is cleared and copied by kernels rather than by
+// memset / memcpy nodes, so that the front of a batch can be captured in a
+// graph and replayed.
+__global__ void k_flag_clear(int* err) {
+    if (threadIdx.x == 0) *err = 0;
+}
+__global__ void k_flag_copy(const int* err, uint64_t* slot) {
+    if (threadIdx.x == 0) *slot = err ? (uint64_t)(*err != 0) : 0ull;
+}
+
+void flag_clear(ms_ctx* c, int* d_err) {
+    hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, c->stream, d_err);
+    check(c, hipGetLastError(), "clear error flag");
+}
+
 // gradient + non-finite flag (flag left on the device at *d_err)
 void gradient_impl(ms_ctx* c, const float* f, const Grid& g, uint32_t* grad, int* d_err) {
-    check(c, hipMemsetAsync(d_err, 0, sizeof(int), c->stream), "clear error flag");
+    flag_clear(c, d_err);
     check(c, launch_gradient(c->grad_tile, f, nullptr, single(g), nullptr, gradient_tiles(g, c->grad_tile), grad, d_err,
                              c->stream),
           "gradient kernel launch");
@@ -66,17 +82,20 @@ void gradient_impl(ms_ctx* c, const float* f, const Grid& g, uint32_t* grad, int
 // counts per index (host) after pass 1; optional scatter into `out`.  The
 // pass scratch is `tmp` (crit_tmp_elems(nv) + 1 words) or, when null, the
 // context's "crit_tmp" buffer.
-void critical_impl(ms_ctx* c, const float* f, const float* const* fptr, const uint32_t* grad, const Geo& g,
-                   const ms_crit* out, int64_t h_count[4], const int* d_err, ms_status* nonfinite,
-                   uint64_t* tmp = nullptr) {
-    if (!tmp) tmp = buf<uint64_t>(c, "crit_tmp", crit_tmp_elems(g.nv) + 1);
+// Pass 1 of the extraction (counts, scan, totals) and the copy of the
+// non-finite flag (0 without d_err) into the slot after them: kernels only.
+void critical_front(ms_ctx* c, const uint32_t* grad, const Geo& g, uint64_t* tmp, const int* d_err) {
     uint64_t* d_tot = nullptr;
     check(c, launch_crit_count(grad, g, tmp, &d_tot, c->stream), "critical count launch");
+    hipLaunchKernelGGL(k_flag_copy, dim3(1), dim3(64), 0, c->stream, d_err, tmp + crit_tmp_elems(g.nv));
+    check(c, hipGetLastError(), "flag copy");
+}
+
+// Reads the counts (and flag) back after critical_front; optional scatter.
+void critical_finish(ms_ctx* c, const float* f, const float* const* fptr, const uint32_t* grad, const Geo& g,
+                     const ms_crit* out, int64_t h_count[4], const int* d_err, ms_status* nonfinite, uint64_t* tmp) {
+    const uint64_t* d_tot = crit_totals_ptr(tmp, g.nv);
     uint64_t* flag_slot = tmp + crit_tmp_elems(g.nv);
-    if (d_err) {
-        check(c, hipMemsetAsync(flag_slot, 0, sizeof(uint64_t), c->stream), "flag clear");
-        check(c, hipMemcpyAsync(flag_slot, d_err, sizeof(int), hipMemcpyDeviceToDevice, c->stream), "flag copy");
-    }
     check(c, hipMemcpyAsync(c->h_small, d_tot, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream), "readback");
     check(c, hipMemcpyAsync(c->h_small + 8, flag_slot, sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream),
           "readback");
@@ -99,6 +118,14 @@ void critical_impl(ms_ctx* c, const float* f, const float* const* fptr, const ui
     if (!out->id || !out->index || !out->value || !out->vmax) fail(c, MS_ERR_INVALID_ARG, "null critical output array");
     check(c, launch_crit_scatter(f, fptr, grad, g, tmp, out->id, out->index, out->value, out->vmax, c->stream),
           "critical scatter launch");
+}
+
+void critical_impl(ms_ctx* c, const float* f, const float* const* fptr, const uint32_t* grad, const Geo& g,
+                   const ms_crit* out, int64_t h_count[4], const int* d_err, ms_status* nonfinite,
+                   uint64_t* tmp = nullptr) {
+    if (!tmp) tmp = buf<uint64_t>(c, "crit_tmp", crit_tmp_elems(g.nv) + 1);
+    critical_front(c, grad, g, tmp, d_err);
+    critical_finish(c, f, fptr, grad, g, out, h_count, d_err, nonfinite, tmp);
 }
 
 // ---- fixed device scratch of the allocation-free entry point ----------------
@@ -193,6 +220,8 @@ void ms_ctx_destroy(ms_ctx* ctx) {
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : ctx->rank_ev) (void)hipEventDestroy(e);
+    if (ctx->front_exec) (void)hipGraphExecDestroy(ctx->front_exec);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     delete ctx;
 }
 
@@ -231,6 +260,10 @@ ms_status ms_ctx_set_option(ms_ctx* ctx, int option, int64_t value) {
         ctx->grad_tile = (int)value;
         return MS_OK;
     }
+    if (option == MS_OPT_BATCH_GRAPH && (value == 0 || value == 1)) {
+        ctx->batch_graph = value != 0;
+        return MS_OK;
+    }
     ctx->err = "unknown option or value";
     return MS_ERR_INVALID_ARG;
 }
@@ -267,6 +300,8 @@ ms_status ms_ctx_get_timing(ms_ctx* ctx, ms_timing* out) {
     out->rank_launches = ctx->rank_launches;
     out->rank_entries = ctx->rank_entries;
     out->rank_heads = ctx->rank_heads;
+    out->graph_captures = ctx->front_captures;
+    out->graph_replays = ctx->front_replays;
     return MS_OK;
 }
 
@@ -361,7 +396,7 @@ ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out
     memset(out, 0, sizeof(*out));
     uint32_t* grad = buf<uint32_t>(ctx, "cx_grad", g.nv);
     int* d_err = buf<int>(ctx, "err_flag", 4);
-    check(ctx, hipMemsetAsync(d_err, 0, sizeof(int), ctx->stream), "clear error flag");
+    flag_clear(ctx, d_err);
     mark(ctx, 0);
     check(ctx, launch_gradient(ctx->grad_tile, d_f, nullptr, single(g), nullptr, gradient_tiles(g, ctx->grad_tile), grad,
                                d_err, ctx->stream),
@@ -431,14 +466,71 @@ ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f
     // the hot path over the concatenation
     uint32_t* grad = buf<uint32_t>(ctx, "cx_grad", total);
     int* d_err = buf<int>(ctx, "err_flag", 4);
-    check(ctx, hipMemsetAsync(d_err, 0, sizeof(int), s), "clear error flag");
-    mark(ctx, 0);
-    check(ctx, launch_gradient(ctx->grad_tile, d_f[0], d_fptr, geo, d_toff, tiles, grad, d_err, s),
-          "gradient kernel launch");
-    mark(ctx, 1);
+    uint64_t* ctmp = buf<uint64_t>(ctx, "crit_tmp", crit_tmp_elems(geo.nv) + 1);
+    // The front (flag clear, gradient, critical counts, scan, totals) has a
+    // fixed shape for given dims: it is captured once in a graph and
+    // replayed while the dims and the buffers stay the same (the fields are
+    // read through the device table, so new fields reuse the graph).
+    auto front = [&](hipStream_t st) {
+        hipStream_t keep = ctx->stream;
+        ctx->stream = st;
+        try {
+            flag_clear(ctx, d_err);
+            check(ctx, launch_gradient(ctx->grad_tile, d_f[0], d_fptr, geo, d_toff, tiles, grad, d_err, st),
+                  "gradient kernel launch");
+            critical_front(ctx, grad, geo, ctmp, d_err);
+        } catch (...) {
+            ctx->stream = keep;
+            throw;
+        }
+        ctx->stream = keep;
+    };
+    if (ctx->batch_graph && !ctx->timing) {
+        std::vector<uint64_t> key = {nf, (uint64_t)ctx->grad_tile, (uint64_t)(uintptr_t)grad, (uint64_t)(uintptr_t)d_err,
+                                     (uint64_t)(uintptr_t)ctmp, (uint64_t)(uintptr_t)d_grids, (uint64_t)(uintptr_t)d_voff,
+                                     (uint64_t)(uintptr_t)d_toff, (uint64_t)(uintptr_t)d_fptr};
+        for (uint32_t f = 0; f < nf; f++) {
+            key.push_back(grids[f].n[0]);
+            key.push_back(grids[f].n[1]);
+            key.push_back(grids[f].n[2]);
+        }
+        if (!ctx->front_exec || key != ctx->front_key) {
+            if (ctx->front_exec) {
+                (void)hipGraphExecDestroy(ctx->front_exec);
+                ctx->front_exec = nullptr;
+            }
+            if (!ctx->capture_stream)
+                check(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking), "stream create");
+            hipGraph_t graph = nullptr;
+            check(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal), "begin capture");
+            try {
+                front(ctx->capture_stream);
+            } catch (...) {
+                (void)hipStreamEndCapture(ctx->capture_stream, &graph);
+                if (graph) (void)hipGraphDestroy(graph);
+                throw;
+            }
+            check(ctx, hipStreamEndCapture(ctx->capture_stream, &graph), "end capture");
+            hipError_t e = hipGraphInstantiate(&ctx->front_exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) ctx->front_exec = nullptr;
+            check(ctx, e, "graph instantiate");
+            ctx->front_key = key;
+            ctx->front_captures++;
+        }
+        check(ctx, hipGraphLaunch(ctx->front_exec, s), "graph launch");
+        ctx->front_replays++;
+    } else {
+        mark(ctx, 0);
+        flag_clear(ctx, d_err);
+        check(ctx, launch_gradient(ctx->grad_tile, d_f[0], d_fptr, geo, d_toff, tiles, grad, d_err, s),
+              "gradient kernel launch");
+        mark(ctx, 1);
+        critical_front(ctx, grad, geo, ctmp, d_err);
+    }
     int64_t cnt[4];
     ms_status st = MS_OK;
-    critical_impl(ctx, d_f[0], d_fptr, grad, geo, nullptr, cnt, d_err, &st);
+    critical_finish(ctx, d_f[0], d_fptr, grad, geo, nullptr, cnt, d_err, &st, ctmp);
     if (st == MS_ERR_NONFINITE) fail(ctx, st, "a field contains NaN or infinite values");
     const int64_t ncrit = cnt[0] + cnt[1] + cnt[2] + cnt[3];
     ms_crit cr;

@@ -49,6 +49,13 @@ struct ms_ctx {
     uint32_t merge_chunk = 4096; // see MS_OPT_MERGE_CHUNK
     int grad_tile = 0;           // see MS_OPT_GRADIENT_TILE
     uint32_t wave_blocks = 1024; // workgroups of a wave-path merge launch (4 per compute unit)
+    // graph of the front of ms_complex_batch, captured on a private stream
+    // and keyed by the dims and the buffers it uses (see ms_complex_batch)
+    bool batch_graph = true;
+    std::vector<uint64_t> front_key;
+    hipGraphExec_t front_exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int64_t front_captures = 0, front_replays = 0;
 };
 
 namespace msc {

@@ -12,12 +12,18 @@ slots overlaps on the device.  Inputs stay on the device: the base field is
 resident in HBM and each timestep is formed there.
 
 HBM admission.  A context keeps its workspace between calls (it only grows),
-so each slot holds about the footprint of the largest batch it has run.  The
-footprint of a batch is estimated as ``bytes_per_voxel * voxels``.  A slot
-may take a batch only if the resident estimates of the other slots plus
-max(its own, the batch's) stay within the budget.  When nothing fits, the
-workspaces of idle slots are released first; a request larger than the whole
-budget runs alone once every other slot is idle.
+and reports exactly how much device memory it holds (workspace_bytes of
+ms_ctx_get_timing); the server reads that after every batch and release.
+The need of a batch not yet run is estimated as ``bytes_per_voxel * voxels``
+with a per-voxel figure measured at the high-water mark of the densest
+inputs.  A slot may take a batch only if the other slots' real holdings plus
+max(its own real holding, the batch's estimate) stay within the budget; if
+the slot then holds more than that reservation, the per-voxel estimate is
+scaled up by the overshoot (batches hold per-field copies of their outputs,
+so they need more per voxel than single fields do).
+When nothing fits, the workspaces of idle slots are released first; a
+request larger than the whole budget runs alone once every other slot is
+idle.
 
 Latency of a request = completion time - arrival time.  A request's result
 is identical to running it alone: a batched launch is byte-identical per
@@ -33,12 +39,13 @@ from dataclasses import dataclass, field as dc_field
 
 import numpy as np
 
-# Device bytes per voxel of the library's workspace plus outputs, measured
-# at the high-water mark on noise-dominated blob fields (the densest inputs:
-# about 0.4 critical cells and 5 closure entries of the 1-saddle/2-saddle
-# DAG per vertex), rounded up.  It bounds every per-buffer size, so the
-# element-wise maximum over batches stays within it as well.
-BYTES_PER_VOXEL = 192
+# Device bytes per voxel that a context holds after a call, growth headroom
+# of its buffers included: 343 at the high-water mark of the densest inputs
+# measured (512^3 noise-dominated blobs: 0.41 critical cells and 4.6 closure
+# entries of the 1-saddle/2-saddle DAG per vertex), rounded up.  It is an
+# estimate, not a bound (the closure is data dependent); the server raises
+# it when a slot is seen to hold more.
+BYTES_PER_VOXEL = 400
 
 
 @dataclass
@@ -95,6 +102,10 @@ class GpuSlot:
     def release(self):
         self.ctx.release()
 
+    def workspace_bytes(self) -> int:
+        """Device memory the slot's context holds now (exact)."""
+        return int(self.ctx.timing()["workspace_bytes"])
+
     def start_counting(self):
         self.ctx.set_timing(True)
 
@@ -110,7 +121,7 @@ class GpuSlot:
 class Server:
     """Slots pull batches from the queue; see the module docstring."""
 
-    def __init__(self, slots, hbm_budget: int, max_batch_voxels: int = 96 << 20, max_batch: int = 64,
+    def __init__(self, slots, hbm_budget: int, max_batch_voxels: int = 192 << 20, max_batch: int = 64,
                  bytes_per_voxel: int = BYTES_PER_VOXEL, close_slots: bool = True):
         self.close_slots = close_slots
         self.hbm_budget = int(hbm_budget)
@@ -122,7 +133,12 @@ class Server:
         self._cv = threading.Condition()
         self._pending = collections.deque()
         self._busy = [False] * n
-        self._resident = [0] * n      # estimated workspace each slot holds
+        # what each slot's context reported holding (at start, after its last
+        # batch or release), and that or the reservation of its running batch
+        self._real = [int(sl.workspace_bytes()) for sl in self._slots]
+        self._resident = list(self._real)
+        self._reserved = [0] * n      # what admission reserved for each slot's running batch
+        self.estimate_raises = 0      # times a batch needed more than its reservation
         self._release = [False] * n   # asked to drop its workspace before the next batch
         self._stop = False
         self._handed = 0
@@ -130,7 +146,7 @@ class Server:
         self.batches = []             # (slot, size, voxels, start, done)
         self.admission_waits = 0      # times a free slot found nothing that fits
         self.releases = 0
-        self.max_resident = 0
+        self.max_resident = 0         # largest sum of what the slots' contexts reported holding
         self.errors = []
         self._threads = [threading.Thread(target=self._worker, args=(i,), daemon=True) for i in range(n)]
         for t in self._threads:
@@ -188,8 +204,8 @@ class Server:
             r.order = self._handed
             self._handed += 1
         self._busy[s] = True
-        self._resident[s] = max(self._resident[s], fp)
-        self.max_resident = max(self.max_resident, sum(self._resident))
+        self._resident[s] = max(self._resident[s], fp)  # reserved until the real figure is read
+        self._reserved[s] = self._resident[s]
         return batch
 
     def _worker(self, s: int):
@@ -209,7 +225,10 @@ class Server:
                     return
             if release:
                 slot.release()
+                held = slot.workspace_bytes()
                 with self._cv:
+                    self._real[s] = held
+                    self._resident[s] = held
                     self._release[s] = False
                     self._cv.notify_all()
                 continue
@@ -223,9 +242,19 @@ class Server:
                 t_done = self.now()
             for r in batch:
                 r.start, r.done, r.batch_size, r.slot = t_start, t_done, len(batch), s
+            held = slot.workspace_bytes()
+            vox = sum(r.voxels for r in batch)
             with self._cv:
                 self._busy[s] = False
-                self.batches.append((s, len(batch), sum(r.voxels for r in batch), t_start, t_done))
+                if held > self._reserved[s] > 0:
+                    # the batch needed more than admission reserved for it:
+                    # scale the per-voxel estimate by the overshoot
+                    self.bpv = -(-self.bpv * held // self._reserved[s])
+                    self.estimate_raises += 1
+                self._real[s] = held
+                self._resident[s] = held
+                self.max_resident = max(self.max_resident, sum(self._real))
+                self.batches.append((s, len(batch), vox, t_start, t_done))
                 self._cv.notify_all()
 
     def close(self):
@@ -353,7 +382,6 @@ def serve_benchmark(steps: int = 200, slots: int = 3, options: dict | None = Non
         return [Request(rid=r.rid, arrival=r.arrival, field=r.field, kind=r.kind, nvox=r.nvox) for r in reqs]
 
     torch.cuda.synchronize()
-    free0, res0 = torch.cuda.mem_get_info()[0], torch.cuda.memory_reserved()
     slot_set = [GpuSlot(options) for _ in range(slots)]
 
     def serve(time_scale):
@@ -370,9 +398,9 @@ def serve_benchmark(steps: int = 200, slots: int = 3, options: dict | None = Non
     try:
         _, warm = serve(0.0)  # warm the slots' workspaces on the whole stream
         torch.cuda.synchronize()
-        # device memory the contexts hold (torch's own pool excluded) against
+        # device memory the contexts hold (their own exact figures) against
         # the largest batch each slot ran
-        lib_bytes = (free0 - torch.cuda.mem_get_info()[0]) - (torch.cuda.memory_reserved() - res0)
+        lib_bytes = sum(sl.workspace_bytes() for sl in slot_set)
         slot_vox = [max([b[2] for b in warm.batches if b[0] == i] or [0]) for i in range(slots)]
         rt, srv = serve(1.0)
         log(f"serve realtime: {json.dumps(rt)}")
@@ -386,6 +414,8 @@ def serve_benchmark(steps: int = 200, slots: int = 3, options: dict | None = Non
     out = {
         "workload": f"advected grf {nx}x{ny}x{nz}, {steps} steps at 10 Hz + Poisson 20/s sides 64..256",
         "slots": slots, "hbm_budget_gb": round(budget / 1e9, 1), "bytes_per_voxel": BYTES_PER_VOXEL,
+        "bytes_per_voxel_learned": max(srv.bpv, srv2.bpv), "max_resident_gb": round(max(srv.max_resident,
+                                                                                       srv2.max_resident) / 1e9, 2),
         "workspace_gb": round(lib_bytes / 1e9, 2),
         "measured_bytes_per_voxel": round(lib_bytes / max(sum(slot_vox), 1), 1),
         "realtime": rt, "all_at_once": cap,

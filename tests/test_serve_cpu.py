@@ -54,6 +54,10 @@ class FakeSlot:
             with self.ledger.lock:
                 self.ledger.running -= 1
 
+    def workspace_bytes(self):
+        with self.ledger.lock:
+            return self.ws
+
     def release(self):
         with self.ledger.lock:
             self.ws = 0

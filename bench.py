@@ -89,6 +89,28 @@ def measured_traffic(kernel, source):
         return None
 
 
+def valu_profile(kernel, source):
+    """VALU counters of `kernel` from its committed summary
+    (profiles/<kernel>_blobs512_valu.txt), or None when the kernel's source
+    has changed since they were taken."""
+    import hashlib
+    try:
+        lines = open(os.path.join(PROFILES, f"{kernel}_blobs512_valu.txt")).read().splitlines()
+    except OSError:
+        return None
+    kv = dict((a.strip(), b.strip()) for a, b in (l.split(":", 1) for l in lines if ":" in l and not l.startswith("#")))
+    src = hashlib.sha256(open(os.path.join(CSRC, source), "rb").read()).hexdigest()
+    if kv.get("source_sha256") != src:
+        return None
+    return {k: float(v) for k, v in kv.items() if k not in ("kernel", "source", "source_sha256")}
+
+
+# MI355X vector ALU: 256 compute units at 2.4 GHz, each issuing one wave64
+# VALU instruction per cycle across its four SIMDs (a SIMD takes four cycles
+# for a wave64 instruction on 16 lanes) = 64 lane-operations per CU-cycle.
+VALU_PEAK_LANE_OPS = 256 * 2.4e9 * 64
+
+
 def roofline(kernel, source, bytes_per_launch, avg_launch_ms):
     achieved = bytes_per_launch / (avg_launch_ms / 1e3) / 1e9
     return {"kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -265,6 +287,27 @@ def main():
     grad_ms = tm["gradient_ms"] / calls
     grad_bytes = 8 * n  # 4 B field read + 4 B gradient word written per vertex
     grad_roof = roofline("grad_lowerstar", "gradient.hip", grad_bytes, grad_ms)
+    vp = valu_profile("grad_lowerstar", "gradient.hip")
+    if vp:
+        # the gradient is bound by the vector ALU: active lane-operations
+        # (VALU instructions x the lanes each had active, from the counters)
+        # per second against the VALU peak; issue_frac counts every
+        # instruction as 64 lanes (the issue slots the kernel used)
+        lane_ops = vp["thread_cycles_valu_per_launch"]
+        issued = vp["valu_insts_per_launch"] * 64
+        grad_roof.update({"bound": "alu", "hbm_gbs": grad_roof["achieved"], "hbm_frac": grad_roof["frac"],
+                          "achieved": round(lane_ops / (grad_ms / 1e3) / 1e12, 2),
+                          "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2), "unit": "T lane-ops/s",
+                          "frac": round(lane_ops / (grad_ms / 1e3) / VALU_PEAK_LANE_OPS, 4),
+                          "issue_frac": round(issued / (grad_ms / 1e3) / VALU_PEAK_LANE_OPS, 4),
+                          "lane_ops_per_launch": int(lane_ops), "valu_insts_per_launch": int(vp["valu_insts_per_launch"])})
+    # critical-cell stage: every gradient word read once, 13 B written per
+    # critical cell (id, index, value, highest vertex)
+    crit_ms = tm["critical_ms"] / calls
+    ncrit = int(sum(r.count))
+    crit_roof = roofline("crit_count+crit_scatter", "critical.hip", 4 * n + 13 * ncrit, crit_ms)
+    crit_roof["traffic"] = None
+    crit_roof["note"] = "whole critical stage (both passes, scan, count readback), per call"
     if tm["rank_launches"] > 0:
         # path-count ranking: per input entry 4 B row + 8 B count read and a
         # 1 B head flag written; per run head 4 B row + 8 B sum written
@@ -272,12 +315,14 @@ def main():
         main_roof = roofline("k_entry_rank", "paths.hip", rank_bytes / tm["rank_launches"],
                              tm["rank_ms"] / tm["rank_launches"])
         main_roof["launches_per_step"] = tm["rank_launches"] // calls
+        main_roof["entries_per_step"] = tm["rank_entries"] // calls
+        main_roof["heads_per_step"] = tm["rank_heads"] // calls
     else:
         main_roof = grad_roof
     stages = {k.replace("_ms", ""): round(v / calls, 3) for k, v in tm.items() if k.endswith("_ms") and k != "rank_ms"}
     ctx.set_timing(False)
     copy_gbs = copy_bandwidth(torch)
-    for roof in (main_roof, grad_roof):
+    for roof in (main_roof, crit_roof):
         roof["copy_gbs"] = round(copy_gbs, 1)
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
     log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
@@ -293,12 +338,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u32",
+        "dtype": "u32/u64",
         "data": "synthetic",
         "config": {"workload": desc, "method": "plain (one field per call)", "voxels": n,
                    "critical_counts": counts},
         "roofline": main_roof,
         "roofline_gradient": grad_roof,
+        "roofline_critical": crit_roof,
         "stages_ms": stages,
         "stats": stats,
         "launch_params": tuned,

@@ -21,6 +21,12 @@ for the run's first plain copy dispatch of B bytes (bench.py
 is hashed so that a later change of the kernel invalidates the figure.
 
     python -m paper_2009_03707_amd.prof_summary traffic FETCH.csv WRITE.csv KERNEL SOURCE B
+
+VALU counters of one kernel per launch (SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU,
+SQ_THREAD_CYCLES_VALU, SQ_BUSY_CU_CYCLES, GRBM_GUI_ACTIVE in one --pmc run),
+with the kernel's source hash:
+
+    python -m paper_2009_03707_amd.prof_summary valu COUNTERS.csv KERNEL SOURCE
 """
 import collections
 import csv
@@ -94,7 +100,48 @@ def traffic(fetch_csv, write_csv, kernel, source, copy_bytes):
     print(f"traffic_bytes_per_launch: {int(f_b + w_b)}")
 
 
+def valu(csv_path, kernel, source, cus=256):
+    """VALU counters of one kernel per launch, from a --pmc run with
+    SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU, SQ_THREAD_CYCLES_VALU,
+    SQ_BUSY_CU_CYCLES and GRBM_GUI_ACTIVE (each summed over the shader
+    engines / dies by rocprofv3)."""
+    import hashlib
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = hashlib.sha256(open(os.path.join(here, "csrc", source), "rb").read()).hexdigest()
+    acc = collections.defaultdict(float)
+    disp = set()
+    with open(csv_path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            if not short(row["Kernel_Name"]).startswith(kernel):
+                continue
+            disp.add(row["Dispatch_Id"])
+            acc[row["Counter_Name"]] += float(row["Counter_Value"])
+    n = max(len(disp), 1)
+    per = {k: v / n for k, v in acc.items()}
+    print(f"# {kernel}: VALU counters per launch (rocprofv3 --pmc, summed over shader engines and dies)")
+    print("# valu_busy_pct follows rocprofv3's VALUBusy: 100 * SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE, with"
+          " GRBM_GUI_ACTIVE taken per die (summed value / 8)")
+    print(f"kernel: {kernel}")
+    print(f"source: {source}")
+    print(f"source_sha256: {src}")
+    print(f"launches: {len(disp)}")
+    print(f"valu_insts_per_launch: {per.get('SQ_INSTS_VALU', 0):.0f}")
+    print(f"active_inst_valu_per_launch: {per.get('SQ_ACTIVE_INST_VALU', 0):.0f}")
+    print(f"thread_cycles_valu_per_launch: {per.get('SQ_THREAD_CYCLES_VALU', 0):.0f}")
+    print(f"busy_cu_cycles_per_launch: {per.get('SQ_BUSY_CU_CYCLES', 0):.0f}")
+    print(f"gui_active_per_launch: {per.get('GRBM_GUI_ACTIVE', 0):.0f}")
+    gui = per.get("GRBM_GUI_ACTIVE", 0) / 8.0
+    if gui > 0:
+        print(f"valu_busy_pct: {100.0 * per.get('SQ_ACTIVE_INST_VALU', 0) / cus / gui:.2f}")
+    if per.get("SQ_ACTIVE_INST_VALU", 0) > 0:
+        print(f"lanes_per_valu_inst: {per.get('SQ_THREAD_CYCLES_VALU', 0) / per['SQ_ACTIVE_INST_VALU']:.2f}")
+
+
 def main():
+    if sys.argv[1] == "valu":
+        valu(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
     if sys.argv[1] == "traffic":
         traffic(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5], int(sys.argv[6]))
         return

@@ -306,7 +306,8 @@ def main():
     crit_ms = tm["critical_ms"] / calls
     ncrit = int(sum(r.count))
     crit_roof = roofline("crit_count+crit_scatter", "critical.hip", 4 * n + 13 * ncrit, crit_ms)
-    crit_roof["traffic"] = None
+    tc, ts = measured_traffic("crit_count", "critical.hip"), measured_traffic("crit_scatter", "critical.hip")
+    crit_roof["traffic"] = tc + ts if tc is not None and ts is not None else None
     crit_roof["note"] = "whole critical stage (both passes, scan, count readback), per call"
     if tm["rank_launches"] > 0:
         # path-count ranking: per input entry 4 B row + 8 B count read and a
@@ -356,6 +357,7 @@ def main():
     torch.cuda.empty_cache()
     if args.batch > 0:
         out["batched"] = batch_bench(args, torch, msc)
+        torch.cuda.empty_cache()  # the batch's workspace goes back to the device before serving
     if args.serve_steps > 0:
         from paper_2009_03707_amd import serve
         out["served"] = serve.serve_benchmark(steps=args.serve_steps, slots=args.serve_slots, options=tuned,

@@ -409,6 +409,7 @@ def serve_benchmark(steps: int = 200, slots: int = 3, options: dict | None = Non
     finally:
         for sl in slot_set:
             sl.close()
+    torch.cuda.empty_cache()  # the plain path starts from the same free memory as the slots did
     plain_s = run_plain(fresh(), produce=produce, options=options)
     vox = sum(r.voxels for r in reqs)
     out = {

@@ -7,15 +7,19 @@
 // whose highest vertex is x are paired among themselves by two priority
 // queues ordered by the cells' vertex values.
 //
-// MI355X design: one workgroup computes the gradient words of an
-// OX x OY x OZ block of vertices.  The field tile (with a one-vertex halo on
-// each side plus one extra vertex on the high side) is staged in LDS as
-// order-preserving integer keys; every vertex of the block and of its
-// high-side halo runs the lower-star pairing in registers with bitmask
-// queues, the vertices taken in order of lower-star size so that the lanes
-// of a wave do similar work; each lower star's nibbles are OR-ed into an LDS
-// word tile (each nibble is written by exactly one lower star), which is
-// then stored coalesced.
+// MI355X design: one workgroup runs the lower stars of an OX x OY x OZ
+// block of vertices.  The field tile (with a one-vertex halo on each side)
+// is staged in LDS as order-preserving integer keys; every vertex of the
+// block runs the lower-star pairing in registers with bitmask queues, the
+// vertices taken in order of lower-star size so that the lanes of a wave do
+// similar work; each lower star's nibbles are OR-ed into an LDS word tile
+// (each nibble is written by exactly one lower star).  A word receives the
+// nibbles of the lower stars of its vertex and of its +x / +y / +z
+// neighbours, so the words of the block's interior get all of theirs from
+// the block and are stored plainly, while the words on the block's high
+// faces and the low-side halo words get nibbles from several blocks and are
+// OR-ed atomically into the gradient, which is cleared first.  Every lower
+// star is thus computed once.
 #include "common.h"
 
 namespace msc {
@@ -25,12 +29,12 @@ namespace {
 // autotuner picks one per size class.  Results do not depend on the shape.
 template <int X, int Y, int Z>
 struct Tile {
-    static constexpr int OX = X, OY = Y, OZ = Z;            // output words per block
-    static constexpr int FX = X + 3, FY = Y + 3, FZ = Z + 3;  // staged field tile
+    static constexpr int OX = X, OY = Y, OZ = Z;            // vertices (lower stars) per block
+    static constexpr int FX = X + 2, FY = Y + 2, FZ = Z + 2;  // staged field tile
     static constexpr int NF = FX * FY * FZ;
-    static constexpr int NW = X * Y * Z;
-    static constexpr int PX = X + 1, PY = Y + 1, PZ = Z + 1;  // lower stars computed
-    static constexpr int NPLS = PX * PY * PZ;
+    static constexpr int NV = X * Y * Z;
+    static constexpr int WX = X + 1, WY = Y + 1, WZ = Z + 1;  // word tile: the block plus its low-side halo
+    static constexpr int NW = WX * WY * WZ;
 };
 constexpr int THREADS = 256;
 constexpr uint32_t NXCD = 8;  // accelerator complex dies of an MI355X
@@ -142,9 +146,9 @@ struct Star {
         });
         Unroll<8>::run([&](auto cc) {
             constexpr int c = decltype(cc)::value;
-            const int wx = lx - (c & 1), wy = ly - ((c >> 1) & 1), wz = lz - ((c >> 2) & 1);
-            if (w[c] && (unsigned)wx < (unsigned)OX && (unsigned)wy < (unsigned)OY && (unsigned)wz < (unsigned)OZ)
-                atomicOr(&words[wx + OX * (wy + OY * wz)], w[c]);
+            // word (lx - a, ly - b, lz - c) of the tile, which starts one word below the block
+            const int wx = lx + 1 - (c & 1), wy = ly + 1 - ((c >> 1) & 1), wz = lz + 1 - ((c >> 2) & 1);
+            if (w[c]) atomicOr(&words[wx + (OX + 1) * (wy + (OY + 1) * wz)], w[c]);
         });
     }
 };
@@ -394,12 +398,12 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
                                                            uint32_t total_tiles, uint32_t* __restrict__ grad_all,
                                                            int* __restrict__ err) {
     constexpr int OX = T::OX, OY = T::OY, OZ = T::OZ, FX = T::FX, FY = T::FY, NF = T::NF, NW = T::NW;
-    constexpr int PX = T::PX, PY = T::PY, NPLS = T::NPLS;
+    constexpr int WX = T::WX, WY = T::WY, NV = T::NV;
     __shared__ uint32_t fk[NF];
     __shared__ uint32_t words[NW];
     __shared__ Tables tab;
-    __shared__ uint8_t s_size[NPLS];
-    __shared__ uint16_t s_ord[NPLS];
+    __shared__ uint8_t s_size[NV];
+    __shared__ uint16_t s_ord[NV];
     __shared__ uint32_t s_cnt[32];
     const int tid = threadIdx.x;
     // Workgroups are dealt to the 8 XCDs round-robin; block b takes tile
@@ -454,8 +458,8 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
     // Nibbles are OR-ed into the word tile, so the order does not matter.
     if (tid < 32) s_cnt[tid] = 0;
     __syncthreads();
-    for (int i = tid; i < NPLS; i += THREADS) {
-        int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
+    for (int i = tid; i < NV; i += THREADS) {
+        int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
         int x = x0 + lx, y = y0 + ly, z = z0 + lz;
         uint32_t sz = 0;  // vertices outside the grid: size 0, skipped below
         if (x < nx && y < ny && z < nz) sz = lower_star_size<T>(fk, (lx + 1) + FX * ((ly + 1) + FY * (lz + 1)));
@@ -472,12 +476,12 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
         }
     }
     __syncthreads();
-    for (int i = tid; i < NPLS; i += THREADS) s_ord[atomicAdd(&s_cnt[s_size[i]], 1u)] = (uint16_t)i;
+    for (int i = tid; i < NV; i += THREADS) s_ord[atomicAdd(&s_cnt[s_size[i]], 1u)] = (uint16_t)i;
     __syncthreads();
-    for (int k = tid; k < NPLS; k += THREADS) {
+    for (int k = tid; k < NV; k += THREADS) {
         const int i = s_ord[k];
         if (s_size[i] == 0) continue;
-        int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
+        int lx = i % OX, ly = (i / OX) % OY, lz = i / (OX * OY);
         Star<T> st{lx, ly, lz, words, &tab};
         int fidx = (lx + 1) + FX * ((ly + 1) + FY * (lz + 1));
         lower_star(fk, fidx, st);
@@ -485,14 +489,33 @@ __global__ __launch_bounds__(THREADS) void grad_lowerstar(const float* __restric
     __syncthreads();
 
     for (int i = tid; i < NW; i += THREADS) {
-        int wx = i % OX, wy = (i / OX) % OY, wz = i / (OX * OY);
-        int x = x0 + wx, y = y0 + wy, z = z0 + wz;
-        if (x >= nx || y >= ny || z >= nz) continue;
+        // tile word (wx, wy, wz) is word (x0 - 1 + wx, ...) of the grid
+        int wx = i % WX, wy = (i / WX) % WY, wz = i / (WX * WY);
+        int x = x0 - 1 + wx, y = y0 - 1 + wy, z = z0 - 1 + wz;
+        if (x < 0 || y < 0 || z < 0 || x >= nx || y >= ny || z >= nz) continue;
         uint32_t w = words[i];
         if (x == nx - 1) w |= 0x70707070u;  // cells with an odd X beyond the grid
         if (y == ny - 1) w |= 0x77007700u;
         if (z == nz - 1) w |= 0x77770000u;
-        grad[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * (size_t)z)] = w;
+        uint32_t* dst = &grad[(size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * (size_t)z)];
+        // a word of the block's interior (its vertex and +x/+y/+z neighbours
+        // all in the block) has all its nibbles here; any other word also
+        // gets nibbles from a neighbouring block
+        const bool whole = wx >= 1 && wx < OX && wy >= 1 && wy < OY && wz >= 1 && wz < OZ;
+        if (whole) *dst = w;
+        else if (w) atomicOr(dst, w);
+    }
+}
+
+// Clears the gradient words (four per thread; 16-byte stores when aligned).
+__global__ __launch_bounds__(THREADS) void k_zero_words(uint32_t* __restrict__ grad, uint64_t nv) {
+    const uint64_t q = (uint64_t)blockIdx.x * THREADS + threadIdx.x;
+    const uint64_t i = 4 * q;
+    if (i >= nv) return;
+    if (i + 4 <= nv && ((uintptr_t)(grad + i) & 15u) == 0) {
+        *reinterpret_cast<uint4*>(grad + i) = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        for (uint64_t j = i; j < nv && j < i + 4; j++) grad[j] = 0u;
     }
 }
 
@@ -529,6 +552,11 @@ uint32_t gradient_tiles(const Grid& g, int shape) {
 hipError_t launch_gradient(int shape, const float* f0, const float* const* fptr, const Geo& geo,
                            const uint32_t* tile_off, uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s) {
     if (total_tiles == 0) return hipSuccess;
+    // words on block faces are OR-ed together from several blocks
+    hipLaunchKernelGGL(k_zero_words, dim3(grid_blocks((geo.nv + 3) / 4, THREADS)), dim3(THREADS), 0, s, grad,
+                       (uint64_t)geo.nv);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const uint32_t tt = (uint32_t)total_tiles;
     dim3 gd((unsigned)(NXCD * ((tt + NXCD - 1) / NXCD))), bd(THREADS);
     switch (shape) {

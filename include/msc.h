@@ -188,6 +188,36 @@ ms_status ms_critical(ms_ctx* ctx, const float* d_f, const uint32_t* d_grad, ms_
 ms_status ms_critical_noalloc(ms_ctx* ctx, const float* d_f, const uint32_t* d_grad, ms_dims dims,
                               const ms_crit* out, int64_t h_count[4]);
 
+/* Critical-cell list with 64-bit ids, structure of arrays in HOST memory,
+ * caller-owned (the out-of-core entry point below). */
+typedef struct {
+    uint64_t* id;      /* cell ids 8 * v + nibble, v = x + nx*(y + ny*z) in 64 bits */
+    uint8_t* index;    /* index = dimension, 0..3 */
+    float* value;      /* f at the cell's highest vertex (bit copy) */
+    uint64_t* vmax;    /* id of the cell's highest vertex */
+    int64_t capacity;  /* entries available in each array */
+} ms_crit64;
+
+/* Out-of-core gradient and critical cells of a field held in HOST memory,
+ * of any size up to 2^40 vertices (nx*ny <= 2^29), streamed through the GPU
+ * in z-slabs of `slab` rows (clamped so that a slab plus halo is at most
+ * 2^29 vertices).  The paper names device memory as its method's limit
+ * (Section 5.2) and cites parcels computed separately (Section 1.1); the
+ * gradient needs no stitching, as a lower star depends only on its 26
+ * neighbours: each slab is computed with one halo row below and two above,
+ * and its rows are exact.  The results equal ms_gradient / ms_critical on
+ * the whole field (ids widened to 64 bits).  Host-to-device copies of the
+ * next slab overlap the current slab's kernels.
+ *   h_f     : host, nx*ny*nz float32 (layout as everywhere).
+ *   h_grad  : host, nx*ny*nz uint32 gradient words, or NULL (not written).
+ *   out     : host arrays sorted by (index, id), or NULL (counts only).
+ *   h_count : host, critical cells per index.
+ * Errors: MS_ERR_INVALID_ARG, MS_ERR_TOO_LARGE, MS_ERR_NONFINITE,
+ * MS_ERR_CAPACITY (counts written, outputs untouched), MS_ERR_OOM.
+ * Synchronises the context's stream. */
+ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab,
+                                       uint32_t* h_grad, const ms_crit64* out, int64_t h_count[4]);
+
 /* A CSR matrix in device memory, context-owned. */
 typedef struct {
     int64_t nrows, ncols, nnz;

@@ -1,0 +1,237 @@
+// Out-of-core gradient and critical cells: a field held in host memory, of
+// any size, streamed through the GPU in z-slabs.
+//
+// The paper names device memory as the limit of its method (Section 5.2,
+// memory usage) and cites the computation of parcels that are stitched
+// afterwards (Section 1.1).  The gradient and the critical cells need no
+// stitching: the pairing of a lower star depends only on the vertex's 26
+// neighbours, and a gradient word holds the cells whose lowest corner is its
+// vertex, whose lower stars are those of the word's vertex and of its +x /
+// +y / +z neighbours.  So the words of rows [z0, z1) are exact when the
+// gradient kernel runs on rows [z0 - 1, z1 + 2) as a grid of its own (the
+// lower stars of rows [z0, z1 + 1) see all their neighbours there); rows
+// outside [z0, z1) are computed and discarded.  The critical cells of those
+// rows are then extracted from the exact words alone, with 64-bit cell ids
+// (8 * vertex + nibble, vertex = x + nx (y + ny z)) so the field may exceed
+// the 2^29 vertices of the in-HBM entry points.
+//
+// Pipelining: two device field buffers and two pinned staging buffers; the
+// slab after the current one is copied into staging on the host and sent on
+// a copy stream while the current slab is computed on the context's stream.
+#include <string.h>
+
+#include <vector>
+
+#include "ctx.h"
+#include "prims.h"
+
+namespace msc {
+uint32_t gradient_tiles(const Grid& g, int shape);
+hipError_t launch_gradient(int shape, const float* f0, const float* const* fptr, const Geo& geo,
+                           const uint32_t* tile_off, uint64_t total_tiles, uint32_t* grad, int* err, hipStream_t s);
+size_t crit_tmp_elems(uint64_t nv);
+hipError_t launch_crit_count(const uint32_t* grad, const Geo& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s);
+hipError_t launch_crit_scatter(const float* f0, const float* const* fptr, const uint32_t* grad, const Geo& g,
+                               const uint64_t* tmp, uint32_t* id, uint8_t* index, float* value, uint32_t* vmax,
+                               hipStream_t s);
+Geo single(const Grid& g);
+void flag_clear(ms_ctx* c, int* d_err);
+
+namespace {
+
+struct Pinned {
+    void* p = nullptr;
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+struct Ev {
+    hipEvent_t e = nullptr;
+    ~Ev() {
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+
+struct Stream {
+    hipStream_t s = nullptr;
+    ~Stream() {
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
+}  // namespace
+}  // namespace msc
+
+using namespace msc;
+
+extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab,
+                                                  uint32_t* h_grad, const ms_crit64* out, int64_t h_count[4]) {
+    if (!ctx) return MS_ERR_INVALID_ARG;
+    try {
+        if (!h_f || !h_count) fail(ctx, MS_ERR_INVALID_ARG, "null field or count pointer");
+        if (dims.nx < 1 || dims.ny < 1 || dims.nz < 1 || slab < 1) fail(ctx, MS_ERR_INVALID_ARG, "dims and slab must be >= 1");
+        const int64_t nx = dims.nx, ny = dims.ny, nz = dims.nz;
+        if (nx > (1 << 29) || ny > (1 << 29) || nx * ny > ((int64_t)1 << 29))
+            fail(ctx, MS_ERR_TOO_LARGE, "nx*ny must not exceed 2^29");
+        if (nz > ((int64_t)1 << 40) / (nx * ny)) fail(ctx, MS_ERR_TOO_LARGE, "field larger than 2^40 vertices");
+        const int64_t nxy = nx * ny;
+        if (slab > nz) slab = nz;
+        // a slab plus its halo (one row below, two above) must be one in-HBM grid
+        const int64_t max_rows = ((int64_t)1 << 29) / nxy;
+        if (max_rows < 4) fail(ctx, MS_ERR_TOO_LARGE, "an xy plane is too large for slabs of one row plus halo");
+        if (slab + 3 > max_rows) slab = max_rows - 3;
+        const int64_t rows_cap = slab + 3;
+        const size_t fbytes = (size_t)(rows_cap * nxy) * sizeof(float);
+
+        hipStream_t cs = ctx->stream;
+        Stream xs;
+        check(ctx, hipStreamCreateWithFlags(&xs.s, hipStreamNonBlocking), "stream create");
+        Pinned stage[2];
+        Ev ev_h2d[2], ev_done[2];
+        for (int b = 0; b < 2; b++) {
+            if (hipHostMalloc(&stage[b].p, fbytes, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                fail(ctx, MS_ERR_OOM, "pinned staging allocation failed");
+            }
+            check(ctx, hipEventCreateWithFlags(&ev_h2d[b].e, hipEventDisableTiming), "event create");
+            check(ctx, hipEventCreateWithFlags(&ev_done[b].e, hipEventDisableTiming), "event create");
+        }
+        float* d_f[2] = {buf<float>(ctx, "ooc.f0", (size_t)(rows_cap * nxy)),
+                         buf<float>(ctx, "ooc.f1", (size_t)(rows_cap * nxy))};
+        uint32_t* d_grad = buf<uint32_t>(ctx, "ooc.grad", (size_t)(rows_cap * nxy));
+        uint64_t* tmp = buf<uint64_t>(ctx, "ooc.tmp", crit_tmp_elems((uint64_t)(slab * nxy)) + 1);
+        int* d_err = buf<int>(ctx, "ooc.err", 4);
+
+        std::vector<uint64_t> rid[4], rvmax[4];
+        std::vector<float> rval[4];
+        std::vector<uint32_t> hid, hvm;
+        std::vector<uint8_t> hix;
+        std::vector<float> hval;
+
+        const int64_t nslab = (nz + slab - 1) / slab;
+        auto rows_of = [&](int64_t i, int64_t& z0, int64_t& z1, int64_t& zs, int64_t& ze) {
+            z0 = i * slab;
+            z1 = z0 + slab < nz ? z0 + slab : nz;
+            zs = z0 > 0 ? z0 - 1 : 0;
+            ze = z1 + 2 < nz ? z1 + 2 : nz;
+        };
+        // host copy into staging, then H2D on the copy stream once the
+        // device buffer's previous slab is done
+        auto send = [&](int64_t i) {
+            int64_t z0, z1, zs, ze;
+            rows_of(i, z0, z1, zs, ze);
+            const int b = (int)(i & 1);
+            check(ctx, hipEventSynchronize(ev_h2d[b].e), "event synchronize");  // staging b free
+            const size_t bytes = (size_t)((ze - zs) * nxy) * sizeof(float);
+            memcpy(stage[b].p, h_f + zs * nxy, bytes);
+            check(ctx, hipStreamWaitEvent(xs.s, ev_done[b].e, 0), "stream wait");
+            check(ctx, hipMemcpyAsync(d_f[b], stage[b].p, bytes, hipMemcpyHostToDevice, xs.s), "copy to device");
+            check(ctx, hipEventRecord(ev_h2d[b].e, xs.s), "event record");
+        };
+        for (int b = 0; b < 2; b++) {  // events start signalled
+            check(ctx, hipEventRecord(ev_h2d[b].e, xs.s), "event record");
+            check(ctx, hipEventRecord(ev_done[b].e, cs), "event record");
+        }
+        send(0);
+        bool nonfinite = false;
+        for (int64_t i = 0; i < nslab; i++) {
+            int64_t z0, z1, zs, ze;
+            rows_of(i, z0, z1, zs, ze);
+            const int b = (int)(i & 1);
+            check(ctx, hipStreamWaitEvent(cs, ev_h2d[b].e, 0), "stream wait");
+            const Grid gs = Grid::make(nx, ny, ze - zs);
+            flag_clear(ctx, d_err);
+            check(ctx, launch_gradient(ctx->grad_tile, d_f[b], nullptr, single(gs), nullptr,
+                                       gradient_tiles(gs, ctx->grad_tile), d_grad, d_err, cs),
+                  "gradient kernel launch");
+            if (i + 1 < nslab) send(i + 1);
+            // the exact rows [z0, z1) as a grid of their own
+            const int64_t off = (z0 - zs) * nxy;
+            const Grid gi = Grid::make(nx, ny, z1 - z0);
+            uint64_t* d_tot = nullptr;
+            check(ctx, launch_crit_count(d_grad + off, single(gi), tmp, &d_tot, cs), "critical count launch");
+            check(ctx, hipMemcpyAsync(ctx->h_small, d_tot, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, cs), "readback");
+            check(ctx, hipMemcpyAsync(ctx->h_small + 8, d_err, sizeof(int), hipMemcpyDeviceToHost, cs), "readback");
+            check(ctx, hipStreamSynchronize(cs), "stream synchronize");
+            int flag = 0;
+            memcpy(&flag, ctx->h_small + 8, sizeof(int));
+            if (flag) {
+                nonfinite = true;
+                check(ctx, hipEventRecord(ev_done[b].e, cs), "event record");
+                break;
+            }
+            int64_t cnt[4], n = 0;
+            for (int k = 0; k < 4; k++) {
+                cnt[k] = (int64_t)ctx->h_small[k];
+                n += cnt[k];
+            }
+            // the slab's records (grow-only buffers, sized by this slab's count)
+            uint32_t* d_id = buf<uint32_t>(ctx, "ooc.id", (size_t)n);
+            uint8_t* d_index = buf<uint8_t>(ctx, "ooc.index", (size_t)n);
+            float* d_value = buf<float>(ctx, "ooc.value", (size_t)n);
+            uint32_t* d_vmax = buf<uint32_t>(ctx, "ooc.vmax", (size_t)n);
+            if (n > 0)
+                check(ctx, launch_crit_scatter(d_f[b] + off, nullptr, d_grad + off, single(gi), tmp, d_id, d_index,
+                                               d_value, d_vmax, cs),
+                      "critical scatter launch");
+            check(ctx, hipEventRecord(ev_done[b].e, cs), "event record");  // d_f[b] may be refilled
+            if (h_grad)
+                check(ctx, hipMemcpyAsync(h_grad + z0 * nxy, d_grad + off, (size_t)((z1 - z0) * nxy) * sizeof(uint32_t),
+                                          hipMemcpyDeviceToHost, cs),
+                      "copy to host");
+            hid.resize((size_t)n);
+            hvm.resize((size_t)n);
+            hval.resize((size_t)n);
+            if (n > 0) {
+                check(ctx, hipMemcpyAsync(hid.data(), d_id, 4 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
+                check(ctx, hipMemcpyAsync(hvm.data(), d_vmax, 4 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
+                check(ctx, hipMemcpyAsync(hval.data(), d_value, 4 * (size_t)n, hipMemcpyDeviceToHost, cs),
+                      "copy to host");
+            }
+            check(ctx, hipStreamSynchronize(cs), "stream synchronize");
+            // slab-local ids and vertices -> global ones; the slab's list is
+            // sorted by (index, id) and slabs come in id order, so appending
+            // per index keeps the global order
+            const uint64_t vbase = (uint64_t)z0 * (uint64_t)nxy;
+            int64_t p = 0;
+            for (int k = 0; k < 4; k++) {
+                for (int64_t j = 0; j < cnt[k]; j++, p++) {
+                    rid[k].push_back(8 * vbase + hid[(size_t)p]);
+                    rvmax[k].push_back(vbase + hvm[(size_t)p]);
+                    rval[k].push_back(hval[(size_t)p]);
+                }
+            }
+        }
+        check(ctx, hipStreamSynchronize(xs.s), "stream synchronize");
+        if (nonfinite) fail(ctx, MS_ERR_NONFINITE, "the field contains NaN or infinite values");
+        int64_t total = 0;
+        for (int k = 0; k < 4; k++) {
+            h_count[k] = (int64_t)rid[k].size();
+            total += h_count[k];
+        }
+        if (!out) return MS_OK;
+        if (total > out->capacity) fail(ctx, MS_ERR_CAPACITY, "critical output capacity too small");
+        if (total > 0 && (!out->id || !out->index || !out->value || !out->vmax))
+            fail(ctx, MS_ERR_INVALID_ARG, "null critical output array");
+        int64_t p = 0;
+        for (int k = 0; k < 4; k++) {
+            const size_t m = rid[k].size();
+            if (m == 0) continue;
+            memcpy(out->id + p, rid[k].data(), 8 * m);
+            memcpy(out->vmax + p, rvmax[k].data(), 8 * m);
+            memcpy(out->value + p, rval[k].data(), 4 * m);
+            memset(out->index + p, k, m);
+            p += (int64_t)m;
+        }
+    } catch (const Fail& e) {
+        return e.st;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host allocation failed";
+        return MS_ERR_OOM;
+    } catch (const std::exception& e) {
+        ctx->err = std::string("internal error: ") + e.what();
+        return MS_ERR_INTERNAL;
+    }
+    return MS_OK;
+}

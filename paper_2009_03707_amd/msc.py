@@ -24,7 +24,7 @@ EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_err
             "ms_ctx_set_option", "ms_complex_batch", "ms_ctx_release", "ms_critical_noalloc",
             "ms_graph_build", "ms_graph_build_host", "ms_graph_destroy", "ms_graph_num_nodes", "ms_graph_last_error",
             "ms_graph_node", "ms_graph_find", "ms_graph_arcs", "ms_graph_counts", "ms_graph_simplify",
-            "ms_graph_num_cancellations", "ms_graph_cancellations"]
+            "ms_graph_num_cancellations", "ms_graph_cancellations", "ms_gradient_critical_chunked"]
 MS_DOWN, MS_UP = 0, 1
 MS_SIMPLIFY_SERIAL, MS_SIMPLIFY_SUBGRID = 0, 1
 
@@ -50,6 +50,11 @@ class Crit(C.Structure):
 class Csr(C.Structure):
     _fields_ = [("nrows", C.c_int64), ("ncols", C.c_int64), ("nnz", C.c_int64),
                 ("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p)]
+
+
+class Crit64(C.Structure):
+    _fields_ = [("id", C.c_void_p), ("index", C.c_void_p), ("value", C.c_void_p), ("vmax", C.c_void_p),
+                ("capacity", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -138,6 +143,7 @@ def lib():
         L.ms_ctx_set_option.argtypes = [vp, C.c_int, C.c_int64]
         L.ms_complex_batch.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(Dims), C.POINTER(Result)]
         L.ms_ctx_release.argtypes = [vp]
+        L.ms_gradient_critical_chunked.argtypes = [vp, vp, Dims, i64, vp, C.POINTER(Crit64), C.POINTER(i64)]
         L.ms_graph_build.argtypes = [vp, C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
         L.ms_graph_build_host.argtypes = [C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
         L.ms_graph_destroy.argtypes = [vp]
@@ -296,6 +302,28 @@ class Context:
                                        cr, cnt)
         self._raise(st, "ms_critical_noalloc")
         return list(cnt)
+
+    def gradient_critical_chunked(self, f, slab: int, want_grad: bool = True):
+        """ms_gradient_critical_chunked on a host numpy float32 field (nz, ny,
+        nx): returns (grad uint32 (nz, ny, nx) or None, id uint64[], index
+        uint8[], value float32[], vmax uint64[], counts)."""
+        import numpy as np
+        f = np.ascontiguousarray(f, dtype=np.float32)
+        nz, ny, nx = f.shape
+        self._sync_stream()
+        cnt = (C.c_int64 * 4)()
+        grad = np.empty(f.shape, np.uint32) if want_grad else None
+        gp = grad.ctypes.data if want_grad else None
+        st = lib().ms_gradient_critical_chunked(self._h, f.ctypes.data, Dims(nx, ny, nz), int(slab), gp, None, cnt)
+        self._raise(st, "ms_gradient_critical_chunked (count)")
+        n = int(sum(cnt))
+        arrs = (np.empty(max(n, 1), np.uint64), np.empty(max(n, 1), np.uint8), np.empty(max(n, 1), np.float32),
+                np.empty(max(n, 1), np.uint64))
+        cr = Crit64(*[a.ctypes.data for a in arrs], n)
+        st = lib().ms_gradient_critical_chunked(self._h, f.ctypes.data, Dims(nx, ny, nz), int(slab), None,
+                                                C.byref(cr), cnt)
+        self._raise(st, "ms_gradient_critical_chunked")
+        return (grad,) + tuple(a[:n] for a in arrs) + (list(cnt),)
 
     def connect(self, grad: torch.Tensor, dims, crit_id: torch.Tensor, counts) -> "Arcs":
         self._sync_stream()

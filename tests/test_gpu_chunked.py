@@ -1,0 +1,121 @@
+"""Out-of-core gradient and critical cells (ms_gradient_critical_chunked).
+
+* Small fields, many slab heights (one row up to the whole field): the
+  gradient words and the critical list (ids widened to 64 bits) equal the
+  oracle's on the whole field, bit for bit -- the slabs' halos make every
+  lower star exact and the slabs' lists concatenate in id order.
+* A field of 1024 x 1024 x 600 vertices (more than the 2^29 vertices whose
+  cell ids fit the 32-bit in-HBM entry points), separable with integer
+  values: its critical counts per index are the closed-form count polynomial
+  prod_axes (m + M t) (m = 1D minima, M = interior 1D maxima; pinned against
+  the oracle in tests/test_oracle_pins.py), its ids strictly increase, and
+  each value is the field at the recorded highest vertex.
+* Non-finite input and too small an output are reported."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2009_03707_amd import fields
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2009_03707_amd import msc
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = msc.Context()
+    yield c
+    c.close()
+
+
+CASES = [("rand", (9, 8, 7), 0), ("rand", (16, 5, 23), 1), ("rand", (1, 1, 9), 2), ("rand", (13, 1, 6), 3),
+         ("grf", (30, 24, 20), 4), ("blob", (40, 33, 27), 5), ("sine", 32, 0)]
+
+
+def _field(kind, dims, seed):
+    if kind == "rand":
+        return fields.random_field(dims, seed=seed, levels=seed % 3)
+    if kind == "grf":
+        return fields.grf_field(dims, seed=seed)
+    if kind == "blob":
+        return fields.blob_field(dims, nblobs=6, seed=seed)
+    return fields.sine_field(dims)
+
+
+@pytest.mark.parametrize("kind,dims,seed", CASES)
+def test_slabs_equal_oracle(ctx, kind, dims, seed):
+    f = _field(kind, dims, seed)
+    ref_g = O.gradient(f)
+    ref = O.critical(f, ref_g)
+    nz = f.shape[0]
+    for slab in sorted({1, 2, 3, 5, max(1, nz // 2), nz}):
+        grad, cid, idx, val, vmax, cnt = ctx.gradient_critical_chunked(f, slab)
+        np.testing.assert_array_equal(grad, ref_g, err_msg=f"slab {slab}")
+        assert cnt == ref.count.tolist(), slab
+        np.testing.assert_array_equal(cid, ref.id.astype(np.uint64))
+        np.testing.assert_array_equal(idx, ref.index)
+        np.testing.assert_array_equal(val.view(np.uint32), ref.value.view(np.uint32))
+        np.testing.assert_array_equal(vmax, ref.vmax.astype(np.uint64))
+
+
+def _zigzag(n, period, phase):
+    """Integer sequence with distinct neighbours and a few extrema:
+    |((i + phase) mod period) - period / 2| doubled, plus one for the
+    falling half, so neighbours always differ."""
+    t = (np.arange(n) + phase) % period
+    h = period // 2
+    return np.where(t < h, 2 * (h - t) + 1, 2 * (t - h)).astype(np.float64)
+
+
+def _count_poly_1d(seq):
+    n = len(seq)
+    m = sum(1 for i in range(n) if (i == 0 or seq[i - 1] > seq[i]) and (i == n - 1 or seq[i + 1] > seq[i]))
+    M = sum(1 for i in range(1, n - 1) if seq[i - 1] < seq[i] > seq[i + 1])
+    return m, M
+
+
+def test_beyond_32bit_cell_ids(ctx):
+    nx, ny, nz = 1024, 1024, 600
+    assert nx * ny * nz > (1 << 29)
+    # z minima at 160, 360, 560: the last lies beyond vertex 2^29 (cell id 2^32)
+    a, b, c = _zigzag(nx, 300, 7), _zigzag(ny, 410, 100), _zigzag(nz, 200, 140)
+    f = np.empty((nz, ny, nx), np.float32)
+    ab = (b[:, None] + a[None, :]).astype(np.float32)
+    for z in range(nz):
+        np.add(ab, np.float32(c[z]), out=f[z])
+    print("[chunked] field built", flush=True)
+    grad, cid, idx, val, vmax, cnt = ctx.gradient_critical_chunked(f, 120, want_grad=False)
+    poly = np.array([1])
+    for seq in (a, b, c):
+        m, M = _count_poly_1d(list(seq))
+        poly = np.polymul(poly, np.array([M, m]))
+    want = [int(x) for x in list(poly[::-1]) + [0] * 4][:4]
+    assert cnt == want
+    off = np.cumsum([0] + cnt)
+    for k in range(4):
+        ids = cid[off[k]:off[k + 1]]
+        assert (np.diff(ids.astype(np.int64)) > 0).all()
+        assert (idx[off[k]:off[k + 1]] == k).all()
+        assert bin(int(ids[0]) & 7).count("1") == k if len(ids) else True
+    assert int(cid.max()) >= (1 << 32)  # cells whose ids do not fit 32 bits
+    flat = f.reshape(-1)
+    np.testing.assert_array_equal(val, flat[vmax.astype(np.int64)])
+    assert ((cid >> np.uint64(3)) <= vmax).all()
+
+
+def test_errors(ctx):
+    from paper_2009_03707_amd import msc
+    f = fields.random_field((10, 9, 8), seed=1)
+    bad = f.copy()
+    bad[5, 3, 2] = np.inf
+    with pytest.raises(msc.MscError) as e:
+        ctx.gradient_critical_chunked(bad, 2)
+    assert e.value.status == msc.MS_ERR_NONFINITE
+    lib, C = msc.lib(), msc.C
+    cnt = (C.c_int64 * 4)()
+    out = msc.Crit64(None, None, None, None, 0)
+    st = lib.ms_gradient_critical_chunked(ctx._h, f.ctypes.data, msc.Dims(10, 9, 8), 3, None, C.byref(out), cnt)
+    assert st == msc.MS_ERR_CAPACITY and sum(cnt) > 0

@@ -96,9 +96,10 @@ void critical_finish(ms_ctx* c, const float* f, const float* const* fptr, const 
                      const ms_crit* out, int64_t h_count[4], const int* d_err, ms_status* nonfinite, uint64_t* tmp) {
     const uint64_t* d_tot = crit_totals_ptr(tmp, g.nv);
     uint64_t* flag_slot = tmp + crit_tmp_elems(g.nv);
-    check(c, hipMemcpyAsync(c->h_small, d_tot, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream), "readback");
-    check(c, hipMemcpyAsync(c->h_small + 8, flag_slot, sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream),
-          "readback");
+    // counts and the flag slot after them are contiguous: one readback
+    static_assert(HOST_SCRATCH_WORDS >= 9, "scratch too small");
+    check(c, launch_publish(d_tot, 8, c->h_small_dev, c->stream), "readback");
+    check(c, launch_publish(flag_slot, 1, c->h_small_dev + 8, c->stream), "readback");
     check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     if (d_err && c->h_small[8]) {
         *nonfinite = MS_ERR_NONFINITE;
@@ -193,7 +194,9 @@ ms_status ms_ctx_create(ms_ctx** out, void* stream, ms_alloc_fn alloc_fn, ms_fre
         delete c;
         return MS_ERR_HIP;
     }
-    if (hipHostMalloc((void**)&c->h_small, HOST_SCRATCH_WORDS * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->h_small, HOST_SCRATCH_WORDS * sizeof(uint64_t),
+                      hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&c->h_small_dev, c->h_small, 0) != hipSuccess) {
         (void)hipGetLastError();
         delete c;
         return MS_ERR_OOM;

@@ -591,8 +591,7 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
         while (ncur > 0) {
             uint32_t* cur = buf<uint32_t>(c, cur_name, ncur);
             uint32_t* nxt = buf<uint32_t>(c, nxt_name, 4 * ncur);
-            uint64_t init = J << 32;
-            check(c, hipMemcpyAsync(d_cnt, &init, 8, hipMemcpyHostToDevice, s), "counter init");
+            check(c, launch_set_u64((uint64_t*)d_cnt, J << 32, s), "counter init");
             check(c, launch_bfs_expand(cur, ncur, level0, grad, g, vis, nxt, d_cnt, label, s), "bfs expand");
             uint64_t h = readback(c, (const uint64_t*)d_cnt, 1)[0];
             uint64_t nn = h & 0xFFFFFFFFull;

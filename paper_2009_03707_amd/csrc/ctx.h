@@ -30,7 +30,8 @@ struct ms_ctx {
         size_t cap = 0;
     };
     std::map<std::string, Buf> bufs;
-    uint64_t* h_small = nullptr;  // pinned host scratch (64 words)
+    uint64_t* h_small = nullptr;  // pinned, coherent host scratch for small readbacks
+    uint64_t* h_small_dev = nullptr;  // the same memory as the device addresses it
     // stage timing (events at stage boundaries of ms_complex)
     bool timing = false;
     hipEvent_t ev[8] = {};
@@ -148,11 +149,14 @@ inline void fail(ms_ctx* c, ms_status st, const std::string& msg) {
     throw Fail{st};
 }
 
+hipError_t launch_publish(const uint64_t* src, uint64_t n, uint64_t* dst, hipStream_t s);
+
 // Copies `n` uint64 words (n <= HOST_SCRATCH_WORDS) from device to the
-// pinned scratch and waits.
+// pinned scratch and waits.  A one-thread kernel writes them straight into
+// the scratch (coherent, device-mapped host memory).
 inline uint64_t* readback(ms_ctx* c, const uint64_t* d, size_t n) {
     if (n > HOST_SCRATCH_WORDS) fail(c, MS_ERR_INTERNAL, "readback larger than the pinned scratch");
-    check(c, hipMemcpyAsync(c->h_small, d, n * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream), "readback");
+    check(c, launch_publish(d, n, c->h_small_dev, c->stream), "readback");
     check(c, hipStreamSynchronize(c->stream), "stream synchronize");
     return c->h_small;
 }

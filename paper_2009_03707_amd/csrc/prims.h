@@ -47,6 +47,14 @@ __device__ __forceinline__ T block_excl_scan(T x, T* scratch, T& total) {
     return inc - x + scratch[w];
 }
 
+// Copies n words to `dst`, memory the device can write directly (the
+// context's pinned, device-mapped host scratch): small readbacks without a
+// copy-engine or blit round of their own.
+hipError_t launch_publish(const uint64_t* src, uint64_t n, uint64_t* dst, hipStream_t s);
+// *dst = v (a kernel, so that a host value reaches the device without a
+// host-to-device copy of pageable memory).
+hipError_t launch_set_u64(uint64_t* dst, uint64_t v, hipStream_t s);
+
 // Device-wide exclusive prefix sum of n uint64 values (out may equal in);
 // writes the total to *d_total when non-null.  `tmp` needs
 // scan_tmp_elems(n) uint64 elements.

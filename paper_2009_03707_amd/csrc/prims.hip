@@ -294,6 +294,26 @@ hipError_t radix_impl(const K* keys0, const uint32_t* vals0, K* ka, uint32_t* va
 
 }  // namespace
 
+namespace {
+__global__ void k_publish(const uint64_t* __restrict__ src, uint64_t n, uint64_t* __restrict__ dst) {
+    for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+__global__ void k_set_u64(uint64_t* __restrict__ dst, uint64_t v) {
+    if (threadIdx.x == 0) *dst = v;
+}
+}  // namespace
+
+hipError_t launch_publish(const uint64_t* src, uint64_t n, uint64_t* dst, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, src, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u64(uint64_t* dst, uint64_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, dst, v);
+    return hipGetLastError();
+}
+
 size_t scan_tmp_elems(uint64_t n) {
     size_t t = 1;
     while (n > (uint64_t)STILE) {

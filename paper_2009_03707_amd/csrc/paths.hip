@@ -723,7 +723,9 @@ __global__ __launch_bounds__(BT) void k_block_start(const uint64_t* __restrict__
 // list lies inside the block's entry range, else in global memory.  The
 // head of a run of equal rows (no earlier list holds the row) sums the
 // run's scaled counts.  Entries of columns beyond the staged window read
-// their metadata from global memory (same result).
+// their metadata from global memory (same result).  Each entry's own scaled
+// count is loaded in phase 1 together with its row, so that its latency
+// overlaps the barrier instead of opening phase 2.
 // off: exclusive scan of ub (n + 1 entries, off[n] = T).
 __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* __restrict__ off, uint64_t T,
                                                    const uint32_t* __restrict__ bstart, uint32_t* __restrict__ hrow,
@@ -797,12 +799,14 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
     uint32_t e_col[EPT], e_list[EPT], e_loc[EPT], x[EPT];
     bool e_win[EPT];
     uint64_t e_glo[EPT];
+    uint64_t own[EPT];  // the entry's own scaled count, loaded with its row
 #pragma unroll
     for (int r = 0; r < EPT; r++) {
         const uint32_t j = (uint32_t)r * BT + threadIdx.x;
         const uint64_t e = e0 + j;
         e_win[r] = false;
         e_glo[r] = 0;
+        own[r] = 0;
         e_col[r] = 0;
         e_list[r] = 0;
         e_loc[r] = 0;
@@ -827,6 +831,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
             e_list[r] = q;
             e_loc[r] = (uint32_t)local;
             x[r] = (q == 0 ? a.bcol : a.arow)[s_lo[b + q] + local];
+            own[r] = sat_mul((q == 0 ? a.bval : a.aval)[s_lo[b + q] + local], s_mul[b + q]);
         } else {
             uint64_t glo = i0 + lo, ghi = a.n;  // last i with off[i] <= e
             while (ghi - glo > 1) {
@@ -847,6 +852,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
             e_list[r] = q;
             e_loc[r] = (uint32_t)local;
             x[r] = L.row[local];
+            own[r] = sat_mul(L.val[local], L.mul);
         }
         s_x[j] = x[r];
     }
@@ -865,7 +871,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
         if (e_win[r]) {
             const uint32_t lo = e_col[r], b = s_lbase[lo], k = s_lbase[lo + 1] - b;
             start = s_off[lo];
-            sum = sat_mul((s == 0 ? a.bval : a.aval)[s_lo[b + s] + e_loc[r]], s_mul[b + s]);
+            sum = own[r];
             uint64_t lstart = start;  // first entry of list t
             for (uint32_t t = 0; t < k; t++) {
                 const uint32_t l = s_len[b + t];
@@ -897,7 +903,7 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
             const uint32_t k = num_lists(a, c);
             start = off[glo];
             const ListRef L = list_of(a, c, s);
-            sum = sat_mul(L.val[e_loc[r]], L.mul);
+            sum = own[r];
             for (uint32_t t = 0; t < k; t++) {
                 if (t == s) continue;
                 const ListRef M = list_of(a, c, t);

@@ -3,9 +3,11 @@
 It picks, per GPU architecture and size class:
   * the gradient workgroup tile shape (MS_OPT_GRADIENT_TILE), timed on the
     gradient stage alone;
-  * the path-counting schedule (MS_OPT_PATH_SCHEDULE: ready frontier or the
-    paper's power iteration) and the column-merge parameters
-    (MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK), timed on the path stage.
+  * the path-counting schedule (MS_OPT_PATH_SCHEDULE: the ready frontier
+    with column merges, the ready frontier with entry-parallel merges, or
+    the paper's power iteration, the last only below 2^26 voxels) and the
+    ready schedule's column-merge parameters (MS_OPT_MERGE_LIGHT,
+    MS_OPT_MERGE_CHUNK), timed on the path stage.
 
 None of these options changes any result (the library is bit-exact for every
 setting); only the time does.  Choices are cached as JSON in

@@ -174,6 +174,52 @@ def transfer_bench(ctx, f, torch, msc, reps=3):
             "d2h_bytes": int(d2h)}
 
 
+def out_of_core_bench(ctx, f, torch, msc, slab=64, reps=2):
+    """ms_gradient_critical_chunked on the benchmark field held in host
+    memory, streamed in z-slabs (copies of the next slab overlap the current
+    slab's kernels); whole-job rate including the host-to-device traffic."""
+    import numpy as np
+    f = np.ascontiguousarray(f)
+    ctx.gradient_critical_chunked(f, slab, want_grad=False)  # warm
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, cid, idx, val, vmax, cnt = ctx.gradient_critical_chunked(f, slab, want_grad=False)
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    return {"slab_rows": slab, "ms_per_call": round(ms, 2), "mvox_s": round(f.size / ms / 1e3, 2),
+            "h2d_gbs": round(4 * f.size * (slab + 3) / slab / (ms / 1e3) / 1e9, 2), "critical_counts": cnt,
+            "note": "host field in, critical list out (64-bit ids); counts equal the in-HBM run's"}
+
+
+def graph_bench(torch, msc, nthreads=16):
+    """Host MS-complex graph of the 256^3 GRF (build from the device result)
+    and its simplification, serial and by the paper's subgrid schedule."""
+    from paper_2009_03707_amd import fields
+    f = fields.grf_field((256, 256, 256), seed=0)
+    fd = torch.from_numpy(f).cuda()
+    ctx = msc.Context()
+    r = ctx.complex_raw(fd)
+    torch.cuda.synchronize()
+    out = {"workload": "grf256 (256^3 k^-3 GRF, seed 0)", "nodes": int(sum(r.count)), "threads": nthreads}
+    t0 = time.perf_counter()
+    g = msc.Graph.from_result(ctx, r, (256, 256, 256), nthreads=nthreads)
+    out["build_s"] = round(time.perf_counter() - t0, 3)
+    out["arcs"] = g.counts()[1]
+    thr = 0.05  # in units of the field's standard deviation (the GRF is normalised)
+    t0 = time.perf_counter()
+    n = g.simplify(thr, msc.MS_SIMPLIFY_SERIAL, 1)
+    out["serial"] = {"threshold": thr, "cancellations": n, "s": round(time.perf_counter() - t0, 3),
+                     "alive": g.counts()[0]}
+    g.close()
+    g = msc.Graph.from_result(ctx, r, (256, 256, 256), nthreads=nthreads)
+    t0 = time.perf_counter()
+    n = g.simplify(thr, msc.MS_SIMPLIFY_SUBGRID, 2)
+    out["subgrid2"] = {"threshold": thr, "cancellations": n, "s": round(time.perf_counter() - t0, 3),
+                       "alive": g.counts()[0]}
+    g.close()
+    ctx.close()
+    return out
+
+
 def batch_bench(args, torch, msc):
     """The same kernels on the uneven 64-field batch: one field per call in
     sequence (plain) versus one ms_complex_batch call (batched)."""
@@ -231,6 +277,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--no-transfers", dest="transfers", action="store_false",
                     help="skip the run that includes the host-device copies")
+    ap.add_argument("--no-extras", dest="extras", action="store_false",
+                    help="skip the out-of-core run and the host graph / simplification timings")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device-to-device copy of this many MiB (a known-size kernel for "
                          "scaling hardware traffic counters)")
@@ -328,6 +376,12 @@ def main():
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
     log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
     transfers = transfer_bench(ctx, f, torch, msc) if args.transfers else None
+    ooc = None
+    if args.extras:
+        log("out-of-core run of the same field from host memory")
+        ooc = out_of_core_bench(ctx, f, torch, msc)
+        if ooc["critical_counts"] != counts:
+            raise SystemExit(f"out-of-core counts {ooc['critical_counts']} differ from the in-HBM run's {counts}")
     out = {
         "metric": "MS-complex Mvoxels/s at 512^3 (plain vs batched), %HBM peak; p50/p99 latency",
         "value": round(value, 2),
@@ -352,6 +406,8 @@ def main():
     }
     if transfers:
         out["with_transfers"] = transfers
+    if ooc:
+        out["out_of_core"] = ooc
     ctx.close()
     del fd
     torch.cuda.empty_cache()
@@ -363,6 +419,9 @@ def main():
         out["served"] = serve.serve_benchmark(steps=args.serve_steps, slots=args.serve_slots, options=tuned,
                                               log=log)
         torch.cuda.empty_cache()
+    if args.extras:
+        log("host MS-complex graph and simplification of grf256")
+        out["graph"] = graph_bench(torch, msc)
     if args.cpu_sample > 0:
         log(f"timing the oracle on a {args.cpu_sample}^3 crop")
         out["cpu_baseline"] = cpu_baseline(f, args.cpu_sample)

@@ -27,6 +27,12 @@ SQ_THREAD_CYCLES_VALU, SQ_BUSY_CU_CYCLES, GRBM_GUI_ACTIVE in one --pmc run),
 with the kernel's source hash:
 
     python -m paper_2009_03707_amd.prof_summary valu COUNTERS.csv KERNEL SOURCE
+
+SQ instruction counters of one kernel per launch (SQ_INSTS_VALU,
+SQ_INSTS_SALU, SQ_WAVE_CYCLES, SQ_BUSY_CYCLES in one --pmc run), with the
+instructions per 64 entries when the entries per launch are given:
+
+    python -m paper_2009_03707_amd.prof_summary sq COUNTERS.csv KERNEL SOURCE [ENTRIES]
 """
 import collections
 import csv
@@ -138,7 +144,42 @@ def valu(csv_path, kernel, source, cus=256):
         print(f"lanes_per_valu_inst: {per.get('SQ_THREAD_CYCLES_VALU', 0) / per['SQ_ACTIVE_INST_VALU']:.2f}")
 
 
+def sq(csv_path, kernel, source, entries_per_launch=0):
+    """SQ instruction and cycle counters of one kernel per launch, from a
+    --pmc run with SQ_INSTS_VALU, SQ_INSTS_SALU, SQ_WAVE_CYCLES and
+    SQ_BUSY_CYCLES; with the entries one launch ranks, the instructions per
+    64 entries (one wave's worth)."""
+    import hashlib
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = hashlib.sha256(open(os.path.join(here, "csrc", source), "rb").read()).hexdigest()
+    acc = collections.defaultdict(float)
+    disp = set()
+    with open(csv_path, newline="") as fh:
+        for row in csv.DictReader(fh):
+            if not short(row["Kernel_Name"]).startswith(kernel):
+                continue
+            disp.add(row["Dispatch_Id"])
+            acc[row["Counter_Name"]] += float(row["Counter_Value"])
+    n = max(len(disp), 1)
+    per = {k: v / n for k, v in acc.items()}
+    print(f"# {kernel}: SQ counters per launch, mean over the launches (summed over shader engines and dies)")
+    print(f"kernel: {kernel}")
+    print(f"source: {source}")
+    print(f"source_sha256: {src}")
+    print(f"launches: {len(disp)}")
+    for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"):
+        print(f"{c.lower()}_per_launch: {per.get(c, 0):.0f}")
+    if entries_per_launch:
+        print(f"entries_per_launch: {entries_per_launch}")
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_SALU"):
+            print(f"{c[9:].lower()}_insts_per_64_entries: {64.0 * per.get(c, 0) / entries_per_launch:.1f}")
+
+
 def main():
+    if sys.argv[1] == "sq":
+        sq(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]) if len(sys.argv) > 5 else 0)
+        return
     if sys.argv[1] == "valu":
         valu(sys.argv[2], sys.argv[3], sys.argv[4])
         return

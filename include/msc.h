@@ -124,7 +124,14 @@ enum {
      * graph per set of dims and replays it while the dims and the context's
      * buffers stay the same; 0 launches it eagerly.  The graph is also
      * bypassed while timing is on.  Results never depend on it. */
-    MS_OPT_BATCH_GRAPH = 5
+    MS_OPT_BATCH_GRAPH = 5,
+    /* Sparse transposes (the column-major copies of the arc and path
+     * matrices): when every value of a matrix fits in the bits its row ids
+     * leave free, and in at most this many bits (1..24, default 24), the
+     * values travel packed with the row ids through the radix passes; else
+     * (and always with 0) as a separate 64-bit payload.  Results never
+     * depend on it. */
+    MS_OPT_TRANSPOSE_PACK = 6
 };
 enum {
     /* Default.  A* is the solution of A* = A + A* B; its columns are formed by

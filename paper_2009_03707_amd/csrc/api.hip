@@ -267,6 +267,10 @@ ms_status ms_ctx_set_option(ms_ctx* ctx, int option, int64_t value) {
         ctx->batch_graph = value != 0;
         return MS_OK;
     }
+    if (option == MS_OPT_TRANSPOSE_PACK && value >= 0 && value <= 24) {
+        ctx->transpose_pack = (int)value;
+        return MS_OK;
+    }
     ctx->err = "unknown option or value";
     return MS_ERR_INVALID_ARG;
 }

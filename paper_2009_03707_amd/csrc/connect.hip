@@ -21,9 +21,10 @@ hipError_t launch_m32t(bool fill, const uint32_t* s2, uint64_t S2, const Geo& g,
 hipError_t launch_manifold_labels(uint32_t* Pv, uint32_t* Pc, const Geo& g, const uint64_t* before, hipStream_t s);
 int bit_width(uint64_t v);
 hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, const uint32_t* map, uint32_t* rows,
-                              hipStream_t s);
+                              hipStream_t s, const uint64_t* val = nullptr, int vb = 0);
 hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s);
 hipError_t launch_sum_u32(const uint32_t* a, uint64_t n, uint64_t* out, hipStream_t s);
+hipError_t launch_max_u64(const uint64_t* a, uint64_t n, uint64_t* out, hipStream_t s);
 hipError_t launch_hist(const uint32_t* keys, uint64_t n, uint32_t* h, hipStream_t s);
 size_t key_bounds_tmp_elems(uint64_t n, uint64_t nkeys);
 hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, uint64_t* rowptr, uint64_t* tmp,
@@ -106,13 +107,14 @@ uint64_t counts_to_rowptr(ms_ctx* c, const uint32_t* cnt, uint64_t n, uint64_t* 
     return read_u64(c, rowptr + n);
 }
 
-// Transpose of a CSR (stable radix sort by column; rows of the output come out
-// with ascending columns because input entries are in row-major order).
-// Transpose: a stable radix sort of the column ids (read in place, entry
-// index as payload), a gather of rows and values, and the row pointer of
-// the result from the boundaries between equal keys.
-// With row_map set, the transposed matrix's column ids are row_map[row]
-// (the input's rows renumbered while they are expanded, read in order).
+// Transpose of a CSR: a stable radix sort of the column ids (read in
+// place), carrying each entry's row (row_map[row] when a map is given: the
+// input's rows renumbered while they are expanded) and value, and the row
+// pointer of the result from the boundaries between equal keys.  Rows of
+// the output come out with ascending columns because the input entries are
+// in row-major order.  When every value fits in the bits the row ids leave
+// free (their largest is read back first), values ride in those bits;
+// otherwise they move as a separate 64-bit payload.
 void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const uint32_t* row_map = nullptr) {
     uint64_t nnz = (uint64_t)in.nnz;
     out = csr_buf(c, name, (uint64_t)in.ncols, (uint64_t)in.nrows, nnz);
@@ -125,15 +127,33 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const
     uint32_t* kb = buf<uint32_t>(c, "tr.kb", nnz);
     uint32_t* va = buf<uint32_t>(c, "tr.va", nnz);
     uint32_t* vb = buf<uint32_t>(c, "tr.vb", nnz);
-    uint64_t* wa = buf<uint64_t>(c, "tr.wa", nnz);
-    uint64_t* wb = buf<uint64_t>(c, "tr.wb", nnz);
     uint64_t* tmp = buf<uint64_t>(c, "tr.tmp", radix_tmp_elems(nnz));
-    check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, row_map, rows, c->stream),
-          "expand rows");
+    const int kbits = bit_width((uint64_t)in.ncols - 1);
+    const int free_bits = 32 - bit_width((uint64_t)in.nrows - 1);
+    const int vbits = free_bits < c->transpose_pack ? free_bits : c->transpose_pack;
+    bool packed = false;
+    if (vbits >= 1) {
+        uint64_t* d_max = buf<uint64_t>(c, "tr.max", 1);
+        check(c, launch_max_u64((const uint64_t*)in.val, nnz, d_max, c->stream), "max");
+        packed = read_u64(c, d_max) < (1ull << vbits);
+    }
     const uint32_t* keys = nullptr;
-    check(c, radix_transpose_u32(in.col, rows, (const uint64_t*)in.val, ka, va, kb, vb, wa, wb, nnz,
-                                 bit_width((uint64_t)in.ncols - 1), tmp, out.col, (uint64_t*)out.val, &keys, c->stream),
-          "sort");
+    if (packed) {
+        check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, row_map, rows, c->stream,
+                                    (const uint64_t*)in.val, vbits),
+              "expand rows");
+        const Unpack up{vbits, out.col, (uint64_t*)out.val};
+        check(c, radix_transpose_packed_u32(in.col, rows, ka, va, kb, vb, nnz, kbits, tmp, up, &keys, c->stream),
+              "sort");
+    } else {
+        uint64_t* wa = buf<uint64_t>(c, "tr.wa", nnz);
+        uint64_t* wb = buf<uint64_t>(c, "tr.wb", nnz);
+        check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, row_map, rows, c->stream),
+              "expand rows");
+        check(c, radix_transpose_u32(in.col, rows, (const uint64_t*)in.val, ka, va, kb, vb, wa, wb, nnz, kbits, tmp,
+                                     out.col, (uint64_t*)out.val, &keys, c->stream),
+              "sort");
+    }
     uint64_t* gtmp = buf<uint64_t>(c, "tr.gaps", key_bounds_tmp_elems(nnz, (uint64_t)in.ncols));
     check(c, launch_key_bounds(keys, nnz, (uint64_t)in.ncols, (uint64_t*)out.rowptr, gtmp, c->stream), "bounds");
 }

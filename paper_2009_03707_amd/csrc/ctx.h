@@ -49,6 +49,7 @@ struct ms_ctx {
     uint32_t merge_light = 32;   // see MS_OPT_MERGE_LIGHT
     uint32_t merge_chunk = 4096; // see MS_OPT_MERGE_CHUNK
     int grad_tile = 0;           // see MS_OPT_GRADIENT_TILE
+    int transpose_pack = 24;     // see MS_OPT_TRANSPOSE_PACK
     uint32_t wave_blocks = 1024; // workgroups of a wave-path merge launch (4 per compute unit)
     // graph of the front of ms_complex_batch, captured on a private stream
     // and keyed by the dims and the buffers it uses (see ms_complex_batch)

@@ -82,6 +82,18 @@ hipError_t radix_transpose_u32(const uint32_t* keys, const uint32_t* rows, const
                                uint32_t* va, uint32_t* kb, uint32_t* vb, uint64_t* wa, uint64_t* wb, uint64_t n,
                                int bits, uint64_t* tmp, uint32_t* ocol, uint64_t* oval, const uint32_t** sorted_keys,
                                hipStream_t s);
+// Packed transpose: each 32-bit payload holds an entry's output column in
+// its high bits and its value in its low vb bits (the caller has checked
+// that every value fits), so only 8 bytes per entry move through the
+// passes; the last pass splits the payload into ocol and oval.
+struct Unpack {
+    int vb;          // value bits, 1..24
+    uint32_t* ocol;  // n output column ids
+    uint64_t* oval;  // n output values
+};
+hipError_t radix_transpose_packed_u32(const uint32_t* keys, const uint32_t* packed, uint32_t* ka, uint32_t* va,
+                                      uint32_t* kb, uint32_t* vb, uint64_t n, int bits, uint64_t* tmp,
+                                      const Unpack& up, const uint32_t** sorted_keys, hipStream_t s);
 // Same, reading the keys from `keys` (left intact) with the entry index as
 // payload; the result lands in (a) or (b).
 hipError_t radix_sort_u32_from(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,

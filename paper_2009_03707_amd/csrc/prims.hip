@@ -110,12 +110,13 @@ struct Wide {
 // digit's global offset for this tile.  vals null: the payload is the entry
 // index.  With a side payload (wd.win set) the same LDS then stages the
 // 64-bit side values, read again in the input order, and writes them in
-// the same runs.
+// the same runs.  With up.ocol set (the last pass of a packed transpose)
+// each payload is split into its column and value instead of written out.
 template <typename K, int DB>
 __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, const uint32_t* __restrict__ vals,
                                                     K* __restrict__ okeys, uint32_t* __restrict__ ovals, uint64_t n,
                                                     int shift, uint64_t nblk, const uint64_t* __restrict__ offs,
-                                                    Wide wd) {
+                                                    Wide wd, Unpack up) {
     constexpr uint32_t NB = 1u << DB;
     constexpr uint32_t DPT = NB / RT;       // digits owned by one thread in the tile scan
     constexpr int WR = RTILE / RWAVES / WAVE;  // rounds of one wave (RR)
@@ -202,6 +203,19 @@ __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, 
         }
     }
     __syncthreads();
+    if (up.ocol) {  // uniform
+        const uint32_t mask = (1u << up.vb) - 1u;
+        for (uint32_t i = (uint32_t)tid; i < tot; i += RT) {
+            const K key = skey[i];
+            const uint32_t d = (uint32_t)(key >> shift) & (NB - 1u);
+            const uint64_t g = gbase[d] + (i - tstart[d]);
+            const uint32_t v = sval[i];
+            okeys[g] = key;
+            up.ocol[g] = v >> up.vb;
+            up.oval[g] = v & mask;
+        }
+        return;
+    }
     for (uint32_t i = (uint32_t)tid; i < tot; i += RT) {
         const K key = skey[i];
         const uint32_t d = (uint32_t)(key >> shift) & (NB - 1u);
@@ -235,14 +249,15 @@ __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, 
 
 template <typename K, int DB>
 hipError_t radix_pass(const K* src_k, const uint32_t* src_v, K* dst_k, uint32_t* dst_v, uint64_t n, int sh,
-                      uint64_t nblk, uint64_t* hist, uint64_t* stmp, const Wide& wd, hipStream_t s) {
+                      uint64_t nblk, uint64_t* hist, uint64_t* stmp, const Wide& wd, const Unpack& up,
+                      hipStream_t s) {
     hipLaunchKernelGGL((radix_hist<K, DB>), dim3((unsigned)nblk), dim3(RT), 0, s, src_k, n, sh, nblk, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = scan_impl<uint64_t>(hist, hist, (uint64_t)(1u << DB) * nblk, stmp, (uint64_t*)nullptr, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((radix_scatter<K, DB>), dim3((unsigned)nblk), dim3(RT), 0, s, src_k, src_v, dst_k, dst_v, n, sh,
-                       nblk, (const uint64_t*)hist, wd);
+                       nblk, (const uint64_t*)hist, wd, up);
     return hipGetLastError();
 }
 
@@ -252,11 +267,12 @@ hipError_t radix_pass(const K* src_k, const uint32_t* src_v, K* dst_k, uint32_t*
 // are 8 bits, or 9 when that needs fewer passes.  With w0 set, a 64-bit
 // side payload moves along, from w0 through (wa, wb).  With last_v set, the
 // last pass writes the payload to last_v and the side payload to last_w.
+// With last_up set, the last pass splits packed payloads as it describes.
 template <typename K>
 hipError_t radix_impl(const K* keys0, const uint32_t* vals0, K* ka, uint32_t* va, K* kb, uint32_t* vb, uint64_t n,
                       int bits, uint64_t* tmp, bool* in_b, hipStream_t s, const uint64_t* w0 = nullptr,
                       uint64_t* wa = nullptr, uint64_t* wb = nullptr, uint32_t* last_v = nullptr,
-                      uint64_t* last_w = nullptr) {
+                      uint64_t* last_w = nullptr, const Unpack* last_up = nullptr) {
     *in_b = false;
     if (n == 0) return hipSuccess;
     const int p8 = bits <= 0 ? 1 : (bits + 7) / 8;
@@ -277,8 +293,9 @@ hipError_t radix_impl(const K* keys0, const uint32_t* vals0, K* ka, uint32_t* va
         const bool last = p + 1 == passes;
         uint32_t* pv = last && last_v ? last_v : dst_v;
         const Wide wd{src_w, last && last_w ? last_w : dst_w};
-        hipError_t e = nine ? radix_pass<K, 9>(src_k, src_v, dst_k, pv, n, 9 * p, nblk, hist, stmp, wd, s)
-                            : radix_pass<K, 8>(src_k, src_v, dst_k, pv, n, 8 * p, nblk, hist, stmp, wd, s);
+        const Unpack up = last && last_up ? *last_up : Unpack{};
+        hipError_t e = nine ? radix_pass<K, 9>(src_k, src_v, dst_k, pv, n, 9 * p, nblk, hist, stmp, wd, up, s)
+                            : radix_pass<K, 8>(src_k, src_v, dst_k, pv, n, 8 * p, nblk, hist, stmp, wd, up, s);
         if (e != hipSuccess) return e;
         *in_b = dst_is_b;
         src_k = dst_k;
@@ -373,6 +390,17 @@ hipError_t radix_transpose_u32(const uint32_t* keys, const uint32_t* rows, const
                                hipStream_t s) {
     bool in_b = false;
     hipError_t e = radix_impl<uint32_t>(keys, rows, ka, va, kb, vb, n, bits, tmp, &in_b, s, val, wa, wb, ocol, oval);
+    *sorted_keys = in_b ? kb : ka;
+    return e;
+}
+
+hipError_t radix_transpose_packed_u32(const uint32_t* keys, const uint32_t* packed, uint32_t* ka, uint32_t* va,
+                                      uint32_t* kb, uint32_t* vb, uint64_t n, int bits, uint64_t* tmp,
+                                      const Unpack& up, const uint32_t** sorted_keys, hipStream_t s) {
+    if (up.vb < 1 || up.vb > 24 || !up.ocol || !up.oval) return hipErrorInvalidValue;
+    bool in_b = false;
+    hipError_t e = radix_impl<uint32_t>(keys, packed, ka, va, kb, vb, n, bits, tmp, &in_b, s, nullptr, nullptr,
+                                        nullptr, nullptr, nullptr, &up);
     *sorted_keys = in_b ? kb : ka;
     return e;
 }

@@ -14,13 +14,20 @@ namespace {
 
 constexpr int BT = 256;
 
-// rows[p] = the row of entry p, or map[row] when a map is given.
+// rows[p] = the row of entry p, or map[row] when a map is given; with val
+// set, packed as (row << vb) | val[p] (every value below 2^vb).
 __global__ __launch_bounds__(BT) void k_expand_rows(const uint64_t* __restrict__ rowptr, uint64_t nrows,
-                                                    const uint32_t* __restrict__ map, uint32_t* __restrict__ rows) {
+                                                    const uint32_t* __restrict__ map, const uint64_t* __restrict__ val,
+                                                    int vb, uint32_t* __restrict__ rows) {
     uint64_t r = (uint64_t)blockIdx.x * BT + threadIdx.x;
     if (r >= nrows) return;
     const uint32_t v = map ? map[r] : (uint32_t)r;
-    for (uint64_t p = rowptr[r]; p < rowptr[r + 1]; p++) rows[p] = v;
+    const uint64_t e = rowptr[r + 1];
+    if (!val) {
+        for (uint64_t p = rowptr[r]; p < e; p++) rows[p] = v;
+        return;
+    }
+    for (uint64_t p = rowptr[r]; p < e; p++) rows[p] = (v << vb) | (uint32_t)val[p];
 }
 
 // *out += the sum of a[0, n) (one atomic per workgroup; *out zeroed by the caller)
@@ -32,6 +39,26 @@ __global__ __launch_bounds__(BT) void k_sum_u32(const uint32_t* __restrict__ a, 
     unsigned long long tot;
     block_excl_scan<unsigned long long, BT>(v, sc, tot);
     if (threadIdx.x == 0 && tot) atomicAdd(out, tot);
+}
+
+// *out = max(*out, the largest of a[0, n)) (one atomic per workgroup; *out zeroed by the caller)
+__global__ __launch_bounds__(BT) void k_max_u64(const uint64_t* __restrict__ a, uint64_t n,
+                                                unsigned long long* __restrict__ out) {
+    __shared__ unsigned long long sm[BT / WAVE];
+    unsigned long long v = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x; i < n; i += (uint64_t)gridDim.x * BT)
+        v = a[i] > v ? a[i] : v;
+#pragma unroll
+    for (int d = WAVE / 2; d >= 1; d >>= 1) {
+        const unsigned long long o = __shfl_xor(v, d, WAVE);
+        v = o > v ? o : v;
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0) sm[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < BT / WAVE; w++) v = sm[w] > v ? sm[w] : v;
+        if (v) atomicMax(out, v);
+    }
 }
 
 __global__ __launch_bounds__(BT) void k_iota(uint32_t* __restrict__ a, uint64_t n) {
@@ -190,9 +217,10 @@ hipError_t launch_key_bounds(const uint32_t* keys, uint64_t n, uint64_t nkeys, u
 }
 
 hipError_t launch_expand_rows(const uint64_t* rowptr, uint64_t nrows, const uint32_t* map, uint32_t* rows,
-                              hipStream_t s) {
+                              hipStream_t s, const uint64_t* val, int vb) {
     if (nrows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_expand_rows, dim3(grid_blocks(nrows, BT)), dim3(BT), 0, s, rowptr, nrows, map, rows);
+    hipLaunchKernelGGL(k_expand_rows, dim3(grid_blocks(nrows, BT)), dim3(BT), 0, s, rowptr, nrows, map, val, vb,
+                       rows);
     return hipGetLastError();
 }
 hipError_t launch_sum_u32(const uint32_t* a, uint64_t n, uint64_t* out, hipStream_t s) {
@@ -200,6 +228,13 @@ hipError_t launch_sum_u32(const uint32_t* a, uint64_t n, uint64_t* out, hipStrea
     if (e != hipSuccess || n == 0) return e;
     const unsigned nb = grid_blocks(n, BT) < 2048u ? grid_blocks(n, BT) : 2048u;
     hipLaunchKernelGGL(k_sum_u32, dim3(nb), dim3(BT), 0, s, a, n, (unsigned long long*)out);
+    return hipGetLastError();
+}
+hipError_t launch_max_u64(const uint64_t* a, uint64_t n, uint64_t* out, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(out, 0, sizeof(uint64_t), s);
+    if (e != hipSuccess || n == 0) return e;
+    const unsigned nb = grid_blocks(n, BT) < 2048u ? grid_blocks(n, BT) : 2048u;
+    hipLaunchKernelGGL(k_max_u64, dim3(nb), dim3(BT), 0, s, a, n, (unsigned long long*)out);
     return hipGetLastError();
 }
 hipError_t launch_iota(uint32_t* a, uint64_t n, hipStream_t s) {

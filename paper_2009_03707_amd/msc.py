@@ -28,7 +28,8 @@ EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_err
 MS_DOWN, MS_UP = 0, 1
 MS_SIMPLIFY_SERIAL, MS_SIMPLIFY_SUBGRID = 0, 1
 
-MS_OPT_PATH_SCHEDULE, MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK, MS_OPT_GRADIENT_TILE, MS_OPT_BATCH_GRAPH = 1, 2, 3, 4, 5
+(MS_OPT_PATH_SCHEDULE, MS_OPT_MERGE_LIGHT, MS_OPT_MERGE_CHUNK, MS_OPT_GRADIENT_TILE, MS_OPT_BATCH_GRAPH,
+ MS_OPT_TRANSPOSE_PACK) = 1, 2, 3, 4, 5, 6
 MS_PATHS_READY, MS_PATHS_POWER, MS_PATHS_ENTRY = 0, 1, 2
 
 

@@ -11,21 +11,28 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=["ready", "power", "ready-chunked", "entry"])
+@pytest.fixture(scope="module", params=["ready", "power", "ready-chunked", "entry", "entry-pack1", "entry-wide",
+                                        "ready-pack2"])
 def ctx(request):
-    """Both path-counting schedules: the default ready frontier and the
-    paper's power iteration; "ready-chunked" sends every column through the
-    workgroup merge with tiny chunks, so that chunk splitting is exercised on
-    small fields."""
+    """The path-counting schedules: the ready frontier, the paper's power
+    iteration and the entry ranking; "ready-chunked" sends every column
+    through the workgroup merge with tiny chunks, so that chunk splitting is
+    exercised on small fields.  The transposes: "entry-pack1" packs only
+    the matrices whose values are all 1 and "ready-pack2" those whose values
+    are at most 3 (the others move their values as a separate payload);
+    "entry-wide" packs none."""
     from paper_2009_03707_amd import msc
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     c = msc.Context()
-    c.set_path_schedule({"power": msc.MS_PATHS_POWER, "entry": msc.MS_PATHS_ENTRY}.get(request.param,
-                                                                                      msc.MS_PATHS_READY))
+    sched = request.param.split("-")[0]
+    c.set_path_schedule({"power": msc.MS_PATHS_POWER, "entry": msc.MS_PATHS_ENTRY}.get(sched, msc.MS_PATHS_READY))
     if request.param == "ready-chunked":
         c.set_option(msc.MS_OPT_MERGE_LIGHT, 0)
         c.set_option(msc.MS_OPT_MERGE_CHUNK, 3)
+    pack = {"entry-pack1": 1, "entry-wide": 0, "ready-pack2": 2}.get(request.param)
+    if pack is not None:
+        c.set_option(msc.MS_OPT_TRANSPOSE_PACK, pack)
     yield c
     c.close()
 

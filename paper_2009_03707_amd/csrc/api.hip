@@ -20,7 +20,7 @@ const uint64_t* crit_totals_ptr(const uint64_t* tmp, uint64_t nv);
 hipError_t launch_crit_count(const uint32_t* grad, const Geo& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s);
 hipError_t launch_crit_scatter(const float* f0, const float* const* fptr, const uint32_t* grad, const Geo& g,
                                const uint64_t* tmp, uint32_t* id, uint8_t* index, float* value, uint32_t* vmax,
-                               hipStream_t s);
+                               hipStream_t s, uint64_t cap = ~0ull);
 void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t* crit_id, const int64_t count[4],
                   ms_arcs* out);
 
@@ -119,6 +119,15 @@ void critical_finish(ms_ctx* c, const float* f, const float* const* fptr, const 
     if (!out->id || !out->index || !out->value || !out->vmax) fail(c, MS_ERR_INVALID_ARG, "null critical output array");
     check(c, launch_crit_scatter(f, fptr, grad, g, tmp, out->id, out->index, out->value, out->vmax, c->stream),
           "critical scatter launch");
+}
+
+// Records the context's critical-record buffers (cx_crit_*) hold now.
+uint64_t crit_record_capacity(const ms_ctx* c) {
+    size_t a = buf_elems<uint32_t>(c, "cx_crit_id"), b = buf_elems<uint8_t>(c, "cx_crit_index");
+    size_t d = buf_elems<float>(c, "cx_crit_value"), e = buf_elems<uint32_t>(c, "cx_crit_vmax");
+    size_t m = a < b ? a : b;
+    m = m < d ? m : d;
+    return m < e ? m : e;
 }
 
 void critical_impl(ms_ctx* c, const float* f, const float* const* fptr, const uint32_t* grad, const Geo& g,
@@ -411,7 +420,18 @@ ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out
     mark(ctx, 1);
     int64_t cnt[4];
     ms_status st = MS_OK;
-    critical_impl(ctx, d_f, nullptr, grad, single(g), nullptr, cnt, d_err, &st);
+    // the records go to context buffers: when they are already allocated the
+    // scatter is queued before the counts are read (it writes nothing if they
+    // do not fit), so the device does not wait for the host in between
+    uint64_t* tmp = buf<uint64_t>(ctx, "crit_tmp", crit_tmp_elems(g.nv) + 1);
+    critical_front(ctx, grad, single(g), tmp, d_err);
+    const uint64_t cap = crit_record_capacity(ctx);
+    if (cap > 0)
+        check(ctx, launch_crit_scatter(d_f, nullptr, grad, single(g), tmp, buf<uint32_t>(ctx, "cx_crit_id", 1),
+                                       buf<uint8_t>(ctx, "cx_crit_index", 1), buf<float>(ctx, "cx_crit_value", 1),
+                                       buf<uint32_t>(ctx, "cx_crit_vmax", 1), ctx->stream, cap),
+              "critical scatter launch");
+    critical_finish(ctx, d_f, nullptr, grad, single(g), nullptr, cnt, d_err, &st, tmp);
     if (st == MS_ERR_NONFINITE) fail(ctx, st, "the field contains NaN or infinite values");
     int64_t total = cnt[0] + cnt[1] + cnt[2] + cnt[3];
     ms_crit cr;
@@ -420,9 +440,9 @@ ms_status ms_complex(ms_ctx* ctx, const float* d_f, ms_dims dims, ms_result* out
     cr.value = buf<float>(ctx, "cx_crit_value", total);
     cr.vmax = buf<uint32_t>(ctx, "cx_crit_vmax", total);
     cr.capacity = total;
-    if (total > 0)
-        check(ctx, launch_crit_scatter(d_f, nullptr, grad, single(g), buf<uint64_t>(ctx, "crit_tmp", 1), cr.id,
-                                       cr.index, cr.value, cr.vmax, ctx->stream),
+    if (total > 0 && (uint64_t)total > cap)
+        check(ctx, launch_crit_scatter(d_f, nullptr, grad, single(g), tmp, cr.id, cr.index, cr.value, cr.vmax,
+                                       ctx->stream),
               "critical scatter launch");
     out->grad = grad;
     out->crit = cr;
@@ -537,6 +557,13 @@ ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f
     }
     int64_t cnt[4];
     ms_status st = MS_OK;
+    // as in ms_complex: queued before the counts are read when the record buffers exist
+    const uint64_t cap = crit_record_capacity(ctx);
+    if (cap > 0)
+        check(ctx, launch_crit_scatter(d_f[0], d_fptr, grad, geo, ctmp, buf<uint32_t>(ctx, "cx_crit_id", 1),
+                                       buf<uint8_t>(ctx, "cx_crit_index", 1), buf<float>(ctx, "cx_crit_value", 1),
+                                       buf<uint32_t>(ctx, "cx_crit_vmax", 1), s, cap),
+              "critical scatter launch");
     critical_finish(ctx, d_f[0], d_fptr, grad, geo, nullptr, cnt, d_err, &st, ctmp);
     if (st == MS_ERR_NONFINITE) fail(ctx, st, "a field contains NaN or infinite values");
     const int64_t ncrit = cnt[0] + cnt[1] + cnt[2] + cnt[3];
@@ -546,9 +573,8 @@ ms_status ms_complex_batch(ms_ctx* ctx, int32_t nfields, const float* const* d_f
     cr.value = buf<float>(ctx, "cx_crit_value", ncrit);
     cr.vmax = buf<uint32_t>(ctx, "cx_crit_vmax", ncrit);
     cr.capacity = ncrit;
-    if (ncrit > 0)
-        check(ctx, launch_crit_scatter(d_f[0], d_fptr, grad, geo, buf<uint64_t>(ctx, "crit_tmp", 1), cr.id, cr.index,
-                                       cr.value, cr.vmax, s),
+    if (ncrit > 0 && (uint64_t)ncrit > cap)
+        check(ctx, launch_crit_scatter(d_f[0], d_fptr, grad, geo, ctmp, cr.id, cr.index, cr.value, cr.vmax, s),
               "critical scatter launch");
     mark(ctx, 2);
     ms_arcs arcs;

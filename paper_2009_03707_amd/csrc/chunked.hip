@@ -33,7 +33,7 @@ size_t crit_tmp_elems(uint64_t nv);
 hipError_t launch_crit_count(const uint32_t* grad, const Geo& g, uint64_t* tmp, uint64_t** d_totals, hipStream_t s);
 hipError_t launch_crit_scatter(const float* f0, const float* const* fptr, const uint32_t* grad, const Geo& g,
                                const uint64_t* tmp, uint32_t* id, uint8_t* index, float* value, uint32_t* vmax,
-                               hipStream_t s);
+                               hipStream_t s, uint64_t cap = ~0ull);
 Geo single(const Grid& g);
 void flag_clear(ms_ctx* c, int* d_err);
 

@@ -89,16 +89,18 @@ __global__ void crit_totals(const uint64_t* __restrict__ excl, uint64_t nb, cons
 constexpr uint32_t CCAP = 2048;
 
 __global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f0, const float* const* __restrict__ fptr,
-                                                   const uint32_t* __restrict__ grad, Geo geo,
+                                                   const uint32_t* __restrict__ grad, Geo geo, uint64_t nb,
                                                    const uint64_t* __restrict__ excl,
+                                                   const uint64_t* __restrict__ guard, uint64_t cap,
                                                    uint32_t* __restrict__ o_id, uint8_t* __restrict__ o_index,
                                                    float* __restrict__ o_value, uint32_t* __restrict__ o_vmax) {
     __shared__ uint64_t sc[CT / WAVE + 1];
     __shared__ uint32_t s_id[CCAP];
     __shared__ uint32_t s_vmax[CCAP];
     const uint64_t nv = geo.nv;
-    const uint64_t nb = gridDim.x;
-    uint64_t base = (uint64_t)blockIdx.x * CTILE + (uint64_t)threadIdx.x * CWPT;
+    const uint64_t tile = blockIdx.x;
+    if (guard && guard[0] + guard[1] + guard[2] + guard[3] > cap) return;  // uniform
+    uint64_t base = tile * CTILE + (uint64_t)threadIdx.x * CWPT;
     uint32_t w[CWPT];
     uint64_t s = 0;
 #pragma unroll
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f0,
     uint64_t pos[4];
 #pragma unroll
     for (int k = 0; k < 4; k++)
-        pos[k] = (staged ? (uint64_t)seg[k] : excl[(uint64_t)k * nb + blockIdx.x]) + ((ex >> (16 * k)) & 0xFFFFu);
+        pos[k] = (staged ? (uint64_t)seg[k] : excl[(uint64_t)k * nb + tile]) + ((ex >> (16 * k)) & 0xFFFFu);
 #pragma unroll
     for (int i = 0; i < CWPT; i++) {
         uint32_t word = w[i];
@@ -150,7 +152,7 @@ __global__ __launch_bounds__(CT) void crit_scatter(const float* __restrict__ f0,
     if (!staged) return;  // uniform
     uint64_t eo[4];  // global start of each index run of this tile
 #pragma unroll
-    for (int k = 0; k < 4; k++) eo[k] = excl[(uint64_t)k * nb + blockIdx.x] - seg[k];
+    for (int k = 0; k < 4; k++) eo[k] = excl[(uint64_t)k * nb + tile] - seg[k];
     __syncthreads();
     constexpr int R = 4;  // records per thread per round, their loads in flight together
     for (uint32_t i0 = threadIdx.x; i0 < n; i0 += R * CT) {
@@ -219,13 +221,17 @@ hipError_t launch_crit_count(const uint32_t* grad, const Geo& g, uint64_t* tmp, 
 
 // Pass 2: the exclusive offsets over [index][block] are global positions in
 // the (index, id)-sorted list because index segments are concatenated.
+// With cap below ~0, the launch may precede the host's reading of the counts
+// (into record buffers of cap entries kept from an earlier call): every
+// workgroup reads the totals and writes nothing when they exceed cap.
 hipError_t launch_crit_scatter(const float* f0, const float* const* fptr, const uint32_t* grad, const Geo& g,
                                const uint64_t* tmp, uint32_t* id, uint8_t* index, float* value, uint32_t* vmax,
-                               hipStream_t s) {
+                               hipStream_t s, uint64_t cap) {
     uint64_t nb = (g.nv + CTILE - 1) / CTILE;
     const uint64_t* excl = tmp + 4 * nb;
-    hipLaunchKernelGGL(crit_scatter, dim3((unsigned)nb), dim3(CT), 0, s, f0, fptr, grad, g, excl, id, index, value,
-                       vmax);
+    const uint64_t* guard = cap == ~0ull ? nullptr : crit_totals_ptr(tmp, g.nv);
+    hipLaunchKernelGGL(crit_scatter, dim3((unsigned)nb), dim3(CT), 0, s, f0, fptr, grad, g, nb, excl, guard, cap, id,
+                       index, value, vmax);
     return hipGetLastError();
 }
 

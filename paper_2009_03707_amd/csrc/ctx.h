@@ -114,6 +114,13 @@ T* buf(ms_ctx* c, const char* name, size_t count) {
     return (T*)b.p;
 }
 
+// Elements of T that buffer `name` holds now (0 if it was never allocated).
+template <typename T>
+size_t buf_elems(const ms_ctx* c, const char* name) {
+    auto it = c->bufs.find(name);
+    return it == c->bufs.end() ? 0 : it->second.cap / sizeof(T);
+}
+
 // Like buf(), but a growth keeps the first `used` elements.
 template <typename T>
 T* buf_keep(ms_ctx* c, const char* name, size_t count, size_t used) {

@@ -150,3 +150,20 @@ def test_connect_rejects_mismatched_critical_list(ctx):
     with pytest.raises(msc.MscError) as e:
         ctx.connect(g, (10, 9, 8), bad, cnt)
     assert e.value.status == msc.MS_ERR_INTERNAL
+
+
+def test_record_buffers_reused_across_sizes():
+    """The critical records are scattered before the host reads their count
+    whenever the context already holds record buffers; a call whose records
+    do not fit them writes nothing there and scatters again once they have
+    grown.  A fresh context sees: no buffers, then more records than they
+    hold, fewer, far fewer, more again -- each result equal to the oracle's."""
+    from paper_2009_03707_amd import msc
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = msc.Context()
+    try:
+        for dims, seed in [((12, 10, 9), 1), ((40, 38, 30), 2), ((20, 22, 18), 3), ((3, 2, 2), 4), ((44, 40, 33), 5)]:
+            check_complex(c, fields.random_field(dims, seed=seed))
+    finally:
+        c.close()

@@ -210,12 +210,13 @@ def graph_bench(torch, msc, nthreads=16):
     out["serial"] = {"threshold": thr, "cancellations": n, "s": round(time.perf_counter() - t0, 3),
                      "alive": g.counts()[0]}
     g.close()
-    g = msc.Graph.from_result(ctx, r, (256, 256, 256), nthreads=nthreads)
-    t0 = time.perf_counter()
-    n = g.simplify(thr, msc.MS_SIMPLIFY_SUBGRID, 2)
-    out["subgrid2"] = {"threshold": thr, "cancellations": n, "s": round(time.perf_counter() - t0, 3),
-                       "alive": g.counts()[0]}
-    g.close()
+    for k in (2, nthreads):  # the paper's two subgrids per round, and one per host thread
+        g = msc.Graph.from_result(ctx, r, (256, 256, 256), nthreads=nthreads)
+        t0 = time.perf_counter()
+        n = g.simplify(thr, msc.MS_SIMPLIFY_SUBGRID, k)
+        out[f"subgrid{k}"] = {"threshold": thr, "cancellations": n, "s": round(time.perf_counter() - t0, 3),
+                              "alive": g.counts()[0]}
+        g.close()
     ctx.close()
     return out
 

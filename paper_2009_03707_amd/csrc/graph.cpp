@@ -116,10 +116,12 @@ struct ms_graph {
         return a ? a->mult : 0;
     }
 
-    // Cancels (u, l); appends the arcs it creates or changes to `touched`.
+    // Cancels (u, l); appends the arcs it creates or changes to `touched`
+    // (U and D: the caller's scratch lists).
     void cancel(int64_t u, int64_t l, std::vector<std::pair<int64_t, int64_t>>& touched,
-                std::vector<ms_cancellation>& out) {
-        std::vector<Arc> U, D;
+                std::vector<ms_cancellation>& out, std::vector<Arc>& U, std::vector<Arc>& D) {
+        U.clear();
+        D.clear();
         for (const Arc& a : up[l])
             if (alive[a.nbr] && a.nbr != u) U.push_back(a);
         for (const Arc& a : down[u])
@@ -137,33 +139,46 @@ struct ms_graph {
     }
 
     // Serial persistence-ordered cancellation restricted to the nodes for
-    // which `in(node)` holds.
+    // which `in(node)` holds.  Candidates are the live arcs of multiplicity
+    // 1 below the threshold; they come from `seeds` (or, without seeds, from
+    // every node's descending arcs) and from the arcs each cancellation
+    // creates or changes.  A candidate with an end outside `in` is appended
+    // to `deferred` (when given) instead of being queued.  A candidate that
+    // fails otherwise can never become one again: persistence is fixed, dead
+    // nodes stay dead and multiplicities only grow.
     template <typename In>
-    void run_serial(double thr, In&& in, std::vector<ms_cancellation>& out, const std::vector<int64_t>* nodes) {
+    void run_serial(double thr, In&& in, std::vector<ms_cancellation>& out,
+                    const std::vector<std::pair<int64_t, int64_t>>* seeds,
+                    std::vector<std::pair<int64_t, int64_t>>* deferred) {
         MinQueue q;
         auto consider = [&](int64_t u, int64_t l) {
-            if (!alive[u] || !alive[l] || !in(u) || !in(l)) return;
+            if (!alive[u] || !alive[l]) return;
             double p = pers(u, l);
             if (!(p < thr)) return;
             if (mult(u, l) != 1) return;
+            if (!in(u) || !in(l)) {
+                if (deferred) deferred->emplace_back(u, l);
+                return;
+            }
             q.push(Cand{p, u, l});
         };
-        auto seed = [&](int64_t u) {
-            if (index[u] == 0 || !alive[u] || !in(u)) return;
-            for (const Arc& a : down[u])
-                if (a.mult == 1) consider(u, a.nbr);
-        };
-        if (nodes)
-            for (int64_t u : *nodes) seed(u);
-        else
-            for (int64_t u = 0; u < n(); u++) seed(u);
+        if (seeds) {
+            for (const auto& c : *seeds) consider(c.first, c.second);
+        } else {
+            for (int64_t u = 0; u < n(); u++) {
+                if (index[u] == 0 || !alive[u]) continue;
+                for (const Arc& a : down[u])
+                    if (a.mult == 1) consider(u, a.nbr);
+            }
+        }
         std::vector<std::pair<int64_t, int64_t>> touched;
+        std::vector<Arc> U, D;
         while (!q.empty()) {
             Cand c = q.top();
             q.pop();
             if (!alive[c.upper] || !alive[c.lower] || mult(c.upper, c.lower) != 1) continue;
             touched.clear();
-            cancel(c.upper, c.lower, touched, out);
+            cancel(c.upper, c.lower, touched, out, U, D);
             for (auto& t : touched) consider(t.first, t.second);
         }
     }
@@ -177,48 +192,109 @@ struct ms_graph {
         return (int64_t)(2 * c + ((k >> axis) & 1u));
     }
 
+    // The candidates of the whole graph: its live arcs of multiplicity 1
+    // below the threshold, gathered in parallel.
+    std::vector<std::pair<int64_t, int64_t>> candidates(double thr, int nthreads) const {
+        const int64_t N = n();
+        const int nt = nthreads < 1 ? 1 : nthreads;
+        std::vector<std::vector<std::pair<int64_t, int64_t>>> part(nt);
+        const int64_t per = (N + nt - 1) / nt;
+        std::vector<std::thread> th;
+        for (int t = 0; t < nt; t++)
+            th.emplace_back([&, t] {
+                const int64_t a = (int64_t)t * per, b = std::min(N, a + per);
+                for (int64_t u = a; u < b; u++) {
+                    if (index[u] == 0 || !alive[u]) continue;
+                    for (const Arc& x : down[u])
+                        if (x.mult == 1 && alive[x.nbr] && pers(u, x.nbr) < thr) part[t].emplace_back(u, x.nbr);
+                }
+            });
+        for (auto& x : th) x.join();
+        std::vector<std::pair<int64_t, int64_t>> all;
+        for (auto& p : part) all.insert(all.end(), p.begin(), p.end());
+        return all;
+    }
+
+    // Rounds of the subdivision schedule.  Only candidates are carried from
+    // round to round (the pool): a round hands every pooled candidate whose
+    // ends lie unfrozen in one slab to that slab's thread, keeps the others,
+    // and takes back what the threads deferred -- so no round rescans the
+    // graph, and the final serial round starts from the pool.  A node's slab
+    // follows from its cell; whether it is frozen (a live arc to another
+    // slab at the start of the round) is worked out when first asked, from
+    // a copy of the live flags taken at the start of the round.  That gives
+    // the same answer whenever it is asked: a thread only ever changes the
+    // arc lists of nodes in its own slab (the neighbours of an unfrozen pair
+    // share its slab), and the arcs it adds join nodes of that slab.
     void run_subgrid(double thr, int k, int nthreads) {
         const int64_t N = n();
-        std::vector<int32_t> sub(N);
-        std::vector<uint8_t> frozen(N);
+        std::vector<uint8_t> snap(N), fz(N);  // fz: 0 not yet known, 1 unfrozen, 2 frozen
+        std::vector<std::pair<int64_t, int64_t>> pool = candidates(thr, nthreads);
+        std::vector<uint32_t> rc[3];  // refined coordinates of the nodes' cells
+        for (int axis = 0; axis < 3; axis++) {
+            rc[axis].resize(N);
+            parallel_for(N, nthreads, [&](int64_t a, int64_t b) {
+                for (int64_t i = a; i < b; i++) rc[axis][i] = (uint32_t)coord(i, axis);
+            });
+        }
+        std::vector<int32_t> slab_of;  // slab of each refined coordinate along the round's axis
         for (int pass = 0; pass < 2; pass++)
             for (int axis = 0; axis < 3; axis++) {
                 const int64_t len = 2 * dims[axis] - 1;
                 if (len < 2 * k) continue;  // too thin to slice
+                if (pool.empty()) break;
                 const int64_t off = pass == 0 ? 0 : len / (2 * k);
-                parallel_for(N, nthreads, [&](int64_t a, int64_t b) {
-                    for (int64_t i = a; i < b; i++) {
-                        int64_t c = ((coord(i, axis) - off) % len + len) % len;
-                        sub[i] = (int32_t)(c * k / len);
-                    }
-                });
-                // frozen: an end of a live arc between different slabs
-                parallel_for(N, nthreads, [&](int64_t a, int64_t b) {
-                    for (int64_t i = a; i < b; i++) {
-                        uint8_t fz = 0;
-                        if (alive[i]) {
-                            for (const Arc& x : down[i])
-                                if (alive[x.nbr] && sub[x.nbr] != sub[i]) fz = 1;
-                            for (const Arc& x : up[i])
-                                if (alive[x.nbr] && sub[x.nbr] != sub[i]) fz = 1;
+                slab_of.resize((size_t)len);
+                for (int64_t c = 0; c < len; c++) slab_of[c] = (int32_t)(((c - off + len) % len) * k / len);
+                const uint32_t* rca = rc[axis].data();
+                const int32_t* so = slab_of.data();
+                auto sub = [rca, so](int64_t x) -> int32_t { return so[rca[x]]; };
+                auto frozen = [&](int64_t x) -> bool {
+                    uint8_t& f = fz[x];
+                    if (f) return f == 2;
+                    const int32_t sx = sub(x);
+                    bool z = false;
+                    for (const Arc& a : down[x])
+                        if (snap[a.nbr] && sub(a.nbr) != sx) {
+                            z = true;
+                            break;
                         }
-                        frozen[i] = fz;
-                    }
-                });
-                std::vector<std::vector<int64_t>> members(k);
-                for (int64_t i = 0; i < N; i++)
-                    if (alive[i] && !frozen[i]) members[sub[i]].push_back(i);
+                    if (!z)
+                        for (const Arc& a : up[x])
+                            if (snap[a.nbr] && sub(a.nbr) != sx) {
+                                z = true;
+                                break;
+                            }
+                    f = z ? 2 : 1;
+                    return z;
+                };
+                memcpy(snap.data(), alive.data(), (size_t)N);
+                memset(fz.data(), 0, (size_t)N);
+                std::vector<std::vector<std::pair<int64_t, int64_t>>> seeds(k), deferred(k);
+                std::vector<std::pair<int64_t, int64_t>> kept;
+                for (const auto& c : pool) {
+                    const int64_t u = c.first, l = c.second;
+                    if (!alive[u] || !alive[l]) continue;
+                    const int32_t su = sub(u);
+                    if (su == sub(l) && !frozen(u) && !frozen(l)) seeds[su].push_back(c);
+                    else kept.push_back(c);
+                }
                 std::vector<std::vector<ms_cancellation>> logs(k);
                 std::vector<std::thread> th;
-                for (int s = 0; s < k; s++)
+                for (int s = 0; s < k; s++) {
+                    if (seeds[s].empty()) continue;
                     th.emplace_back([&, s] {
                         run_serial(
-                            thr, [&](int64_t x) { return sub[x] == s && !frozen[x]; }, logs[s], &members[s]);
+                            thr, [&](int64_t x) { return sub(x) == s && !frozen(x); }, logs[s], &seeds[s],
+                            &deferred[s]);
                     });
+                }
                 for (auto& t : th) t.join();
                 for (auto& l : logs) log.insert(log.end(), l.begin(), l.end());
+                pool.swap(kept);
+                for (auto& d : deferred) pool.insert(pool.end(), d.begin(), d.end());
             }
-        run_serial(thr, [](int64_t) { return true; }, log, nullptr);
+        run_serial(thr, [](int64_t) { return true; }, log, &pool, nullptr);
     }
 };
 
@@ -360,7 +436,7 @@ ms_status ms_graph_simplify(ms_graph* g, double threshold, int schedule, int nth
     const size_t before = g->log.size();
     try {
         if (schedule == MS_SIMPLIFY_SERIAL || nthreads == 1)
-            g->run_serial(threshold, [](int64_t) { return true; }, g->log, nullptr);
+            g->run_serial(threshold, [](int64_t) { return true; }, g->log, nullptr, nullptr);
         else
             g->run_subgrid(threshold, nthreads, nthreads);
     } catch (const std::exception& e) {

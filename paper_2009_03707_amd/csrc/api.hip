@@ -229,6 +229,8 @@ void ms_ctx_destroy(ms_ctx* ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto& kv : ctx->bufs) dev_free(ctx, kv.second.p, kv.second.cap);
     if (ctx->h_small) (void)hipHostFree(ctx->h_small);
+    for (void* p : ctx->h_stage)
+        if (p) (void)hipHostFree(p);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto& e : ctx->rank_ev) (void)hipEventDestroy(e);
@@ -243,6 +245,11 @@ ms_status ms_ctx_release(ms_ctx* ctx) {
     for (auto& kv : ctx->bufs) dev_free(ctx, kv.second.p, kv.second.cap);
     ctx->bufs.clear();
     ctx->ws_bytes = 0;
+    for (void*& p : ctx->h_stage) {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+    }
+    ctx->h_stage_bytes = 0;
     return MS_OK;
 }
 

@@ -15,9 +15,15 @@
 // (8 * vertex + nibble, vertex = x + nx (y + ny z)) so the field may exceed
 // the 2^29 vertices of the in-HBM entry points.
 //
-// Pipelining: two device field buffers and two pinned staging buffers; the
-// slab after the current one is copied into staging on the host and sent on
-// a copy stream while the current slab is computed on the context's stream.
+// Pipelining: two device field buffers and two pinned staging buffers (kept
+// by the context); the slab after the current one is copied into staging by
+// host threads and sent on a copy stream while the current slab is computed
+// on the context's stream.  Each slab's records are widened to 64 bits on
+// the device and copied back as they are (one chunk per slab); once all
+// slabs are done, host threads gather the chunks into the index-major output.
+#include <algorithm>
+#include <memory>
+#include <thread>
 #include <string.h>
 
 #include <vector>
@@ -39,11 +45,39 @@ void flag_clear(ms_ctx* c, int* d_err);
 
 namespace {
 
-struct Pinned {
-    void* p = nullptr;
-    ~Pinned() {
-        if (p) (void)hipHostFree(p);
+// ids widened to 64 bits and moved to the slab's place in the field
+__global__ void k_widen(const uint32_t* __restrict__ id, const uint32_t* __restrict__ vmax, uint64_t n, uint64_t vbase,
+                        uint64_t* __restrict__ id64, uint64_t* __restrict__ vmax64) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    id64[i] = 8 * vbase + id[i];
+    vmax64[i] = vbase + vmax[i];
+}
+
+// memcpy split over host threads
+void par_copy(void* dst, const void* src, size_t bytes) {
+    constexpr size_t MIN_PART = (size_t)8 << 20;
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const size_t parts = std::min<size_t>(hw, std::max<size_t>(1, bytes / MIN_PART));
+    if (parts <= 1) {
+        memcpy(dst, src, bytes);
+        return;
     }
+    const size_t per = (bytes + parts - 1) / parts;
+    std::vector<std::thread> th;
+    for (size_t t = 0; t < parts; t++) {
+        const size_t a = t * per, b = std::min(bytes, a + per);
+        if (a >= b) break;
+        th.emplace_back([=] { memcpy((char*)dst + a, (const char*)src + a, b - a); });
+    }
+    for (auto& x : th) x.join();
+}
+
+// one slab's records, as copied back: per index, count; ids, vertices, values
+struct Chunk {
+    int64_t cnt[4] = {0, 0, 0, 0};
+    std::unique_ptr<uint64_t[]> id, vmax;
+    std::unique_ptr<float[]> value;
 };
 
 struct Ev {
@@ -87,13 +121,23 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
         hipStream_t cs = ctx->stream;
         Stream xs;
         check(ctx, hipStreamCreateWithFlags(&xs.s, hipStreamNonBlocking), "stream create");
-        Pinned stage[2];
+        if (ctx->h_stage_bytes < fbytes) {
+            check(ctx, hipStreamSynchronize(cs), "stream synchronize");
+            for (void*& p : ctx->h_stage) {
+                if (p) (void)hipHostFree(p);
+                p = nullptr;
+            }
+            ctx->h_stage_bytes = 0;
+            for (void*& p : ctx->h_stage)
+                if (hipHostMalloc(&p, fbytes, hipHostMallocDefault) != hipSuccess) {
+                    (void)hipGetLastError();
+                    p = nullptr;
+                    fail(ctx, MS_ERR_OOM, "pinned staging allocation failed");
+                }
+            ctx->h_stage_bytes = fbytes;
+        }
         Ev ev_h2d[2], ev_done[2];
         for (int b = 0; b < 2; b++) {
-            if (hipHostMalloc(&stage[b].p, fbytes, hipHostMallocDefault) != hipSuccess) {
-                (void)hipGetLastError();
-                fail(ctx, MS_ERR_OOM, "pinned staging allocation failed");
-            }
             check(ctx, hipEventCreateWithFlags(&ev_h2d[b].e, hipEventDisableTiming), "event create");
             check(ctx, hipEventCreateWithFlags(&ev_done[b].e, hipEventDisableTiming), "event create");
         }
@@ -103,13 +147,8 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
         uint64_t* tmp = buf<uint64_t>(ctx, "ooc.tmp", crit_tmp_elems((uint64_t)(slab * nxy)) + 1);
         int* d_err = buf<int>(ctx, "ooc.err", 4);
 
-        std::vector<uint64_t> rid[4], rvmax[4];
-        std::vector<float> rval[4];
-        std::vector<uint32_t> hid, hvm;
-        std::vector<uint8_t> hix;
-        std::vector<float> hval;
-
         const int64_t nslab = (nz + slab - 1) / slab;
+        std::vector<Chunk> chunks((size_t)nslab);
         auto rows_of = [&](int64_t i, int64_t& z0, int64_t& z1, int64_t& zs, int64_t& ze) {
             z0 = i * slab;
             z1 = z0 + slab < nz ? z0 + slab : nz;
@@ -124,9 +163,9 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
             const int b = (int)(i & 1);
             check(ctx, hipEventSynchronize(ev_h2d[b].e), "event synchronize");  // staging b free
             const size_t bytes = (size_t)((ze - zs) * nxy) * sizeof(float);
-            memcpy(stage[b].p, h_f + zs * nxy, bytes);
+            par_copy(ctx->h_stage[b], h_f + zs * nxy, bytes);
             check(ctx, hipStreamWaitEvent(xs.s, ev_done[b].e, 0), "stream wait");
-            check(ctx, hipMemcpyAsync(d_f[b], stage[b].p, bytes, hipMemcpyHostToDevice, xs.s), "copy to device");
+            check(ctx, hipMemcpyAsync(d_f[b], ctx->h_stage[b], bytes, hipMemcpyHostToDevice, xs.s), "copy to device");
             check(ctx, hipEventRecord(ev_h2d[b].e, xs.s), "event record");
         };
         for (int b = 0; b < 2; b++) {  // events start signalled
@@ -151,8 +190,8 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
             const Grid gi = Grid::make(nx, ny, z1 - z0);
             uint64_t* d_tot = nullptr;
             check(ctx, launch_crit_count(d_grad + off, single(gi), tmp, &d_tot, cs), "critical count launch");
-            check(ctx, hipMemcpyAsync(ctx->h_small, d_tot, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, cs), "readback");
-            check(ctx, hipMemcpyAsync(ctx->h_small + 8, d_err, sizeof(int), hipMemcpyDeviceToHost, cs), "readback");
+            check(ctx, launch_publish(d_tot, 8, ctx->h_small_dev, cs), "readback");
+            check(ctx, launch_publish((const uint64_t*)d_err, 1, ctx->h_small_dev + 8, cs), "readback");
             check(ctx, hipStreamSynchronize(cs), "stream synchronize");
             int flag = 0;
             memcpy(&flag, ctx->h_small + 8, sizeof(int));
@@ -161,69 +200,85 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
                 check(ctx, hipEventRecord(ev_done[b].e, cs), "event record");
                 break;
             }
-            int64_t cnt[4], n = 0;
+            Chunk& ch = chunks[(size_t)i];
+            int64_t n = 0;
             for (int k = 0; k < 4; k++) {
-                cnt[k] = (int64_t)ctx->h_small[k];
-                n += cnt[k];
+                ch.cnt[k] = (int64_t)ctx->h_small[k];
+                n += ch.cnt[k];
             }
             // the slab's records (grow-only buffers, sized by this slab's count)
             uint32_t* d_id = buf<uint32_t>(ctx, "ooc.id", (size_t)n);
             uint8_t* d_index = buf<uint8_t>(ctx, "ooc.index", (size_t)n);
             float* d_value = buf<float>(ctx, "ooc.value", (size_t)n);
             uint32_t* d_vmax = buf<uint32_t>(ctx, "ooc.vmax", (size_t)n);
-            if (n > 0)
+            uint64_t* d_id64 = buf<uint64_t>(ctx, "ooc.id64", (size_t)n);
+            uint64_t* d_vmax64 = buf<uint64_t>(ctx, "ooc.vmax64", (size_t)n);
+            if (n > 0) {
                 check(ctx, launch_crit_scatter(d_f[b] + off, nullptr, d_grad + off, single(gi), tmp, d_id, d_index,
                                                d_value, d_vmax, cs),
                       "critical scatter launch");
+                hipLaunchKernelGGL(k_widen, dim3(grid_blocks((uint64_t)n, 256)), dim3(256), 0, cs, (const uint32_t*)d_id,
+                                   (const uint32_t*)d_vmax, (uint64_t)n, (uint64_t)z0 * (uint64_t)nxy, d_id64, d_vmax64);
+                check(ctx, hipGetLastError(), "widen launch");
+            }
             check(ctx, hipEventRecord(ev_done[b].e, cs), "event record");  // d_f[b] may be refilled
             if (h_grad)
                 check(ctx, hipMemcpyAsync(h_grad + z0 * nxy, d_grad + off, (size_t)((z1 - z0) * nxy) * sizeof(uint32_t),
                                           hipMemcpyDeviceToHost, cs),
                       "copy to host");
-            hid.resize((size_t)n);
-            hvm.resize((size_t)n);
-            hval.resize((size_t)n);
             if (n > 0) {
-                check(ctx, hipMemcpyAsync(hid.data(), d_id, 4 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
-                check(ctx, hipMemcpyAsync(hvm.data(), d_vmax, 4 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
-                check(ctx, hipMemcpyAsync(hval.data(), d_value, 4 * (size_t)n, hipMemcpyDeviceToHost, cs),
+                ch.id.reset(new uint64_t[(size_t)n]);
+                ch.vmax.reset(new uint64_t[(size_t)n]);
+                ch.value.reset(new float[(size_t)n]);
+                check(ctx, hipMemcpyAsync(ch.id.get(), d_id64, 8 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
+                check(ctx, hipMemcpyAsync(ch.vmax.get(), d_vmax64, 8 * (size_t)n, hipMemcpyDeviceToHost, cs),
+                      "copy to host");
+                check(ctx, hipMemcpyAsync(ch.value.get(), d_value, 4 * (size_t)n, hipMemcpyDeviceToHost, cs),
                       "copy to host");
             }
             check(ctx, hipStreamSynchronize(cs), "stream synchronize");
-            // slab-local ids and vertices -> global ones; the slab's list is
-            // sorted by (index, id) and slabs come in id order, so appending
-            // per index keeps the global order
-            const uint64_t vbase = (uint64_t)z0 * (uint64_t)nxy;
-            int64_t p = 0;
-            for (int k = 0; k < 4; k++) {
-                for (int64_t j = 0; j < cnt[k]; j++, p++) {
-                    rid[k].push_back(8 * vbase + hid[(size_t)p]);
-                    rvmax[k].push_back(vbase + hvm[(size_t)p]);
-                    rval[k].push_back(hval[(size_t)p]);
-                }
-            }
         }
         check(ctx, hipStreamSynchronize(xs.s), "stream synchronize");
         if (nonfinite) fail(ctx, MS_ERR_NONFINITE, "the field contains NaN or infinite values");
         int64_t total = 0;
         for (int k = 0; k < 4; k++) {
-            h_count[k] = (int64_t)rid[k].size();
+            h_count[k] = 0;
+            for (const Chunk& ch : chunks) h_count[k] += ch.cnt[k];
             total += h_count[k];
         }
         if (!out) return MS_OK;
         if (total > out->capacity) fail(ctx, MS_ERR_CAPACITY, "critical output capacity too small");
         if (total > 0 && (!out->id || !out->index || !out->value || !out->vmax))
             fail(ctx, MS_ERR_INVALID_ARG, "null critical output array");
-        int64_t p = 0;
-        for (int k = 0; k < 4; k++) {
-            const size_t m = rid[k].size();
-            if (m == 0) continue;
-            memcpy(out->id + p, rid[k].data(), 8 * m);
-            memcpy(out->vmax + p, rvmax[k].data(), 8 * m);
-            memcpy(out->value + p, rval[k].data(), 4 * m);
-            memset(out->index + p, k, m);
-            p += (int64_t)m;
-        }
+        // the slabs' lists are sorted by (index, id) and the slabs come in id
+        // order, so index k's records are the slabs' index-k runs in slab order
+        struct Piece {
+            const Chunk* ch;
+            int64_t src, dst, n;
+            int k;
+        };
+        std::vector<Piece> pieces;
+        int64_t dst = 0;
+        for (int k = 0; k < 4; k++)
+            for (const Chunk& ch : chunks) {
+                int64_t src = 0;
+                for (int q = 0; q < k; q++) src += ch.cnt[q];
+                if (ch.cnt[k] > 0) pieces.push_back(Piece{&ch, src, dst, ch.cnt[k], k});
+                dst += ch.cnt[k];
+            }
+        const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> th;
+        for (unsigned t = 0; t < hw; t++)
+            th.emplace_back([&, t] {
+                for (size_t j = t; j < pieces.size(); j += hw) {
+                    const Piece& pc = pieces[j];
+                    memcpy(out->id + pc.dst, pc.ch->id.get() + pc.src, 8 * (size_t)pc.n);
+                    memcpy(out->vmax + pc.dst, pc.ch->vmax.get() + pc.src, 8 * (size_t)pc.n);
+                    memcpy(out->value + pc.dst, pc.ch->value.get() + pc.src, 4 * (size_t)pc.n);
+                    memset(out->index + pc.dst, pc.k, (size_t)pc.n);
+                }
+            });
+        for (auto& x : th) x.join();
     } catch (const Fail& e) {
         return e.st;
     } catch (const std::bad_alloc&) {

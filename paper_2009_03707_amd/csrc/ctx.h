@@ -30,6 +30,8 @@ struct ms_ctx {
         size_t cap = 0;
     };
     std::map<std::string, Buf> bufs;
+    void* h_stage[2] = {nullptr, nullptr};  // pinned staging of the out-of-core field slabs
+    size_t h_stage_bytes = 0;
     uint64_t* h_small = nullptr;  // pinned, coherent host scratch for small readbacks
     uint64_t* h_small_dev = nullptr;  // the same memory as the device addresses it
     // stage timing (events at stage boundaries of ms_complex)

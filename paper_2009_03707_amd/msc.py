@@ -315,15 +315,20 @@ class Context:
         cnt = (C.c_int64 * 4)()
         grad = np.empty(f.shape, np.uint32) if want_grad else None
         gp = grad.ctypes.data if want_grad else None
-        st = lib().ms_gradient_critical_chunked(self._h, f.ctypes.data, Dims(nx, ny, nz), int(slab), gp, None, cnt)
-        self._raise(st, "ms_gradient_critical_chunked (count)")
-        n = int(sum(cnt))
-        arrs = (np.empty(max(n, 1), np.uint64), np.empty(max(n, 1), np.uint8), np.empty(max(n, 1), np.float32),
-                np.empty(max(n, 1), np.uint64))
-        cr = Crit64(*[a.ctypes.data for a in arrs], n)
-        st = lib().ms_gradient_critical_chunked(self._h, f.ctypes.data, Dims(nx, ny, nz), int(slab), None,
-                                                C.byref(cr), cnt)
+        # room for one record per vertex first (only the pages written are
+        # touched); a denser field reports its counts and is run again
+        cap = max(int(f.size), 1)
+        for attempt in range(2):
+            arrs = (np.empty(cap, np.uint64), np.empty(cap, np.uint8), np.empty(cap, np.float32),
+                    np.empty(cap, np.uint64))
+            cr = Crit64(*[a.ctypes.data for a in arrs], cap)
+            st = lib().ms_gradient_critical_chunked(self._h, f.ctypes.data, Dims(nx, ny, nz), int(slab), gp,
+                                                    C.byref(cr), cnt)
+            if st != MS_ERR_CAPACITY or attempt:
+                break
+            cap = max(int(sum(cnt)), 1)
         self._raise(st, "ms_gradient_critical_chunked")
+        n = int(sum(cnt))
         return (grad,) + tuple(a[:n] for a in arrs) + (list(cnt),)
 
     def connect(self, grad: torch.Tensor, dims, crit_id: torch.Tensor, counts) -> "Arcs":

@@ -102,9 +102,9 @@ ms_status ms_ctx_set_stream(ms_ctx* ctx, void* stream);
 /* Text describing the last non-OK status returned on this context. */
 const char* ms_last_error(const ms_ctx* ctx);
 /* Frees the context's workspace -- its device buffers and the pinned host
- * staging of ms_gradient_critical_chunked (both are reallocated on demand by
- * the next call); invalidates every context-owned output.  Synchronises the
- * stream. */
+ * memory of ms_gradient_critical_chunked (slab staging and records; all are
+ * reallocated on demand by the next call); invalidates every context-owned
+ * output.  Synchronises the stream. */
 ms_status ms_ctx_release(ms_ctx* ctx);
 
 /* Context options (ms_ctx_set_option). */
@@ -217,9 +217,10 @@ typedef struct {
  * and its rows are exact.  The results equal ms_gradient / ms_critical on
  * the whole field (ids widened to 64 bits).  Host-to-device copies of the
  * next slab overlap the current slab's kernels; the slabs' records are held
- * in host memory until the end, so a call with too small an `out` costs a
- * whole pass (size `out` generously: untouched pages cost nothing).  The
- * pinned staging (two slabs plus halo) is kept by the context.
+ * in pinned host memory until the end, so a call with too small an `out`
+ * costs a whole pass (size `out` generously: untouched pages cost nothing).
+ * The pinned memory (two slabs plus halo of staging, and about 20 bytes per
+ * critical cell of records) is kept by the context for later calls.
  *   h_f     : host, nx*ny*nz float32 (layout as everywhere).
  *   h_grad  : host, nx*ny*nz uint32 gradient words, or NULL (not written).
  *   out     : host arrays sorted by (index, id), or NULL (counts only).

@@ -19,8 +19,9 @@
 // by the context); the slab after the current one is copied into staging by
 // host threads and sent on a copy stream while the current slab is computed
 // on the context's stream.  Each slab's records are widened to 64 bits on
-// the device and copied back as they are (one chunk per slab); once all
-// slabs are done, host threads gather the chunks into the index-major output.
+// the device and copied back as they are into pinned blocks the context
+// keeps (one chunk per slab); once all slabs are done, host threads gather
+// the chunks into the index-major output.
 #include <algorithm>
 #include <memory>
 #include <thread>
@@ -76,8 +77,37 @@ void par_copy(void* dst, const void* src, size_t bytes) {
 // one slab's records, as copied back: per index, count; ids, vertices, values
 struct Chunk {
     int64_t cnt[4] = {0, 0, 0, 0};
-    std::unique_ptr<uint64_t[]> id, vmax;
-    std::unique_ptr<float[]> value;
+    const uint64_t* id = nullptr;
+    const uint64_t* vmax = nullptr;
+    const float* value = nullptr;
+};
+
+// Bump allocation of the slabs' records in the context's pinned blocks
+// (kept and reused by later calls; a block is added when none has room).
+struct RecordArena {
+    ms_ctx* c;
+    size_t blk = 0, used = 0;
+    void* take(size_t bytes) {
+        bytes = (bytes + 255) & ~(size_t)255;
+        while (blk < c->h_recs.size() && used + bytes > c->h_recs[blk].second) {
+            blk++;
+            used = 0;
+        }
+        if (blk == c->h_recs.size()) {
+            const size_t prev = c->h_recs.empty() ? 0 : c->h_recs.back().second;
+            const size_t want = std::max({bytes, 2 * prev, (size_t)256 << 20});
+            void* p = nullptr;
+            if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                fail(c, MS_ERR_OOM, "pinned record allocation failed");
+            }
+            c->h_recs.emplace_back(p, want);
+            used = 0;
+        }
+        void* p = (char*)c->h_recs[blk].first + used;
+        used += bytes;
+        return p;
+    }
 };
 
 struct Ev {
@@ -149,6 +179,7 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
 
         const int64_t nslab = (nz + slab - 1) / slab;
         std::vector<Chunk> chunks((size_t)nslab);
+        RecordArena arena{ctx};
         auto rows_of = [&](int64_t i, int64_t& z0, int64_t& z1, int64_t& zs, int64_t& ze) {
             z0 = i * slab;
             z1 = z0 + slab < nz ? z0 + slab : nz;
@@ -227,14 +258,15 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
                                           hipMemcpyDeviceToHost, cs),
                       "copy to host");
             if (n > 0) {
-                ch.id.reset(new uint64_t[(size_t)n]);
-                ch.vmax.reset(new uint64_t[(size_t)n]);
-                ch.value.reset(new float[(size_t)n]);
-                check(ctx, hipMemcpyAsync(ch.id.get(), d_id64, 8 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
-                check(ctx, hipMemcpyAsync(ch.vmax.get(), d_vmax64, 8 * (size_t)n, hipMemcpyDeviceToHost, cs),
-                      "copy to host");
-                check(ctx, hipMemcpyAsync(ch.value.get(), d_value, 4 * (size_t)n, hipMemcpyDeviceToHost, cs),
-                      "copy to host");
+                uint64_t* hid = (uint64_t*)arena.take(8 * (size_t)n);
+                uint64_t* hvm = (uint64_t*)arena.take(8 * (size_t)n);
+                float* hval = (float*)arena.take(4 * (size_t)n);
+                ch.id = hid;
+                ch.vmax = hvm;
+                ch.value = hval;
+                check(ctx, hipMemcpyAsync(hid, d_id64, 8 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
+                check(ctx, hipMemcpyAsync(hvm, d_vmax64, 8 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
+                check(ctx, hipMemcpyAsync(hval, d_value, 4 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
             }
             check(ctx, hipStreamSynchronize(cs), "stream synchronize");
         }
@@ -272,9 +304,9 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
             th.emplace_back([&, t] {
                 for (size_t j = t; j < pieces.size(); j += hw) {
                     const Piece& pc = pieces[j];
-                    memcpy(out->id + pc.dst, pc.ch->id.get() + pc.src, 8 * (size_t)pc.n);
-                    memcpy(out->vmax + pc.dst, pc.ch->vmax.get() + pc.src, 8 * (size_t)pc.n);
-                    memcpy(out->value + pc.dst, pc.ch->value.get() + pc.src, 4 * (size_t)pc.n);
+                    memcpy(out->id + pc.dst, pc.ch->id + pc.src, 8 * (size_t)pc.n);
+                    memcpy(out->vmax + pc.dst, pc.ch->vmax + pc.src, 8 * (size_t)pc.n);
+                    memcpy(out->value + pc.dst, pc.ch->value + pc.src, 4 * (size_t)pc.n);
                     memset(out->index + pc.dst, pc.k, (size_t)pc.n);
                 }
             });

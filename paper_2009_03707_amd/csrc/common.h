@@ -109,21 +109,26 @@ __device__ inline T load_global(const T* p, uint64_t i) {
 // Cell one refined step from (w, k) along `axis` with sign `s` (+1 / -1).
 // Returns false when the step leaves the grid.  `c` holds the coordinates of
 // vertex w.
+// a[i] of a three-element array by selects, so that an index known only at
+// run time does not force the array out of registers
+__device__ inline uint32_t pick3(const uint32_t a[3], uint32_t i) { return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]); }
+
 __device__ inline bool cell_step(const Grid& g, uint32_t w, uint32_t k, const uint32_t c[3], int axis, int s,
                                  uint32_t& w2, uint32_t& k2) {
     uint32_t bit = 1u << axis;
+    const uint32_t st = pick3(g.stride, (uint32_t)axis);
     if (k & bit) {
         k2 = k & ~bit;
-        w2 = (s > 0) ? w + g.stride[axis] : w;
+        w2 = (s > 0) ? w + st : w;
         return true;
     }
     k2 = k | bit;
     if (s > 0) {
-        if (c[axis] + 1 >= g.n[axis]) return false;
+        if (pick3(c, (uint32_t)axis) + 1 >= pick3(g.n, (uint32_t)axis)) return false;
         w2 = w;
     } else {
-        if (c[axis] == 0) return false;
-        w2 = w - g.stride[axis];
+        if (pick3(c, (uint32_t)axis) == 0) return false;
+        w2 = w - st;
     }
     return true;
 }

@@ -113,9 +113,12 @@ uint64_t counts_to_rowptr(ms_ctx* c, const uint32_t* cnt, uint64_t n, uint64_t* 
 // pointer of the result from the boundaries between equal keys.  Rows of
 // the output come out with ascending columns because the input entries are
 // in row-major order.  When every value fits in the bits the row ids leave
-// free (their largest is read back first), values ride in those bits;
-// otherwise they move as a separate 64-bit payload.
-void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const uint32_t* row_map = nullptr) {
+// free (their largest is read back first, unless the caller knows a bound:
+// vmax_bound), values ride in those bits; otherwise they move as a separate
+// 64-bit payload.
+constexpr uint64_t NO_BOUND = ~0ull;
+void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const uint32_t* row_map = nullptr,
+               uint64_t vmax_bound = NO_BOUND) {
     uint64_t nnz = (uint64_t)in.nnz;
     out = csr_buf(c, name, (uint64_t)in.ncols, (uint64_t)in.nrows, nnz);
     if (nnz == 0) {
@@ -133,9 +136,13 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const
     const int vbits = free_bits < c->transpose_pack ? free_bits : c->transpose_pack;
     bool packed = false;
     if (vbits >= 1) {
-        uint64_t* d_max = buf<uint64_t>(c, "tr.max", 1);
-        check(c, launch_max_u64((const uint64_t*)in.val, nnz, d_max, c->stream), "max");
-        packed = read_u64(c, d_max) < (1ull << vbits);
+        uint64_t vmax = vmax_bound;
+        if (vmax == NO_BOUND) {
+            uint64_t* d_max = buf<uint64_t>(c, "tr.max", 1);
+            check(c, launch_max_u64((const uint64_t*)in.val, nnz, d_max, c->stream), "max");
+            vmax = read_u64(c, d_max);
+        }
+        packed = vmax < (1ull << vbits);
     }
     const uint32_t* keys = nullptr;
     if (packed) {
@@ -306,10 +313,11 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     hipStream_t s = c->stream;
     ms_stats& st = out->stats;
     ms_csr At, Bt, Bst, Dt;
-    transpose(c, A, "At", At);     // junction x 1-saddle
-    transpose(c, B, "Bt", Bt);     // junction x predecessor junction
-    transpose(c, Bs, "Bst", Bst);  // 2-saddle x junction
-    transpose(c, D, "Dt", Dt);     // 2-saddle x 1-saddle
+    // minor multiplicities are at most 4: at most four paths leave a source
+    transpose(c, A, "At", At, nullptr, 4);     // junction x 1-saddle
+    transpose(c, B, "Bt", Bt, nullptr, 4);     // junction x predecessor junction
+    transpose(c, Bs, "Bst", Bst, nullptr, 4);  // 2-saddle x junction
+    transpose(c, D, "Dt", Dt, nullptr, 4);     // 2-saddle x 1-saddle
     const uint64_t nmax = (J > S2 ? J : S2) + 1;
     uint32_t* indeg = buf<uint32_t>(c, "pr.indeg", J);
     uint32_t* ready[2] = {buf<uint32_t>(c, "pr.ready0", J), buf<uint32_t>(c, "pr.ready1", J)};
@@ -438,10 +446,11 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     check(c, launch_relabel(A.col, (uint64_t)A.nnz, newid, s), "relabel");
     check(c, launch_relabel(B.col, (uint64_t)B.nnz, newid, s), "relabel");
     ms_csr At, Bt, Bst, Dt;
-    transpose(c, A, "At", At);             // junction x 1-saddle
-    transpose(c, B, "Bt", Bt, newid);      // junction x predecessor junction (sources renumbered)
-    transpose(c, Bs, "Bst", Bst, newid);   // 2-saddle x junction (renumbered)
-    transpose(c, D, "Dt", Dt);             // 2-saddle x 1-saddle
+    // minor multiplicities are at most 4: at most four paths leave a source
+    transpose(c, A, "At", At, nullptr, 4);     // junction x 1-saddle
+    transpose(c, B, "Bt", Bt, newid, 4);       // junction x predecessor junction (sources renumbered)
+    transpose(c, Bs, "Bst", Bst, newid, 4);    // 2-saddle x junction (renumbered)
+    transpose(c, D, "Dt", Dt, nullptr, 4);     // 2-saddle x 1-saddle
     // ---- levels --------------------------------------------------------------
     const uint64_t nmax = (J > S2 ? J : S2) + 1;
     uint64_t* ub = buf<uint64_t>(c, "pr.ub", nmax + 1);
@@ -588,8 +597,9 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
         if (g.nf == 1) check(c, launch_manifold_labels(Pv, Pc, g, nullptr, s), "manifold labels");
         out->min_label = Pv;
         out->max_label = Pc;
-        transpose(c, m10, "m10t", out->m10t);
-        transpose(c, m32t, "m32", out->m32);
+        // saddle-extremum multiplicities are 1 or 2
+        transpose(c, m10, "m10t", out->m10t, nullptr, 2);
+        transpose(c, m32t, "m32", out->m32, nullptr, 2);
     }
 
     mark(c, 3);

@@ -51,44 +51,8 @@ __device__ __forceinline__ bool quad_edge_partner(const Grid& g, uint32_t qw, ui
     uint32_t dq = (nq - 1u) >> 1;
     if (!((qk >> dq) & 1u)) return false;  // partner is a cube
     e.k = qk & ~(1u << dq);
-    e.w = ((nq - 1u) & 1u) ? qw : qw + g.stride[dq];
+    e.w = ((nq - 1u) & 1u) ? qw : qw + pick3(g.stride, dq);
     return true;
-}
-
-// Expands one frontier node: its out-edges (new targets into t, visited
-// bits set), out-degree and, for a node with one out-edge, that edge's step.
-__device__ __forceinline__ void bfs_node(uint32_t e, const uint32_t* __restrict__ grad, const Geo& geo,
-                                         uint32_t* __restrict__ vis, uint32_t t[4], uint32_t& nt, uint32_t& outdeg,
-                                         uint32_t& step) {
-    uint32_t w = e >> 3, k = e & 7u;
-    uint32_t a = (uint32_t)__builtin_ctz(k);
-    uint32_t fld = geo.field_of(w);
-    const Grid g = geo.grid(fld);
-    uint32_t c[3];
-    g.coords(w - geo.base(fld), c);
-    CellRef v;
-    bool hv = paired_quad(g, w, k, nib_of(grad[w], k), c, a, v);
-    for (uint32_t b = 0; b < 3; b++) {
-        if (b == a) continue;
-        for (int s = -1; s <= 1; s += 2) {
-            CellRef q;
-            if (!cell_step(g, w, k, c, (int)b, s, q.w, q.k)) continue;
-            if (hv && q.w == v.w && q.k == v.k) continue;
-            uint32_t nq = nib_of(grad[q.w], q.k);
-            if (nq >= NB_CRIT) {
-                outdeg++;
-                step = (2u * b + (s > 0 ? 1u : 0u)) | (nq << 3);
-                continue;
-            }
-            CellRef e2;
-            if (!quad_edge_partner(g, q.w, q.k, nq, e2)) continue;
-            outdeg++;
-            step = (2u * b + (s > 0 ? 1u : 0u)) | (nq << 3);
-            uint32_t bit = 1u << (8u * (e2.w & 3u) + e2.k);
-            uint32_t old = atomicOr(&vis[e2.w >> 2], bit);
-            if (!(old & bit)) t[nt++] = 8u * e2.w + e2.k;
-        }
-    }
 }
 
 // A workgroup expands BFS_NPT * BT frontier nodes (thread: nodes
@@ -96,33 +60,120 @@ __device__ __forceinline__ void bfs_node(uint32_t e, const uint32_t* __restrict_
 // and junctions with one atomic on a packed counter (low 32 bits: frontier,
 // high 32 bits: junctions); appends to one counter serialise, so they are
 // kept few.
+//
+// A node's expansion is a chain of dependent memory operations (its own
+// word, then the words of its cofacet quads, then a visited-bit atomic per
+// partner edge).  A thread therefore runs its nodes in phases -- every own
+// word, then every quad word, then every atomic -- so that all of one
+// phase's loads (or atomics) are in flight together instead of one chain
+// after another.  Slot 2 b + (s > 0) holds the cofacet quad one step along
+// axis b with sign s (the edge's own axis leaves its two slots empty), so
+// that every array index is known at compile time.  The quads of an edge e
+// (other than V(e)) and the targets they lead to do not depend on the order
+// they are visited in; a node with one out-edge records that edge's step.
 constexpr int BFS_NPT = 2;
+constexpr int BFS_S = 6;  // slots: 3 axes x 2 signs
 
 __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ cur, uint64_t ncur, int level0,
                                                    const uint32_t* __restrict__ grad, Geo geo,
                                                    uint32_t* __restrict__ vis, uint32_t* __restrict__ next,
                                                    unsigned long long* __restrict__ counts,
                                                    uint32_t* __restrict__ label) {
-    uint32_t t[BFS_NPT][4];
-    uint32_t nt[BFS_NPT], isj[BFS_NPT], lab[BFS_NPT], e[BFS_NPT];
-    uint32_t snt = 0, sj = 0;
+    uint32_t e[BFS_NPT], own[BFS_NPT];
+    bool ok[BFS_NPT];
+    // phase 1: the nodes and their own words
 #pragma unroll
     for (int r = 0; r < BFS_NPT; r++) {
         const uint64_t i = ((uint64_t)blockIdx.x * BFS_NPT + r) * BT + threadIdx.x;
-        nt[r] = 0;
-        isj[r] = 0;
-        lab[r] = NOT_JUNCTION;
-        e[r] = 0;
-        if (i < ncur) {
-            uint32_t outdeg = 0, step = 0;
-            e[r] = cur[i];
-            bfs_node(e[r], grad, geo, vis, t[r], nt[r], outdeg, step);
-            isj[r] = (!level0 && outdeg > 1) ? 1u : 0u;
-            lab[r] = level0 ? 0u : (outdeg == 1 ? (SUCC_FLAG | step) : NOT_JUNCTION);
-            if (level0) e[r] = 0xFFFFFFFFu;  // 1-saddles take no label
-        } else {
-            e[r] = 0xFFFFFFFFu;
+        ok[r] = i < ncur;
+        e[r] = ok[r] ? cur[i] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < BFS_NPT; r++) own[r] = ok[r] ? grad[e[r] >> 3] : 0u;
+    // phase 2: each node's cofacet quads other than V(e) (cell ids), and their words
+    uint32_t qc[BFS_NPT][BFS_S], qword[BFS_NPT][BFS_S];
+    uint32_t qvalid[BFS_NPT];  // bit j: slot j holds a quad
+#pragma unroll
+    for (int r = 0; r < BFS_NPT; r++) {
+        qvalid[r] = 0;
+        const uint32_t w = e[r] >> 3, k = e[r] & 7u;
+        const uint32_t fld = geo.field_of(w);
+        const Grid g = geo.grid(fld);
+        uint32_t c[3];
+        g.coords(w - geo.base(fld), c);
+        const uint32_t a = ok[r] ? (uint32_t)__builtin_ctz(k) : 3u;
+        CellRef v;
+        const bool hv = ok[r] && paired_quad(g, w, k, nib_of(own[r], k), c, a, v);
+#pragma unroll
+        for (uint32_t b = 0; b < 3; b++) {
+#pragma unroll
+            for (int sp = 0; sp < 2; sp++) {
+                const int j = 2 * (int)b + sp;
+                CellRef q;
+                q.w = q.k = 0;
+                const bool ex = ok[r] && b != a && cell_step(g, w, k, c, (int)b, sp ? 1 : -1, q.w, q.k) &&
+                                !(hv && q.w == v.w && q.k == v.k);
+                qc[r][j] = 8u * q.w + q.k;
+                qvalid[r] |= (ex ? 1u : 0u) << j;
+            }
         }
+    }
+#pragma unroll
+    for (int r = 0; r < BFS_NPT; r++)
+#pragma unroll
+        for (int j = 0; j < BFS_S; j++) {
+            const bool v = (qvalid[r] >> j) & 1u;
+            const uint32_t qw = qc[r][j] >> 3;
+            qword[r][j] = !v ? 0u : (qw == (e[r] >> 3) ? own[r] : grad[qw]);
+        }
+    // phase 3: out-degrees, steps, and the visited-bit atomics of the partner edges
+    uint32_t outdeg[BFS_NPT], step[BFS_NPT], tgt[BFS_NPT][BFS_S], old[BFS_NPT][BFS_S];
+    uint32_t tvalid[BFS_NPT];
+#pragma unroll
+    for (int r = 0; r < BFS_NPT; r++) {
+        outdeg[r] = 0;
+        step[r] = 0;
+        tvalid[r] = 0;
+        const Grid g = geo.grid(geo.field_of(e[r] >> 3));
+#pragma unroll
+        for (int j = 0; j < BFS_S; j++) {
+            tgt[r][j] = 0;
+            old[r][j] = 0;
+            if (!((qvalid[r] >> j) & 1u)) continue;
+            const uint32_t qw = qc[r][j] >> 3, qk = qc[r][j] & 7u;
+            const uint32_t nq = nib_of(qword[r][j], qk);
+            if (nq >= NB_CRIT) {  // a 2-saddle
+                outdeg[r]++;
+                step[r] = (uint32_t)j | (nq << 3);
+                continue;
+            }
+            CellRef e2;
+            if (!quad_edge_partner(g, qw, qk, nq, e2)) continue;  // paired with a cube
+            outdeg[r]++;
+            step[r] = (uint32_t)j | (nq << 3);
+            tgt[r][j] = 8u * e2.w + e2.k;
+            tvalid[r] |= 1u << j;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < BFS_NPT; r++)
+#pragma unroll
+        for (int j = 0; j < BFS_S; j++)
+            if ((tvalid[r] >> j) & 1u) old[r][j] = atomicOr(&vis[tgt[r][j] >> 5], 1u << (tgt[r][j] & 31u));
+    // phase 4: new targets, junction and label decisions
+    uint32_t fresh[BFS_NPT];  // bit j: the target of slot j is new
+    uint32_t nt[BFS_NPT], isj[BFS_NPT], lab[BFS_NPT];
+    uint32_t snt = 0, sj = 0;
+#pragma unroll
+    for (int r = 0; r < BFS_NPT; r++) {
+        fresh[r] = 0;
+#pragma unroll
+        for (int j = 0; j < BFS_S; j++)
+            if (((tvalid[r] >> j) & 1u) && !(old[r][j] & (1u << (tgt[r][j] & 31u)))) fresh[r] |= 1u << j;
+        nt[r] = (uint32_t)__builtin_popcount(fresh[r]);
+        isj[r] = (ok[r] && !level0 && outdeg[r] > 1) ? 1u : 0u;
+        lab[r] = level0 ? 0u : (outdeg[r] == 1 ? (SUCC_FLAG | step[r]) : NOT_JUNCTION);
+        if (!ok[r] || level0) e[r] = 0xFFFFFFFFu;  // 1-saddles take no label
         snt += nt[r];
         sj += isj[r];
     }
@@ -136,8 +187,9 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
     uint64_t o = (base & 0xFFFFFFFFull) + (ex & 0xFFFFFFFFull);
 #pragma unroll
     for (int r = 0; r < BFS_NPT; r++) {
-        for (uint32_t q = 0; q < nt[r]; q++) next[o + q] = t[r][q];
-        o += nt[r];
+#pragma unroll
+        for (int j = 0; j < BFS_S; j++)
+            if ((fresh[r] >> j) & 1u) next[o++] = tgt[r][j];
         // a junction is marked with id 0 here; junctions are numbered in
         // cell order once the search is complete
         if (e[r] != 0xFFFFFFFFu) label[label_slot(e[r] >> 3, e[r] & 7u, geo.nv)] = isj[r] ? 0u : lab[r];

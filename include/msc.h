@@ -128,11 +128,13 @@ enum {
      * bypassed while timing is on.  Results never depend on it. */
     MS_OPT_BATCH_GRAPH = 5,
     /* Sparse transposes (the column-major copies of the arc and path
-     * matrices): when every value of a matrix fits in the bits its row ids
-     * leave free, and in at most this many bits (1..24, default 24), the
-     * values travel packed with the row ids through the radix passes; else
-     * (and always with 0) as a separate 64-bit payload.  Results never
-     * depend on it. */
+     * matrices): at most this many value bits (1..24, default 24) travel
+     * packed with the row ids through the radix passes, in the bits the row
+     * ids leave free.  A matrix whose values all fit is packed whole; the
+     * path-count matrix, whose counts can be large, is packed when at least
+     * 4 bits are free, with larger counts looked up again after the
+     * transpose; other values move as a separate 64-bit payload, as all do
+     * with 0.  Results never depend on it. */
     MS_OPT_TRANSPOSE_PACK = 6
 };
 enum {

@@ -112,13 +112,15 @@ uint64_t counts_to_rowptr(ms_ctx* c, const uint32_t* cnt, uint64_t n, uint64_t* 
 // input's rows renumbered while they are expanded) and value, and the row
 // pointer of the result from the boundaries between equal keys.  Rows of
 // the output come out with ascending columns because the input entries are
-// in row-major order.  When every value fits in the bits the row ids leave
-// free (their largest is read back first, unless the caller knows a bound:
-// vmax_bound), values ride in those bits; otherwise they move as a separate
-// 64-bit payload.
+// in row-major order.  Values ride in the bits the row ids leave free when
+// every value fits there (a bound the caller knows, vmax_bound, or else the
+// largest value, read back first); when the input's rows are sorted by
+// column (rows_sorted), larger values are packed as escapes and looked up
+// again after the sort instead; otherwise values move as a separate 64-bit
+// payload.  row_inv: the inverse of row_map (needed for escapes).
 constexpr uint64_t NO_BOUND = ~0ull;
 void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const uint32_t* row_map = nullptr,
-               uint64_t vmax_bound = NO_BOUND) {
+               uint64_t vmax_bound = NO_BOUND, bool rows_sorted = false, const uint32_t* row_inv = nullptr) {
     uint64_t nnz = (uint64_t)in.nnz;
     out = csr_buf(c, name, (uint64_t)in.ncols, (uint64_t)in.nrows, nnz);
     if (nnz == 0) {
@@ -134,15 +136,17 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const
     const int kbits = bit_width((uint64_t)in.ncols - 1);
     const int free_bits = 32 - bit_width((uint64_t)in.nrows - 1);
     const int vbits = free_bits < c->transpose_pack ? free_bits : c->transpose_pack;
-    bool packed = false;
+    bool packed = false, escapes = false;
     if (vbits >= 1) {
-        uint64_t vmax = vmax_bound;
-        if (vmax == NO_BOUND) {
+        if (vmax_bound != NO_BOUND) {
+            packed = vmax_bound < (1ull << vbits);
+        } else if (rows_sorted && vbits >= 4 && (!row_map || row_inv)) {
+            packed = escapes = true;
+        } else {
             uint64_t* d_max = buf<uint64_t>(c, "tr.max", 1);
             check(c, launch_max_u64((const uint64_t*)in.val, nnz, d_max, c->stream), "max");
-            vmax = read_u64(c, d_max);
+            packed = read_u64(c, d_max) < (1ull << vbits);
         }
-        packed = vmax < (1ull << vbits);
     }
     const uint32_t* keys = nullptr;
     if (packed) {
@@ -152,6 +156,11 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const
         const Unpack up{vbits, out.col, (uint64_t*)out.val};
         check(c, radix_transpose_packed_u32(in.col, rows, ka, va, kb, vb, nnz, kbits, tmp, up, &keys, c->stream),
               "sort");
+        if (escapes)
+            check(c, launch_escape_fix(nnz, vbits, keys, out.col, (const uint64_t*)in.rowptr, in.col,
+                                       (const uint64_t*)in.val, row_map ? row_inv : nullptr, (uint64_t*)out.val,
+                                       c->stream),
+                  "escape fix");
     } else {
         uint64_t* wa = buf<uint64_t>(c, "tr.wa", nnz);
         uint64_t* wb = buf<uint64_t>(c, "tr.wb", nnz);
@@ -301,7 +310,7 @@ void paths_power(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     prod.n = t + nD;
     Coo P = sort_merge(c, prod, S1, S2, "P");
     coo_to_csr(c, P, S1, S2, "m21t", out->m21t);
-    transpose(c, out->m21t, "m21", out->m21);
+    transpose(c, out->m21t, "m21", out->m21, nullptr, NO_BOUND, true);  // P's rows are sorted by column
 }
 
 // Path counting by column merges in topological order of the junction DAG
@@ -387,7 +396,7 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     ms_csr m21 = csr_buf(c, "m21", S2, S1, nP);
     check(c, launch_compact(ub, (const uint64_t*)m21.rowptr, S2, nP, prow, pval, m21.col, m21.val, s), "compact");
     out->m21 = m21;
-    transpose(c, out->m21, "m21t", out->m21t);
+    transpose(c, out->m21, "m21t", out->m21t, nullptr, NO_BOUND, true);  // M21 rows are sorted by column
     st.spgemm_iters = levels;
     st.nnz_astar = (int64_t)used;
     st.products = (int64_t)(used + tp);
@@ -528,7 +537,7 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     check(c, launch_entry_cols(mp, ub, hp, 0, nullptr, nullptr, (uint64_t*)m21.rowptr, s), "entry cols");
     check_err_flag(c, d_err, "path counting");
     out->m21 = m21;
-    transpose(c, out->m21, "m21t", out->m21t);
+    transpose(c, out->m21, "m21t", out->m21t, nullptr, NO_BOUND, true);  // M21 rows are sorted by column
     // exact nnz of A*: the sum of the column lengths
     uint64_t* sum = buf<uint64_t>(c, "pe.asum", 1);
     check(c, launch_sum_u32(alen, J, sum, s), "sum");

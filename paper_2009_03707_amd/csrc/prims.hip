@@ -312,6 +312,23 @@ hipError_t radix_impl(const K* keys0, const uint32_t* vals0, K* ka, uint32_t* va
 }  // namespace
 
 namespace {
+__global__ __launch_bounds__(256) void k_escape_fix(uint64_t n, uint64_t top, const uint32_t* __restrict__ keys,
+                                                    const uint32_t* __restrict__ ocol,
+                                                    const uint64_t* __restrict__ rowptr,
+                                                    const uint32_t* __restrict__ col, const uint64_t* __restrict__ val,
+                                                    const uint32_t* __restrict__ row_inv, uint64_t* __restrict__ oval) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n || oval[g] != top) return;
+    const uint32_t key = keys[g], c = ocol[g];
+    const uint32_t r = row_inv ? row_inv[c] : c;
+    uint64_t lo = rowptr[r], hi = rowptr[r + 1];  // first column >= key
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (col[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    oval[g] = (lo < rowptr[r + 1] && col[lo] == key) ? val[lo] : 0;  // found for rows holding each column once
+}
 __global__ void k_publish(const uint64_t* __restrict__ src, uint64_t n, uint64_t* __restrict__ dst) {
     for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
 }
@@ -319,6 +336,15 @@ __global__ void k_set_u64(uint64_t* __restrict__ dst, uint64_t v) {
     if (threadIdx.x == 0) *dst = v;
 }
 }  // namespace
+
+hipError_t launch_escape_fix(uint64_t n, int vb, const uint32_t* keys, const uint32_t* ocol, const uint64_t* rowptr,
+                             const uint32_t* col, const uint64_t* val, const uint32_t* row_inv, uint64_t* oval,
+                             hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_escape_fix, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, (1ull << vb) - 1ull, keys,
+                       ocol, rowptr, col, val, row_inv, oval);
+    return hipGetLastError();
+}
 
 hipError_t launch_publish(const uint64_t* src, uint64_t n, uint64_t* dst, hipStream_t s) {
     if (n == 0) return hipSuccess;

@@ -15,7 +15,7 @@ namespace {
 constexpr int BT = 256;
 
 // rows[p] = the row of entry p, or map[row] when a map is given; with val
-// set, packed as (row << vb) | val[p] (every value below 2^vb).
+// set, packed as (row << vb) | min(val[p], 2^vb - 1).
 __global__ __launch_bounds__(BT) void k_expand_rows(const uint64_t* __restrict__ rowptr, uint64_t nrows,
                                                     const uint32_t* __restrict__ map, const uint64_t* __restrict__ val,
                                                     int vb, uint32_t* __restrict__ rows) {
@@ -27,7 +27,8 @@ __global__ __launch_bounds__(BT) void k_expand_rows(const uint64_t* __restrict__
         for (uint64_t p = rowptr[r]; p < e; p++) rows[p] = v;
         return;
     }
-    for (uint64_t p = rowptr[r]; p < e; p++) rows[p] = (v << vb) | (uint32_t)val[p];
+    const uint64_t top = (1ull << vb) - 1ull;
+    for (uint64_t p = rowptr[r]; p < e; p++) rows[p] = (v << vb) | (uint32_t)(val[p] < top ? val[p] : top);
 }
 
 // *out += the sum of a[0, n) (one atomic per workgroup; *out zeroed by the caller)

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module", params=["ready", "power", "ready-chunked", "entry", "entry-pack1", "entry-wide",
-                                        "ready-pack2"])
+                                        "ready-pack2", "entry-pack4", "power-pack4"])
 def ctx(request):
     """The path-counting schedules: the ready frontier, the paper's power
     iteration and the entry ranking; "ready-chunked" sends every column
@@ -20,7 +20,9 @@ def ctx(request):
     exercised on small fields.  The transposes: "entry-pack1" packs only
     the matrices whose values are all 1 and "ready-pack2" those whose values
     are at most 3 (the others move their values as a separate payload);
-    "entry-wide" packs none."""
+    "entry-wide" packs none; "entry-pack4" and "power-pack4" pack four value
+    bits, so that every path count of 15 or more is an escape, looked up
+    again after the transpose."""
     from paper_2009_03707_amd import msc
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -30,7 +32,7 @@ def ctx(request):
     if request.param == "ready-chunked":
         c.set_option(msc.MS_OPT_MERGE_LIGHT, 0)
         c.set_option(msc.MS_OPT_MERGE_CHUNK, 3)
-    pack = {"entry-pack1": 1, "entry-wide": 0, "ready-pack2": 2}.get(request.param)
+    pack = {"entry-pack1": 1, "entry-wide": 0, "ready-pack2": 2, "entry-pack4": 4, "power-pack4": 4}.get(request.param)
     if pack is not None:
         c.set_option(msc.MS_OPT_TRANSPOSE_PACK, pack)
     yield c

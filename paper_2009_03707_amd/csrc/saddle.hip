@@ -263,19 +263,27 @@ __global__ __launch_bounds__(BT) void k_junc_emit(const uint32_t* __restrict__ v
 }
 
 // Trace the simple path leaving source `src` through its out-edge `slot`.
+// Each thread walks MT_W of a source's out-edge slots (slots MT_W h ..
+// MT_W h + MT_W - 1 for its h) in lockstep, one step of every live walk per
+// iteration, so that the walks' label loads would be in flight together; a
+// walk is a chain of dependent loads, one per step.  At 512^3 one walk per
+// thread measured as fast as two (the resident waves already cover the
+// latency) and faster than four (longer divergent tails).
+constexpr int MT_W = 1;
+
 __global__ __launch_bounds__(BT) void k_minor_trace(const uint32_t* __restrict__ s1, uint64_t S1,
                                                     const uint32_t* __restrict__ jlist, uint64_t J,
                                                     const uint32_t* __restrict__ grad, Geo geo,
                                                     const uint32_t* __restrict__ label, uint64_t max_steps,
                                                     uint64_t S2, uint8_t* __restrict__ out_t,
                                                     uint32_t* __restrict__ out_id, int* __restrict__ err) {
-    uint64_t lane = (uint64_t)blockIdx.x * BT + threadIdx.x;
-    uint64_t si = lane >> 2;
+    const uint64_t t = (uint64_t)blockIdx.x * BT + threadIdx.x;
+    const uint64_t si = t / (4 / MT_W);
     if (si >= S1 + J) return;
-    uint32_t slot = (uint32_t)(lane & 3u);
-    uint32_t e = si < S1 ? s1[si] : jlist[si - S1];
-    uint32_t w = e >> 3, k = e & 7u;
-    uint32_t a = (uint32_t)__builtin_ctz(k);
+    const uint32_t slot0 = (uint32_t)(t % (4 / MT_W)) * MT_W;
+    const uint32_t e = si < S1 ? s1[si] : jlist[si - S1];
+    const uint32_t w = e >> 3, k = e & 7u;
+    const uint32_t a = (uint32_t)__builtin_ctz(k);
     // a path never leaves the field it starts in
     const uint32_t fld = geo.field_of(w);
     const Grid g = geo.grid(fld);
@@ -283,51 +291,94 @@ __global__ __launch_bounds__(BT) void k_minor_trace(const uint32_t* __restrict__
     uint32_t c[3];
     g.coords(w - fbase, c);
     CellRef v;
-    bool hv = paired_quad(g, w, k, nib_of(grad[w], k), c, a, v);
-    uint32_t b0 = a == 0 ? 1u : 0u, b1 = a == 2 ? 1u : 2u;
-    uint32_t b = (slot >> 1) ? b1 : b0;
-    int s = (slot & 1u) ? 1 : -1;
-    uint8_t typ = T_NONE;
-    uint32_t id = 0;
-    CellRef q;
-    if (cell_step(g, w, k, c, (int)b, s, q.w, q.k) && !(hv && q.w == v.w && q.k == v.k)) {
-        uint32_t nq = nib_of(grad[q.w], q.k);
-        for (uint64_t step = 0;; step++) {
-            if (step > max_steps) {
-                atomicOr(err, 8);
-                break;
-            }
-            if (nq >= NB_CRIT) {
-                typ = T_S2;
-                id = label[label_slot(q.w, q.k, geo.nv)];
-                break;
-            }
+    const bool hv = paired_quad(g, w, k, nib_of(grad[w], k), c, a, v);
+    const uint32_t b0 = a == 0 ? 1u : 0u, b1 = a == 2 ? 1u : 2u;
+    uint32_t qw[MT_W], qk[MT_W], nq[MT_W], id[MT_W];
+    uint8_t typ[MT_W];
+    uint32_t live = 0;  // bit j: walk j still going
+#pragma unroll
+    for (int j = 0; j < MT_W; j++) {
+        const uint32_t slot = slot0 + (uint32_t)j;
+        const uint32_t b = (slot >> 1) ? b1 : b0;
+        const int s = (slot & 1u) ? 1 : -1;
+        typ[j] = T_NONE;
+        id[j] = 0;
+        CellRef q;
+        q.w = q.k = 0;
+        if (cell_step(g, w, k, c, (int)b, s, q.w, q.k) && !(hv && q.w == v.w && q.k == v.k)) live |= 1u << j;
+        qw[j] = q.w;
+        qk[j] = q.k;
+    }
+#pragma unroll
+    for (int j = 0; j < MT_W; j++) nq[j] = ((live >> j) & 1u) ? nib_of(grad[qw[j]], qk[j]) : 0u;
+    for (uint64_t step = 0; live; step++) {
+        if (step > max_steps) {
+            atomicOr(err, 8);
+            break;
+        }
+        // the label each live walk needs: its 2-saddle's, or its quad's partner edge's
+        uint32_t ew[MT_W], ek[MT_W];
+#pragma unroll
+        for (int j = 0; j < MT_W; j++) {
+            ew[j] = ek[j] = 0;
+            if (!((live >> j) & 1u)) continue;
+            if (nq[j] >= NB_CRIT) continue;  // the label of the quad itself
             CellRef e2;
-            if (!quad_edge_partner(g, q.w, q.k, nq, e2)) break;  // paired with a cube: dead end
-            const uint32_t lab = label[label_slot(e2.w, e2.k, geo.nv)];
-            if (!(lab & SUCC_FLAG)) {
-                typ = T_JUNC;
-                id = lab;
-                break;
+            if (!quad_edge_partner(g, qw[j], qk[j], nq[j], e2)) {  // paired with a cube: dead end
+                live &= ~(1u << j);
+                continue;
             }
-            if (lab == NOT_JUNCTION) break;  // no out-edge: dead end
-            // e2 has exactly one out-edge; its step was recorded by the BFS
+            ew[j] = e2.w;
+            ek[j] = e2.k;
+        }
+        uint32_t lab[MT_W];
+#pragma unroll
+        for (int j = 0; j < MT_W; j++) {
+            lab[j] = 0;
+            if (!((live >> j) & 1u)) continue;
+            lab[j] = nq[j] >= NB_CRIT ? label[label_slot(qw[j], qk[j], geo.nv)]
+                                      : label[label_slot(ew[j], ek[j], geo.nv)];
+        }
+#pragma unroll
+        for (int j = 0; j < MT_W; j++) {
+            if (!((live >> j) & 1u)) continue;
+            if (nq[j] >= NB_CRIT) {
+                typ[j] = T_S2;
+                id[j] = lab[j];
+                live &= ~(1u << j);
+                continue;
+            }
+            if (!(lab[j] & SUCC_FLAG)) {
+                typ[j] = T_JUNC;
+                id[j] = lab[j];
+                live &= ~(1u << j);
+                continue;
+            }
+            if (lab[j] == NOT_JUNCTION) {  // no out-edge: dead end
+                live &= ~(1u << j);
+                continue;
+            }
+            // the edge has exactly one out-edge; its step was recorded by the BFS
             uint32_t c2[3];
-            g.coords(e2.w - fbase, c2);
-            const uint32_t st = lab & 7u;
-            if (!cell_step(g, e2.w, e2.k, c2, (int)(st >> 1), (st & 1u) ? 1 : -1, q.w, q.k)) {
+            g.coords(ew[j] - fbase, c2);
+            const uint32_t st = lab[j] & 7u;
+            if (!cell_step(g, ew[j], ek[j], c2, (int)(st >> 1), (st & 1u) ? 1 : -1, qw[j], qk[j])) {
                 atomicOr(err, 16);
-                break;
+                live &= ~(1u << j);
+                continue;
             }
-            nq = (lab >> 3) & 15u;
+            nq[j] = (lab[j] >> 3) & 15u;
         }
     }
-    if ((typ == T_S2 && id >= S2) || (typ == T_JUNC && id >= J)) {
-        atomicOr(err, 16);  // a label that was never assigned
-        typ = T_NONE;
+#pragma unroll
+    for (int j = 0; j < MT_W; j++) {
+        if ((typ[j] == T_S2 && id[j] >= S2) || (typ[j] == T_JUNC && id[j] >= J)) {
+            atomicOr(err, 16);  // a label that was never assigned
+            typ[j] = T_NONE;
+        }
+        out_t[4 * si + slot0 + j] = typ[j];
+        out_id[4 * si + slot0 + j] = id[j];
     }
-    out_t[lane] = typ;
-    out_id[lane] = id;
 }
 
 // Per source: distinct junction targets and distinct 2-saddle targets with
@@ -440,10 +491,10 @@ hipError_t launch_junc_emit(const uint32_t* vis, uint32_t* label, uint64_t nv, c
 hipError_t launch_minor_trace(const uint32_t* s1, uint64_t S1, const uint32_t* jlist, uint64_t J, const uint32_t* grad,
                               const Geo& g, const uint32_t* label, uint64_t max_steps, uint64_t S2, uint8_t* out_t,
                               uint32_t* out_id, int* err, hipStream_t s) {
-    uint64_t lanes = 4 * (S1 + J);
-    if (lanes == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_minor_trace, dim3(grid_blocks(lanes, BT)), dim3(BT), 0, s, s1, S1, jlist, J, grad, g, label,
-                       max_steps, S2, out_t, out_id, err);
+    uint64_t threads = (4 / MT_W) * (S1 + J);
+    if (threads == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_minor_trace, dim3(grid_blocks(threads, BT)), dim3(BT), 0, s, s1, S1, jlist, J, grad, g,
+                       label, max_steps, S2, out_t, out_id, err);
     return hipGetLastError();
 }
 

@@ -153,11 +153,16 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const
         check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, row_map, rows, c->stream,
                                     (const uint64_t*)in.val, vbits),
               "expand rows");
-        const Unpack up{vbits, out.col, (uint64_t*)out.val};
+        Unpack up{vbits, out.col, (uint64_t*)out.val};
+        if (escapes) {
+            up.esc = buf<uint32_t>(c, "tr.esc", nnz);
+            up.nesc = (unsigned long long*)buf<uint64_t>(c, "tr.nesc", 1);
+            check(c, launch_set_u64((uint64_t*)up.nesc, 0, c->stream), "escape count");
+        }
         check(c, radix_transpose_packed_u32(in.col, rows, ka, va, kb, vb, nnz, kbits, tmp, up, &keys, c->stream),
               "sort");
         if (escapes)
-            check(c, launch_escape_fix(nnz, vbits, keys, out.col, (const uint64_t*)in.rowptr, in.col,
+            check(c, launch_escape_fix(up.esc, up.nesc, keys, out.col, (const uint64_t*)in.rowptr, in.col,
                                        (const uint64_t*)in.val, row_map ? row_inv : nullptr, (uint64_t*)out.val,
                                        c->stream),
                   "escape fix");

@@ -85,24 +85,27 @@ hipError_t radix_transpose_u32(const uint32_t* keys, const uint32_t* rows, const
 // Packed transpose: each 32-bit payload holds an entry's output column in
 // its high bits and its value in its low vb bits, so only 8 bytes per entry
 // move through the passes; the last pass splits the payload into ocol and
-// oval.  Values of 2^vb - 1 and more are packed as 2^vb - 1 (escapes);
-// launch_escape_fix then fills their values from the input matrix.
+// oval.  Values of 2^vb - 1 and more are packed as 2^vb - 1 (escapes): with
+// esc set, the last pass also lists the output positions of the escapes
+// (esc, count in *nesc, which must be zero on entry; one atomic per
+// workgroup), and launch_escape_fix fills their values from the input.
 struct Unpack {
-    int vb;          // value bits, 1..24
-    uint32_t* ocol;  // n output column ids
-    uint64_t* oval;  // n output values
+    int vb;                              // value bits, 1..24
+    uint32_t* ocol;                      // n output column ids
+    uint64_t* oval;                      // n output values
+    uint32_t* esc = nullptr;             // n slots, or null
+    unsigned long long* nesc = nullptr;  // escapes listed
 };
 hipError_t radix_transpose_packed_u32(const uint32_t* keys, const uint32_t* packed, uint32_t* ka, uint32_t* va,
                                       uint32_t* kb, uint32_t* vb, uint64_t n, int bits, uint64_t* tmp,
                                       const Unpack& up, const uint32_t** sorted_keys, hipStream_t s);
-// The escapes of a packed transpose of n entries with vb value bits: every
-// output entry g whose value reads 2^vb - 1 (key keys[g], the input column;
-// column ocol[g], the input row, or the row row_inv maps it back to) takes
-// the input's value at that row and column, found by binary search (the
-// input rows must be sorted by column).
-hipError_t launch_escape_fix(uint64_t n, int vb, const uint32_t* keys, const uint32_t* ocol, const uint64_t* rowptr,
-                             const uint32_t* col, const uint64_t* val, const uint32_t* row_inv, uint64_t* oval,
-                             hipStream_t s);
+// The escapes of a packed transpose: every listed output entry g (key
+// keys[g], the input column; column ocol[g], the input row, or the row
+// row_inv maps it back to) takes the input's value at that row and column,
+// found by binary search (the input rows must be sorted by column).
+hipError_t launch_escape_fix(const uint32_t* esc, const unsigned long long* nesc, const uint32_t* keys,
+                             const uint32_t* ocol, const uint64_t* rowptr, const uint32_t* col, const uint64_t* val,
+                             const uint32_t* row_inv, uint64_t* oval, hipStream_t s);
 // Same, reading the keys from `keys` (left intact) with the entry index as
 // payload; the result lands in (a) or (b).
 hipError_t radix_sort_u32_from(const uint32_t* keys, uint32_t* keys_a, uint32_t* vals_a, uint32_t* keys_b,

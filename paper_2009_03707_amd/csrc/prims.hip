@@ -214,6 +214,24 @@ __global__ __launch_bounds__(RT) void radix_scatter(const K* __restrict__ keys, 
             up.ocol[g] = v >> up.vb;
             up.oval[g] = v & mask;
         }
+        if (!up.esc) return;  // uniform
+        // list the tile's escapes: count per thread, scan, one atomic per workgroup
+        uint32_t mine = 0;
+        for (uint32_t i = (uint32_t)tid; i < tot; i += RT) mine += (sval[i] & mask) == mask ? 1u : 0u;
+        uint32_t all;
+        uint32_t pos = block_excl_scan<uint32_t, RT>(mine, sc, all);
+        if (all == 0) return;  // uniform
+        __shared__ unsigned long long s_base;
+        if (tid == 0) s_base = atomicAdd(up.nesc, (unsigned long long)all);
+        __syncthreads();
+        const uint64_t eb = s_base + pos;
+        uint32_t q = 0;
+        for (uint32_t i = (uint32_t)tid; i < tot && q < mine; i += RT) {
+            if ((sval[i] & mask) != mask) continue;
+            const K key = skey[i];
+            const uint32_t d = (uint32_t)(key >> shift) & (NB - 1u);
+            up.esc[eb + q++] = (uint32_t)(gbase[d] + (i - tstart[d]));
+        }
         return;
     }
     for (uint32_t i = (uint32_t)tid; i < tot; i += RT) {
@@ -312,22 +330,24 @@ hipError_t radix_impl(const K* keys0, const uint32_t* vals0, K* ka, uint32_t* va
 }  // namespace
 
 namespace {
-__global__ __launch_bounds__(256) void k_escape_fix(uint64_t n, uint64_t top, const uint32_t* __restrict__ keys,
-                                                    const uint32_t* __restrict__ ocol,
+__global__ __launch_bounds__(256) void k_escape_fix(const uint32_t* __restrict__ esc,
+                                                    const unsigned long long* __restrict__ nesc,
+                                                    const uint32_t* __restrict__ keys, const uint32_t* __restrict__ ocol,
                                                     const uint64_t* __restrict__ rowptr,
                                                     const uint32_t* __restrict__ col, const uint64_t* __restrict__ val,
                                                     const uint32_t* __restrict__ row_inv, uint64_t* __restrict__ oval) {
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n || oval[g] != top) return;
-    const uint32_t key = keys[g], c = ocol[g];
-    const uint32_t r = row_inv ? row_inv[c] : c;
-    uint64_t lo = rowptr[r], hi = rowptr[r + 1];  // first column >= key
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (col[mid] < key) lo = mid + 1;
-        else hi = mid;
+    const uint64_t n = *nesc;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t g = esc[i], key = keys[g], c = ocol[g];
+        const uint32_t r = row_inv ? row_inv[c] : c;
+        uint64_t lo = rowptr[r], hi = rowptr[r + 1];  // first column >= key
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (col[mid] < key) lo = mid + 1;
+            else hi = mid;
+        }
+        oval[g] = (lo < rowptr[r + 1] && col[lo] == key) ? val[lo] : 0;  // found for rows holding each column once
     }
-    oval[g] = (lo < rowptr[r + 1] && col[lo] == key) ? val[lo] : 0;  // found for rows holding each column once
 }
 __global__ void k_publish(const uint64_t* __restrict__ src, uint64_t n, uint64_t* __restrict__ dst) {
     for (uint64_t i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
@@ -337,12 +357,11 @@ __global__ void k_set_u64(uint64_t* __restrict__ dst, uint64_t v) {
 }
 }  // namespace
 
-hipError_t launch_escape_fix(uint64_t n, int vb, const uint32_t* keys, const uint32_t* ocol, const uint64_t* rowptr,
-                             const uint32_t* col, const uint64_t* val, const uint32_t* row_inv, uint64_t* oval,
-                             hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_escape_fix, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, (1ull << vb) - 1ull, keys,
-                       ocol, rowptr, col, val, row_inv, oval);
+hipError_t launch_escape_fix(const uint32_t* esc, const unsigned long long* nesc, const uint32_t* keys,
+                             const uint32_t* ocol, const uint64_t* rowptr, const uint32_t* col, const uint64_t* val,
+                             const uint32_t* row_inv, uint64_t* oval, hipStream_t s) {
+    hipLaunchKernelGGL(k_escape_fix, dim3(2048), dim3(256), 0, s, esc, nesc, keys, ocol, rowptr, col, val, row_inv,
+                       oval);
     return hipGetLastError();
 }
 

@@ -15,20 +15,33 @@ namespace {
 constexpr int BT = 256;
 
 // rows[p] = the row of entry p, or map[row] when a map is given; with val
-// set, packed as (row << vb) | min(val[p], 2^vb - 1).
+// set, packed as (row << vb) | min(val[p], 2^vb - 1).  A workgroup takes
+// BT consecutive rows and strides over all their entries together (the row
+// of an entry found by binary search in the rows' offsets, staged in LDS),
+// so that reads and writes are coalesced and a long row is shared by the
+// whole workgroup.
 __global__ __launch_bounds__(BT) void k_expand_rows(const uint64_t* __restrict__ rowptr, uint64_t nrows,
                                                     const uint32_t* __restrict__ map, const uint64_t* __restrict__ val,
                                                     int vb, uint32_t* __restrict__ rows) {
-    uint64_t r = (uint64_t)blockIdx.x * BT + threadIdx.x;
-    if (r >= nrows) return;
-    const uint32_t v = map ? map[r] : (uint32_t)r;
-    const uint64_t e = rowptr[r + 1];
-    if (!val) {
-        for (uint64_t p = rowptr[r]; p < e; p++) rows[p] = v;
-        return;
-    }
+    __shared__ uint64_t s_rp[BT + 1];
+    __shared__ uint32_t s_v[BT];
+    const uint64_t r0 = (uint64_t)blockIdx.x * BT;
+    const uint32_t nr = (uint32_t)(nrows - r0 < (uint64_t)BT ? nrows - r0 : (uint64_t)BT);
+    for (uint32_t t = threadIdx.x; t <= nr; t += BT) s_rp[t] = rowptr[r0 + t];
+    if (threadIdx.x < nr) s_v[threadIdx.x] = map ? map[r0 + threadIdx.x] : (uint32_t)(r0 + threadIdx.x);
+    __syncthreads();
+    const uint64_t p0 = s_rp[0], p1 = s_rp[nr];
     const uint64_t top = (1ull << vb) - 1ull;
-    for (uint64_t p = rowptr[r]; p < e; p++) rows[p] = (v << vb) | (uint32_t)(val[p] < top ? val[p] : top);
+    for (uint64_t p = p0 + threadIdx.x; p < p1; p += BT) {
+        uint32_t lo = 0, hi = nr;  // last row j with s_rp[j] <= p
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_rp[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t v = s_v[lo];
+        rows[p] = val ? (v << vb) | (uint32_t)(val[p] < top ? val[p] : top) : v;
+    }
 }
 
 // *out += the sum of a[0, n) (one atomic per workgroup; *out zeroed by the caller)

@@ -601,6 +601,11 @@ __global__ void k_sweep_seal(uint64_t* __restrict__ lv, uint64_t L, const unsign
     if (threadIdx.x == 0) lv[L + 1] = *tail;
 }
 
+// A thread releases SW_R junctions per pass, each step (frontier entry,
+// row offsets, successors, in-degree atomics) issued for all of them before
+// any is used, so the chains of dependent loads overlap.
+constexpr int SW_R = 2;
+
 __global__ __launch_bounds__(BT) void k_sweep_level(uint32_t* __restrict__ order, const uint64_t* __restrict__ lv,
                                                     uint64_t L, const uint64_t* __restrict__ brp,
                                                     const uint32_t* __restrict__ bcol, uint32_t* __restrict__ indeg,
@@ -608,27 +613,46 @@ __global__ __launch_bounds__(BT) void k_sweep_level(uint32_t* __restrict__ order
     __shared__ unsigned long long sc[BT / WAVE + 1];
     __shared__ unsigned long long base;
     const uint64_t b0 = lv[L], n = lv[L + 1] - b0;
-    for (uint64_t blk = (uint64_t)blockIdx.x * BT; blk < n; blk += (uint64_t)gridDim.x * BT) {  // uniform
-        const uint64_t i = blk + threadIdx.x;
-        uint32_t out[3];
-        unsigned long long m = 0;
-        if (i < n) {
-            const uint32_t j = order[b0 + i];
-            uint64_t b = brp[j], e = brp[j + 1];
-            if (e - b > 3) {
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
+    for (uint64_t blk = (uint64_t)blockIdx.x * BT * SW_R; blk < n; blk += (uint64_t)gridDim.x * BT * SW_R) {  // uniform
+        uint32_t j[SW_R];
+#pragma unroll
+        for (int r = 0; r < SW_R; r++) {
+            const uint64_t i = blk + (uint64_t)r * BT + threadIdx.x;
+            j[r] = i < n ? order[b0 + i] : NONE;
+        }
+        uint64_t rb[SW_R], re[SW_R];
+#pragma unroll
+        for (int r = 0; r < SW_R; r++) {
+            rb[r] = j[r] != NONE ? brp[j[r]] : 0;
+            re[r] = j[r] != NONE ? brp[j[r] + 1] : 0;
+            if (re[r] - rb[r] > 3) {  // at most three successors (the other edges of its paired quad)
                 atomicOr(err, 64);
-                e = b + 3;
-            }
-            for (uint64_t q = b; q < e; q++) {
-                const uint32_t t = bcol[q];
-                if (atomicSub(&indeg[t], 1u) == 1u) out[m++] = t;
+                re[r] = rb[r] + 3;
             }
         }
+        uint32_t t[SW_R][3];
+#pragma unroll
+        for (int r = 0; r < SW_R; r++)
+#pragma unroll
+            for (int q = 0; q < 3; q++) t[r][q] = rb[r] + q < re[r] ? bcol[rb[r] + q] : NONE;
+        uint32_t fresh = 0;  // bit 3 r + q: successor q of junction r became ready
+#pragma unroll
+        for (int r = 0; r < SW_R; r++)
+#pragma unroll
+            for (int q = 0; q < 3; q++)
+                if (t[r][q] != NONE && atomicSub(&indeg[t[r][q]], 1u) == 1u) fresh |= 1u << (3 * r + q);
+        const unsigned long long m = (unsigned long long)__builtin_popcount(fresh);
         unsigned long long tot;
         const unsigned long long ex = block_excl_scan<unsigned long long, BT>(m, sc, tot);
         if (threadIdx.x == 0) base = tot ? atomicAdd(tail, tot) : 0;
         __syncthreads();
-        for (unsigned long long t = 0; t < m; t++) order[base + ex + t] = out[t];
+        unsigned long long o = base + ex;
+#pragma unroll
+        for (int r = 0; r < SW_R; r++)
+#pragma unroll
+            for (int q = 0; q < 3; q++)
+                if ((fresh >> (3 * r + q)) & 1u) order[o++] = t[r][q];
         __syncthreads();  // base is rewritten by the next pass
     }
 }
@@ -689,13 +713,21 @@ __global__ __launch_bounds__(BT) void k_relabel(uint32_t* __restrict__ x, uint64
 // also sums the run's scaled counts; a scan of the head flags then gives
 // every output row its final, gap-free position.
 
+// (the first three predecessors' ids, then their lengths, are loaded
+// together; a junction has at most three)
 __global__ __launch_bounds__(BT) void k_entry_ub(MergeArgs a, uint64_t* __restrict__ ub) {
     uint64_t i = (uint64_t)blockIdx.x * BT + threadIdx.x;
     if (i >= a.n) return;
-    uint32_t c = col_of(a, i);
-    uint32_t k = num_lists(a, c);
+    const uint32_t c = col_of(a, i);
+    const uint64_t p0 = a.prp[c], np = a.prp[c + 1] - p0;
     uint64_t u = a.brp[c + 1] - a.brp[c];
-    for (uint32_t s = 1; s < k; s++) u += a.alen[a.pcol[a.prp[c] + (s - 1)]];
+    uint32_t pc[3];
+#pragma unroll
+    for (int q = 0; q < 3; q++) pc[q] = (uint64_t)q < np ? a.pcol[p0 + q] : 0u;
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+        if ((uint64_t)q < np) u += a.alen[pc[q]];
+    for (uint64_t q = 3; q < np; q++) u += a.alen[a.pcol[p0 + q]];
     ub[i] = u;
 }
 

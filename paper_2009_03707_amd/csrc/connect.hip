@@ -42,9 +42,8 @@ hipError_t launch_esc_expand(const uint32_t* xrow, const uint32_t* xcol, const u
                              const uint64_t* poff, const uint64_t* yrowptr, const uint32_t* ycol, const uint64_t* yval,
                              uint32_t* prow, uint32_t* pcol, uint64_t* pval, hipStream_t s);
 hipError_t launch_count_sat(const uint64_t* v, uint64_t n, unsigned long long* out, hipStream_t s);
-hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Geo& g,
-                             uint32_t* vis, uint32_t* next, unsigned long long* counts, uint32_t* label,
-                             hipStream_t s);
+hipError_t launch_bfs_level(uint32_t* queue, uint64_t qcap, uint64_t* lv, uint64_t L, const uint32_t* grad,
+                            const Geo& g, uint32_t* vis, unsigned long long* tail, uint32_t* label, hipStream_t s);
 size_t junction_blocks(uint64_t nv);
 hipError_t launch_junc_count(const uint32_t* vis, const uint32_t* label, uint64_t nv, uint64_t* bcount,
                              hipStream_t s);
@@ -621,32 +620,40 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
     uint64_t nvis = ((uint64_t)g.nv + 3) / 4;
     uint32_t* vis = buf<uint32_t>(c, "visited", nvis);
     check(c, hipMemsetAsync(vis, 0, 4 * nvis, s), "memset");
-    // packed per-level counter: low 32 bits next frontier, high 32 bits junctions so far
-    unsigned long long* d_cnt = (unsigned long long*)buf<uint64_t>(c, "bfs_counts", 1);
-    uint64_t ncur = S1, J = 0, reach = 0;
+    // the frontiers, level after level, in one queue: the 1-saddles, then the
+    // nodes in the order they are first reached (each once, by its visited
+    // bit), at most one per edge of the grid.  The packed tail counts the
+    // queue (low 32 bits) and the junctions (high 32 bits).
+    uint64_t J = 0, reach = 0;
     int64_t levels = 0;
     const uint64_t max_nodes = (uint64_t)3 * g.nv + 1;
     if (S1 > 0) {
-        uint32_t* fa = buf<uint32_t>(c, "front_a", ncur);
-        check(c, hipMemcpyAsync(fa, s1, 4 * ncur, hipMemcpyDeviceToDevice, s), "copy");
-        bool level0 = true;
-        const char* cur_name = "front_a";
-        const char* nxt_name = "front_b";
-        while (ncur > 0) {
-            uint32_t* cur = buf<uint32_t>(c, cur_name, ncur);
-            uint32_t* nxt = buf<uint32_t>(c, nxt_name, 4 * ncur);
-            check(c, launch_set_u64((uint64_t*)d_cnt, J << 32, s), "counter init");
-            check(c, launch_bfs_expand(cur, ncur, level0, grad, g, vis, nxt, d_cnt, label, s), "bfs expand");
-            uint64_t h = readback(c, (const uint64_t*)d_cnt, 1)[0];
-            uint64_t nn = h & 0xFFFFFFFFull;
-            J = h >> 32;
-            reach += level0 ? 0 : ncur;
-            ncur = nn;
-            levels++;
-            level0 = false;
-            std::swap(cur_name, nxt_name);
-            if ((uint64_t)levels > max_nodes) fail(c, MS_ERR_INTERNAL, "BFS did not terminate");
+        uint32_t* queue = buf<uint32_t>(c, "bfs.queue", max_nodes);
+        unsigned long long* tail = (unsigned long long*)buf<uint64_t>(c, "bfs.tail", 1);
+        check(c, hipMemcpyAsync(queue, s1, 4 * S1, hipMemcpyDeviceToDevice, s), "copy");
+        check(c, launch_set_u64((uint64_t*)tail, S1, s), "tail init");
+        constexpr uint64_t BFS_BATCH = 16;
+        uint64_t* lv = buf_keep<uint64_t>(c, "bfs.lv", BFS_BATCH + 2, 0);
+        check(c, launch_set_u64(lv, 0, s), "level start");
+        std::vector<uint64_t> bound{0};  // lv as read back
+        uint64_t L = 0;
+        for (bool done = false; !done;) {
+            const uint64_t L0 = L;
+            lv = buf_keep<uint64_t>(c, "bfs.lv", L0 + BFS_BATCH + 2, L0 + 1);
+            for (; L < L0 + BFS_BATCH; L++)
+                check(c, launch_bfs_level(queue, max_nodes, lv, L, grad, g, vis, tail, label, s), "bfs level");
+            // lv[L0 + 1 .. L]: the boundaries sealed in this batch
+            const uint64_t* h = readback(c, lv + L0 + 1, BFS_BATCH);
+            for (uint64_t q = 0; q < BFS_BATCH && !done; q++) {
+                if (h[q] == bound.back()) done = true;  // an empty level: the search is complete
+                else bound.push_back(h[q]);
+            }
+            if (bound.size() > max_nodes + 1) fail(c, MS_ERR_INTERNAL, "BFS did not terminate");
         }
+        levels = (int64_t)bound.size() - 1;
+        reach = bound.back() - S1;
+        J = readback(c, (const uint64_t*)tail, 1)[0] >> 32;
+        if (bound.back() > max_nodes) fail(c, MS_ERR_INTERNAL, "BFS queue overflow");
     }
     st.bfs_levels = levels;
     st.reachable = (int64_t)reach;

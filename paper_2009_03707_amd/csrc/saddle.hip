@@ -55,11 +55,15 @@ __device__ __forceinline__ bool quad_edge_partner(const Grid& g, uint32_t qw, ui
     return true;
 }
 
-// A workgroup expands BFS_NPT * BT frontier nodes (thread: nodes
-// blockIdx * BFS_NPT * BT + r * BT + tid) and appends all their new targets
-// and junctions with one atomic on a packed counter (low 32 bits: frontier,
-// high 32 bits: junctions); appends to one counter serialise, so they are
-// kept few.
+// The frontiers are consecutive ranges of one queue: level L is
+// queue[lv[L], lv[L + 1]), sealed by k_bfs_seal from the queue's tail before
+// the level is expanded, so the levels run back to back on the device and
+// the host reads the boundaries back once per batch of levels.  The
+// expansion grid is fixed and strides over the level in chunks of
+// BFS_NPT * BT nodes (thread: nodes chunk * BFS_NPT * BT + r * BT + tid); a
+// workgroup appends a chunk's new targets and junctions with one atomic on
+// the packed tail (low 32 bits: queue length, high 32 bits: junctions);
+// appends to one counter serialise, so they are kept few.
 //
 // A node's expansion is a chain of dependent memory operations (its own
 // word, then the words of its cofacet quads, then a visited-bit atomic per
@@ -74,17 +78,30 @@ __device__ __forceinline__ bool quad_edge_partner(const Grid& g, uint32_t qw, ui
 constexpr int BFS_NPT = 2;
 constexpr int BFS_S = 6;  // slots: 3 axes x 2 signs
 
-__global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ cur, uint64_t ncur, int level0,
+constexpr unsigned BFS_GRID = 1024;  // 1024 and 65536 measured best at 512^3 (4096: +1.4 ms)
+
+__global__ void k_bfs_seal(uint64_t* __restrict__ lv, uint64_t L, const unsigned long long* __restrict__ tail) {
+    if (threadIdx.x == 0) lv[L + 1] = *tail & 0xFFFFFFFFull;
+}
+
+__global__ __launch_bounds__(BT) void k_bfs_expand(uint32_t* __restrict__ queue, uint64_t qcap,
+                                                   const uint64_t* __restrict__ lv, uint64_t L,
                                                    const uint32_t* __restrict__ grad, Geo geo,
-                                                   uint32_t* __restrict__ vis, uint32_t* __restrict__ next,
-                                                   unsigned long long* __restrict__ counts,
+                                                   uint32_t* __restrict__ vis, unsigned long long* __restrict__ tail,
                                                    uint32_t* __restrict__ label) {
+    const int level0 = L == 0;
+    const uint64_t b0 = lv[L] < qcap ? lv[L] : qcap, b1 = lv[L + 1] < qcap ? lv[L + 1] : qcap;
+    const uint64_t ncur = b1 > b0 ? b1 - b0 : 0;  // (the queue is never full; reads stay inside it regardless)
+    const uint32_t* __restrict__ cur = queue + b0;
+    __shared__ unsigned long long sc[BT / WAVE + 1];
+    __shared__ unsigned long long base;
+    for (uint64_t chunk = blockIdx.x; chunk * (uint64_t)(BFS_NPT * BT) < ncur; chunk += gridDim.x) {  // uniform
     uint32_t e[BFS_NPT], own[BFS_NPT];
     bool ok[BFS_NPT];
     // phase 1: the nodes and their own words
 #pragma unroll
     for (int r = 0; r < BFS_NPT; r++) {
-        const uint64_t i = ((uint64_t)blockIdx.x * BFS_NPT + r) * BT + threadIdx.x;
+        const uint64_t i = (chunk * BFS_NPT + r) * BT + threadIdx.x;
         ok[r] = i < ncur;
         e[r] = ok[r] ? cur[i] : 0u;
     }
@@ -177,22 +194,25 @@ __global__ __launch_bounds__(BT) void k_bfs_expand(const uint32_t* __restrict__ 
         snt += nt[r];
         sj += isj[r];
     }
-    __shared__ unsigned long long sc[BT / WAVE + 1];
-    __shared__ unsigned long long base;
     unsigned long long packed = (unsigned long long)snt | ((unsigned long long)sj << 32);
     unsigned long long tot;
     unsigned long long ex = block_excl_scan<unsigned long long, BT>(packed, sc, tot);
-    if (threadIdx.x == 0) base = tot ? atomicAdd(counts, tot) : 0ull;
+    if (threadIdx.x == 0) base = tot ? atomicAdd(tail, tot) : 0ull;
     __syncthreads();
     uint64_t o = (base & 0xFFFFFFFFull) + (ex & 0xFFFFFFFFull);
 #pragma unroll
     for (int r = 0; r < BFS_NPT; r++) {
 #pragma unroll
         for (int j = 0; j < BFS_S; j++)
-            if ((fresh[r] >> j) & 1u) next[o++] = tgt[r][j];
+            if ((fresh[r] >> j) & 1u) {
+                if (o < qcap) queue[o] = tgt[r][j];  // never full: a node enters once (the host checks the tail)
+                o++;
+            }
         // a junction is marked with id 0 here; junctions are numbered in
         // cell order once the search is complete
         if (e[r] != 0xFFFFFFFFu) label[label_slot(e[r] >> 3, e[r] & 7u, geo.nv)] = isj[r] ? 0u : lab[r];
+    }
+    __syncthreads();  // base is rewritten by the next chunk
     }
 }
 
@@ -461,12 +481,13 @@ __global__ __launch_bounds__(BT) void k_minor_rows(const uint8_t* __restrict__ o
 
 }  // namespace
 
-hipError_t launch_bfs_expand(const uint32_t* cur, uint64_t ncur, bool level0, const uint32_t* grad, const Geo& g,
-                             uint32_t* vis, uint32_t* next, unsigned long long* counts, uint32_t* label,
-                             hipStream_t s) {
-    if (ncur == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_blocks(ncur, (unsigned)(BT * BFS_NPT))), dim3(BT), 0, s, cur, ncur,
-                       level0 ? 1 : 0, grad, g, vis, next, counts, label);
+hipError_t launch_bfs_level(uint32_t* queue, uint64_t qcap, uint64_t* lv, uint64_t L, const uint32_t* grad,
+                            const Geo& g, uint32_t* vis, unsigned long long* tail, uint32_t* label, hipStream_t s) {
+    hipLaunchKernelGGL(k_bfs_seal, dim3(1), dim3(WAVE), 0, s, lv, L, (const unsigned long long*)tail);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bfs_expand, dim3(BFS_GRID), dim3(BT), 0, s, queue, qcap, (const uint64_t*)lv, L, grad, g,
+                       vis, tail, label);
     return hipGetLastError();
 }
 

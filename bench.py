@@ -360,8 +360,9 @@ def main():
     crit_roof["note"] = "whole critical stage (both passes, scan, count readback), per call"
     if tm["rank_launches"] > 0:
         # path-count ranking: per input entry 4 B row + 8 B count read and a
-        # 1 B head flag written; per run head 4 B row + 8 B sum written
-        rank_bytes = 13 * tm["rank_entries"] + 12 * tm["rank_heads"]
+        # 1 B head flag + 8 B scaled count written at its merged position;
+        # per run head its 4 B row written
+        rank_bytes = 21 * tm["rank_entries"] + 4 * tm["rank_heads"]
         main_roof = roofline("k_entry_rank", "paths.hip", rank_bytes / tm["rank_launches"],
                              tm["rank_ms"] / tm["rank_launches"])
         main_roof["launches_per_step"] = tm["rank_launches"] // calls

@@ -752,13 +752,22 @@ __global__ __launch_bounds__(BT) void k_block_start(const uint64_t* __restrict__
 // once per block.  Phase 1 maps every entry to (column, list, index) and
 // stages its row in LDS; phase 2 ranks it: for every other list of the
 // column, the count of rows below it there -- searched in LDS when that
-// list lies inside the block's entry range, else in global memory.  The
-// head of a run of equal rows (no earlier list holds the row) sums the
-// run's scaled counts.  Entries of columns beyond the staged window read
-// their metadata from global memory (same result).  Each entry's own scaled
-// count is loaded in phase 1 together with its row, so that its latency
-// overlaps the barrier instead of opening phase 2.
+// list lies inside the block's entry range, else in global memory.  Every
+// entry writes its own scaled count at its merged position, the head of a
+// run of equal rows (no earlier list holds the row) also its row; the head
+// scan sums each run.  Entries of columns beyond the staged window read
+// their metadata from global memory (same result).
+//
+// The kernel is bound by the latency of dependent loads, so each step
+// issues all of a thread's independent loads before it uses any: the
+// window's offsets and column ids, then every column's list pointers, then
+// its first predecessors' ids and multiplicities, then their A* offsets and
+// lengths (a junction has at most three predecessors; more are read one by
+// one), and in phase 1 the rows and counts of all EPT entries together.
 // off: exclusive scan of ub (n + 1 entries, off[n] = T).
+static_assert(CW == BT, "one window column per thread");
+constexpr int RP = 3;  // predecessors whose descriptors are loaded together
+
 __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* __restrict__ off, uint64_t T,
                                                    const uint32_t* __restrict__ bstart, uint32_t* __restrict__ hrow,
                                                    uint64_t* __restrict__ hval, uint8_t* __restrict__ head) {
@@ -768,81 +777,86 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
     __shared__ uint32_t s_len[LCAP];
     __shared__ uint32_t s_mul[LCAP];  // minor multiplicities (at most 4 paths leave a source)
     __shared__ uint32_t s_x[EPB];
-    __shared__ uint32_t s_sc[BT / WAVE + 1];
-    __shared__ uint32_t s_nused;
+    __shared__ uint64_t s_sc[BT / WAVE + 1];
     const uint64_t e0 = (uint64_t)blockIdx.x * EPB;
     const uint64_t e_end = e0 + EPB < T ? e0 + EPB : T;
     const uint64_t i0 = bstart[blockIdx.x];  // the column of the block's first entry
     const uint32_t wn = (uint32_t)((a.n - i0) < (uint64_t)CW ? (a.n - i0) : (uint64_t)CW);  // >= 1
-    for (uint32_t t = threadIdx.x; t <= wn; t += BT) s_off[t] = off[i0 + t];
-    __syncthreads();
-    if (threadIdx.x == 0) {  // window columns that hold entries of this block
-        uint32_t lo = 0, hi = wn;
-        while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (s_off[mid] <= e_end - 1) lo = mid;
-            else hi = mid;
-        }
-        s_nused = lo + 1;
+    const uint32_t t = threadIdx.x;
+
+    // window column t: its offset and id, then its list pointers.  Offsets
+    // never decrease, so the columns holding entries of this block (offset
+    // below e_end) are a prefix of the window.
+    const uint64_t o_t = t < wn ? off[i0 + t] : 0;
+    const uint32_t c = t < wn ? col_of(a, i0 + t) : 0u;
+    if (t < wn) s_off[t] = o_t;
+    if (t == 0) s_off[wn] = off[i0 + wn];
+    const bool used = t < wn && o_t < e_end;
+    uint64_t pr0 = 0, pr1 = 0, b0 = 0, b1 = 0;
+    if (used) {
+        pr0 = a.prp[c];
+        pr1 = a.prp[c + 1];
+        b0 = a.brp[c];
+        b1 = a.brp[c + 1];
     }
-    __syncthreads();
-    const uint32_t nused = s_nused;
-    // list counts of the used columns (CW / BT per thread), their scan, the descriptors
-    uint32_t kt[CW / BT], ct[CW / BT], ksum = 0;
+    const uint64_t np = pr1 - pr0;
+    uint32_t pc[RP];
+    uint64_t pv[RP], ao[RP];
+    uint32_t al[RP];
 #pragma unroll
-    for (int r = 0; r < CW / BT; r++) {
-        const uint32_t t = threadIdx.x * (CW / BT) + r;
-        kt[r] = 0;
-        ct[r] = 0;
-        if (t < nused) {
-            ct[r] = col_of(a, i0 + t);
-            kt[r] = num_lists(a, ct[r]);
-        }
-        ksum += kt[r];
+    for (int q = 0; q < RP; q++) {
+        pc[q] = (uint64_t)q < np ? a.pcol[pr0 + q] : 0u;
+        pv[q] = (uint64_t)q < np ? a.pval[pr0 + q] : 0u;
     }
-    uint32_t nl;
-    uint32_t lb = block_excl_scan<uint32_t, BT>(ksum, s_sc, nl);
 #pragma unroll
-    for (int r = 0; r < CW / BT; r++) {
-        const uint32_t t = threadIdx.x * (CW / BT) + r;
-        if (t < nused) {
-            s_lbase[t] = lb;
-            for (uint32_t q = 0; q < kt[r] && lb + q < (uint32_t)LCAP; q++) {
-                if (q == 0) {
-                    const uint64_t b0 = a.brp[ct[r]];
-                    s_lo[lb] = b0;
-                    s_len[lb] = (uint32_t)(a.brp[ct[r] + 1] - b0);
-                    s_mul[lb] = 1;
-                } else {
-                    const uint64_t pq = a.prp[ct[r]] + (q - 1);
-                    const uint32_t p = a.pcol[pq];
-                    s_lo[lb + q] = a.aoff[p];
-                    s_len[lb + q] = a.alen[p];
-                    s_mul[lb + q] = (uint32_t)a.pval[pq];
-                }
+    for (int q = 0; q < RP; q++) {
+        ao[q] = (uint64_t)q < np ? a.aoff[pc[q]] : 0u;
+        al[q] = (uint64_t)q < np ? a.alen[pc[q]] : 0u;
+    }
+    // list slots of the used columns (low half) and the used count (high half)
+    const uint64_t k = used ? 1 + np : 0;
+    uint64_t tot;
+    const uint64_t lbx = block_excl_scan<uint64_t, BT>((used ? 1ull << 32 : 0ull) | k, s_sc, tot);
+    const uint32_t lb = (uint32_t)lbx, nl = (uint32_t)tot, nused = (uint32_t)(tot >> 32);
+    if (used) {
+        s_lbase[t] = lb;
+        if (lb < (uint32_t)LCAP) {
+            s_lo[lb] = b0;
+            s_len[lb] = (uint32_t)(b1 - b0);
+            s_mul[lb] = 1;
+        }
+#pragma unroll
+        for (int q = 0; q < RP; q++)
+            if ((uint64_t)q < np && lb + 1 + q < (uint32_t)LCAP) {
+                s_lo[lb + 1 + q] = ao[q];
+                s_len[lb + 1 + q] = al[q];
+                s_mul[lb + 1 + q] = (uint32_t)pv[q];
             }
+        for (uint64_t q = RP; q < np && lb + 1 + q < (uint64_t)LCAP; q++) {
+            const uint32_t p = a.pcol[pr0 + q];
+            s_lo[lb + 1 + q] = a.aoff[p];
+            s_len[lb + 1 + q] = a.alen[p];
+            s_mul[lb + 1 + q] = (uint32_t)a.pval[pr0 + q];
         }
-        lb += kt[r];
     }
-    if (threadIdx.x == 0) s_lbase[nused] = nl;
+    if (t == 0) s_lbase[nused] = nl;
     __syncthreads();
 
-    // phase 1: map entries, stage rows
+    // phase 1: map entries to (column, list, index); then load all rows and counts
     uint32_t e_col[EPT], e_list[EPT], e_loc[EPT], x[EPT];
     bool e_win[EPT];
-    uint64_t e_glo[EPT];
-    uint64_t own[EPT];  // the entry's own scaled count, loaded with its row
+    uint64_t e_glo[EPT], gi[EPT], own[EPT];
+    uint32_t mul[EPT];
 #pragma unroll
     for (int r = 0; r < EPT; r++) {
-        const uint32_t j = (uint32_t)r * BT + threadIdx.x;
-        const uint64_t e = e0 + j;
+        const uint64_t e = e0 + (uint32_t)r * BT + t;
         e_win[r] = false;
         e_glo[r] = 0;
-        own[r] = 0;
         e_col[r] = 0;
         e_list[r] = 0;
         e_loc[r] = 0;
-        x[r] = 0;
+        gi[r] = 0;
+        mul[r] = 0;
         if (e >= e_end) continue;
         uint32_t lo = 0, hi = nused;
         while (hi - lo > 1) {
@@ -862,8 +876,8 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
             }
             e_list[r] = q;
             e_loc[r] = (uint32_t)local;
-            x[r] = (q == 0 ? a.bcol : a.arow)[s_lo[b + q] + local];
-            own[r] = sat_mul((q == 0 ? a.bval : a.aval)[s_lo[b + q] + local], s_mul[b + q]);
+            gi[r] = s_lo[b + q] + local;
+            mul[r] = s_mul[b + q];
         } else {
             uint64_t glo = i0 + lo, ghi = a.n;  // last i with off[i] <= e
             while (ghi - glo > 1) {
@@ -872,97 +886,91 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
                 else ghi = mid;
             }
             e_glo[r] = glo;
-            const uint32_t c = col_of(a, glo);
+            const uint32_t cc = col_of(a, glo);
             uint64_t local = e - off[glo];
             uint32_t q = 0;
-            ListRef L = list_of(a, c, 0);
+            ListRef L = list_of(a, cc, 0);
             while (local >= L.len) {
                 local -= L.len;
                 q++;
-                L = list_of(a, c, q);
+                L = list_of(a, cc, q);
             }
             e_list[r] = q;
             e_loc[r] = (uint32_t)local;
-            x[r] = L.row[local];
-            own[r] = sat_mul(L.val[local], L.mul);
+            gi[r] = (uint64_t)(L.row - (q == 0 ? a.bcol : a.arow)) + local;
+            mul[r] = (uint32_t)L.mul;
         }
-        s_x[j] = x[r];
+    }
+#pragma unroll
+    for (int r = 0; r < EPT; r++) {
+        const bool ok = e0 + (uint32_t)r * BT + t < e_end;
+        x[r] = ok ? (e_list[r] == 0 ? a.bcol : a.arow)[gi[r]] : 0u;
+        own[r] = ok ? (e_list[r] == 0 ? a.bval : a.aval)[gi[r]] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < EPT; r++) {
+        own[r] = sat_mul(own[r], mul[r]);
+        if (e0 + (uint32_t)r * BT + t < e_end) s_x[(uint32_t)r * BT + t] = x[r];
     }
     __syncthreads();
 
     // phase 2: rank
 #pragma unroll
     for (int r = 0; r < EPT; r++) {
-        const uint64_t e = e0 + (uint32_t)r * BT + threadIdx.x;
+        const uint64_t e = e0 + (uint32_t)r * BT + t;
         if (e >= e_end) continue;
         const uint32_t xs = x[r], s = e_list[r];
         uint64_t rank = e_loc[r];
         bool is_head = true;
-        uint64_t sum = 0;
         uint64_t start;
         if (e_win[r]) {
-            const uint32_t lo = e_col[r], b = s_lbase[lo], k = s_lbase[lo + 1] - b;
+            const uint32_t lo = e_col[r], b = s_lbase[lo], kk = s_lbase[lo + 1] - b;
             start = s_off[lo];
-            sum = own[r];
-            uint64_t lstart = start;  // first entry of list t
-            for (uint32_t t = 0; t < k; t++) {
-                const uint32_t l = s_len[b + t];
-                if (t != s) {
-                    uint32_t lt;
-                    bool has;
-                    if (lstart >= e0 && lstart + l <= e_end) {  // list t is staged
-                        const uint32_t* rt = s_x + (lstart - e0);
-                        lt = count_lt(rt, l, xs);
-                        has = lt < l && rt[lt] == xs;
-                    } else {
-                        const uint32_t* rt = (t == 0 ? a.bcol : a.arow) + s_lo[b + t];
-                        lt = count_lt(rt, l, xs);
-                        has = lt < l && rt[lt] == xs;
-                    }
-                    if (t < s) {
-                        rank += lt + (has ? 1u : 0u);
-                        is_head = is_head && !has;
-                    } else {
-                        rank += lt;
-                        if (has) sum = sat_add(sum, sat_mul((t == 0 ? a.bval : a.aval)[s_lo[b + t] + lt], s_mul[b + t]));
+            uint64_t lstart = start;  // first entry of list q
+            for (uint32_t q = 0; q < kk; q++) {
+                const uint32_t l = s_len[b + q];
+                if (q != s) {
+                    const uint32_t* rt = (lstart >= e0 && lstart + l <= e_end)
+                                             ? s_x + (lstart - e0)  // list q is staged
+                                             : (q == 0 ? a.bcol : a.arow) + s_lo[b + q];
+                    const uint32_t lt = count_lt(rt, l, xs);
+                    rank += lt;
+                    if (q < s && lt < l && rt[lt] == xs) {
+                        rank++;
+                        is_head = false;
                     }
                 }
                 lstart += l;
             }
         } else {
             const uint64_t glo = e_glo[r];
-            const uint32_t c = col_of(a, glo);
-            const uint32_t k = num_lists(a, c);
+            const uint32_t cc = col_of(a, glo);
+            const uint32_t kk = num_lists(a, cc);
             start = off[glo];
-            const ListRef L = list_of(a, c, s);
-            sum = own[r];
-            for (uint32_t t = 0; t < k; t++) {
-                if (t == s) continue;
-                const ListRef M = list_of(a, c, t);
+            for (uint32_t q = 0; q < kk; q++) {
+                if (q == s) continue;
+                const ListRef M = list_of(a, cc, q);
                 const uint32_t lt = count_lt(M.row, (uint32_t)M.len, xs);
-                const bool has = lt < M.len && M.row[lt] == xs;
-                if (t < s) {
-                    rank += lt + (has ? 1u : 0u);
-                    is_head = is_head && !has;
-                } else {
-                    rank += lt;
-                    if (has) sum = sat_add(sum, sat_mul(M.val[lt], M.mul));
+                rank += lt;
+                if (q < s && lt < M.len && M.row[lt] == xs) {
+                    rank++;
+                    is_head = false;
                 }
             }
         }
         const uint64_t p = start + rank;
         // bit 0: run head; bit 1: the column's first position (its offset is read back per column)
         head[p] = (uint8_t)((is_head ? 1u : 0u) | (rank == 0 ? 2u : 0u));
-        if (is_head) {
-            hrow[p] = xs;
-            hval[p] = sum;
-        }
+        hval[p] = own[r];
+        if (is_head) hrow[p] = xs;
     }
 }
 
 
 // Run heads per tile of the head flags, then (with the tile offsets
-// scanned) each head's row and count written at base + (heads before it),
+// scanned) each head's row and its run's summed count (the head's and those
+// of the equal rows that follow it, saturating) written at
+// base + (heads before it),
 // and that prefix into hp at every column's first position (the only
 // positions read back; an empty column's offset is the next column's, or
 // T, whose prefix the scan writes).  A tile is 2048 positions; wave w
@@ -1002,12 +1010,21 @@ __global__ __launch_bounds__(BT) void k_head_emit(const uint8_t* __restrict__ he
     const int lane = lane_id(), w = (int)threadIdx.x / WAVE;
     const uint64_t lt = (1ull << lane) - 1ull;
     const uint64_t b0 = (uint64_t)blockIdx.x * HT_TILE + (uint64_t)w * HT_WAVE;
-    uint64_t mask[HT_R];
+    uint64_t mask[HT_R], v0[HT_R];
+    uint32_t hr[HT_R], hb[HT_R];
     uint32_t cnt = 0, first = 0;  // first: bit r set when position r of this lane starts a column
+    // every position's flags, count and row (rows are read for non-heads
+    // too, and ignored), all loads issued before any is used
 #pragma unroll
     for (int r = 0; r < HT_R; r++) {
         const uint64_t j = b0 + (uint64_t)r * WAVE + lane;
-        const uint32_t h = j < T ? head[j] : 0u;
+        hb[r] = j < T ? head[j] : 0u;
+        v0[r] = j < T ? hval[j] : 0ull;
+        hr[r] = j < T ? hrow[j] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < HT_R; r++) {
+        const uint32_t h = hb[r];
         mask[r] = __ballot(h & 1u);
         first |= (h >> 1 & 1u) << r;
         cnt += (uint32_t)__popcll(mask[r]);
@@ -1020,11 +1037,49 @@ __global__ __launch_bounds__(BT) void k_head_emit(const uint8_t* __restrict__ he
     for (int r = 0; r < HT_R; r++) {
         const uint64_t j = b0 + (uint64_t)r * WAVE + lane;
         const uint64_t p = ex + (uint64_t)__popcll(mask[r] & lt);
+        uint64_t vn[3];  // the next three positions' counts
+#pragma unroll
+        for (int q = 0; q < 3; q++) vn[q] = __shfl_down(v0[r], (unsigned)(q + 1), WAVE);
         if (j < T) {
             if ((first >> r) & 1u) hp[j] = p;  // only column starts are read back
             if ((mask[r] >> lane) & 1ull) {
-                orow[base + p] = hrow[j];
-                oval[base + p] = hval[j];
+                // the run: this head and the positions up to the next head (a
+                // column's first position is a head, so runs stay in their
+                // column), found in this wave's flags; a run reaching the end
+                // of the wave's positions continues in global memory
+                uint64_t m = 0;  // positions after j in the run
+                bool open = true;
+                const uint64_t above = lane == WAVE - 1 ? 0ull : mask[r] >> (lane + 1);
+                if (above) {
+                    m = (uint64_t)__builtin_ctzll(above);
+                    open = false;
+                } else {
+                    m = (uint64_t)(WAVE - 1 - lane);
+                }
+#pragma unroll
+                for (int rr = r + 1; rr < HT_R; rr++) {
+                    if (open) {
+                        if (mask[rr]) {
+                            m += (uint64_t)__builtin_ctzll(mask[rr]);
+                            open = false;
+                        } else {
+                            m += WAVE;
+                        }
+                    }
+                }
+                if (m > T - 1 - j) {
+                    m = T - 1 - j;
+                    open = false;
+                }
+                const uint64_t inr = m < (uint64_t)(WAVE - 1 - lane) ? m : (uint64_t)(WAVE - 1 - lane);
+                uint64_t sum = v0[r];
+#pragma unroll
+                for (int q = 0; q < 3; q++)
+                    if ((uint64_t)q < inr) sum = sat_add(sum, vn[q]);
+                for (uint64_t q = inr < 3 ? inr : 3; q < m; q++) sum = sat_add(sum, hval[j + 1 + q]);
+                for (uint64_t f = j + 1 + m; open && f < T && !(head[f] & 1u); f++) sum = sat_add(sum, hval[f]);
+                orow[base + p] = hr[r];
+                oval[base + p] = sum;
             }
         }
         ex += (uint64_t)__popcll(mask[r]);

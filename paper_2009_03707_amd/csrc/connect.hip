@@ -118,6 +118,8 @@ uint64_t counts_to_rowptr(ms_ctx* c, const uint32_t* cnt, uint64_t n, uint64_t* 
 // again after the sort instead; otherwise values move as a separate 64-bit
 // payload.  row_inv: the inverse of row_map (needed for escapes).
 constexpr uint64_t NO_BOUND = ~0ull;
+// levels whose columns average fewer entries than this list every entry's column for the rank kernel
+constexpr uint64_t RANK_COLOF_AVG = 6;
 void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const uint32_t* row_map = nullptr,
                uint64_t vmax_bound = NO_BOUND, bool rows_sorted = false, const uint32_t* row_inv = nullptr) {
     uint64_t nnz = (uint64_t)in.nnz;
@@ -501,6 +503,15 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
         uint8_t* head = buf<uint8_t>(c, "pe.head", T);
         hp = buf<uint64_t>(c, "pe.hp", T + 1);
         uint32_t* bstart = buf<uint32_t>(c, "pe.bstart", rank_blocks(T));
+        // levels of short columns (fewer than RANK_COLOF_AVG entries each on
+        // average) have many entries beyond a rank block's column window:
+        // their columns are listed once instead of searched per entry
+        const uint32_t* colof = nullptr;
+        if (T > 0 && T < RANK_COLOF_AVG * n) {
+            uint32_t* cb = buf<uint32_t>(c, "pe.colof", T);
+            check(c, launch_expand_rows(ub, n, nullptr, cb, s), "entry columns");
+            colof = cb;
+        }
         const bool timed = c->timing && T > 0;
         if (timed) {
             while (c->rank_ev.size() < 2 * (c->rank_used + 1)) {
@@ -510,7 +521,7 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
             }
             check(c, hipEventRecord(c->rank_ev[2 * c->rank_used], s), "event record");
         }
-        check(c, launch_entry_rank(m, ub, T, bstart, hrow, hval, head, s), "entry rank");
+        check(c, launch_entry_rank(m, ub, T, bstart, colof, hrow, hval, head, s), "entry rank");
         if (timed) {
             check(c, hipEventRecord(c->rank_ev[2 * c->rank_used + 1], s), "event record");
             c->rank_used++;

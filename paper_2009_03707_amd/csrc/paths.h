@@ -49,10 +49,11 @@ hipError_t launch_merge(const MergeLaunch& m, const uint8_t* flag, const uint32_
 // column's range (col_off/col_len by column id and/or a CSR row pointer)
 // from hp[off[i]].
 hipError_t launch_entry_ub(const MergeLaunch& m, uint64_t* ub, hipStream_t s);
-// bstart: scratch of rank_blocks(T) entries (the first column of each rank block)
+// bstart: scratch of rank_blocks(T) entries (the first column of each rank
+// block); colof: null, or the level column of every entry (T entries)
 size_t rank_blocks(uint64_t T);
-hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* bstart, uint32_t* hrow,
-                             uint64_t* hval, uint8_t* head, hipStream_t s);
+hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* bstart,
+                             const uint32_t* colof, uint32_t* hrow, uint64_t* hval, uint8_t* head, hipStream_t s);
 hipError_t launch_entry_cols(const MergeLaunch& m, const uint64_t* off, const uint64_t* hp, uint64_t base,
                              uint64_t* col_off, uint32_t* col_len, uint64_t* rowptr, hipStream_t s);
 // Copies column i from src_off[i] to dst_off[i] (dst_off: n + 1 entries).

@@ -756,7 +756,9 @@ __global__ __launch_bounds__(BT) void k_block_start(const uint64_t* __restrict__
 // entry writes its own scaled count at its merged position, the head of a
 // run of equal rows (no earlier list holds the row) also its row; the head
 // scan sums each run.  Entries of columns beyond the staged window read
-// their metadata from global memory (same result).
+// their metadata from global memory (same result), their column from
+// colof (every entry's column, for levels of short columns, where many
+// entries lie beyond the window) or else by binary search in off.
 //
 // The kernel is bound by the latency of dependent loads, so each step
 // issues all of a thread's independent loads before it uses any: the
@@ -769,7 +771,8 @@ static_assert(CW == BT, "one window column per thread");
 constexpr int RP = 3;  // predecessors whose descriptors are loaded together
 
 __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* __restrict__ off, uint64_t T,
-                                                   const uint32_t* __restrict__ bstart, uint32_t* __restrict__ hrow,
+                                                   const uint32_t* __restrict__ bstart,
+                                                   const uint32_t* __restrict__ colof, uint32_t* __restrict__ hrow,
                                                    uint64_t* __restrict__ hval, uint8_t* __restrict__ head) {
     __shared__ uint64_t s_off[CW + 1];
     __shared__ uint32_t s_lbase[CW + 1];
@@ -880,10 +883,14 @@ __global__ __launch_bounds__(BT) void k_entry_rank(MergeArgs a, const uint64_t* 
             mul[r] = s_mul[b + q];
         } else {
             uint64_t glo = i0 + lo, ghi = a.n;  // last i with off[i] <= e
-            while (ghi - glo > 1) {
-                uint64_t mid = (glo + ghi) >> 1;
-                if (off[mid] <= e) glo = mid;
-                else ghi = mid;
+            if (colof) {
+                glo = colof[e];
+            } else {
+                while (ghi - glo > 1) {
+                    uint64_t mid = (glo + ghi) >> 1;
+                    if (off[mid] <= e) glo = mid;
+                    else ghi = mid;
+                }
             }
             e_glo[r] = glo;
             const uint32_t cc = col_of(a, glo);
@@ -1166,14 +1173,14 @@ hipError_t launch_entry_ub(const MergeLaunch& m, uint64_t* ub, hipStream_t s) {
 
 size_t rank_blocks(uint64_t T) { return (T + EPB - 1) / EPB; }
 
-hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* bstart, uint32_t* hrow,
-                             uint64_t* hval, uint8_t* head, hipStream_t s) {
+hipError_t launch_entry_rank(const MergeLaunch& m, const uint64_t* off, uint64_t T, uint32_t* bstart,
+                             const uint32_t* colof, uint32_t* hrow, uint64_t* hval, uint8_t* head, hipStream_t s) {
     if (T == 0) return hipSuccess;
     hipLaunchKernelGGL(k_block_start, dim3(grid_blocks(m.n, BT)), dim3(BT), 0, s, off, m.n, bstart);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_entry_rank, dim3(grid_blocks(T, EPB)), dim3(BT), 0, s, to_args(m), off, T,
-                       (const uint32_t*)bstart, hrow, hval, head);
+                       (const uint32_t*)bstart, colof, hrow, hval, head);
     return hipGetLastError();
 }
 

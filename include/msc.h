@@ -302,7 +302,8 @@ typedef struct {
 typedef struct {
     double gradient_ms;  /* gradient kernel */
     double critical_ms;  /* critical counts, scan, compaction */
-    double extrema_ms;   /* pointer jumping, M10 / M32 and transposes */
+    double extrema_ms;   /* pointer set-up and critical-cell labels (the rest of the
+                            saddle-extremum arcs overlaps later stages: extrema_side_ms) */
     double bfs_ms;       /* saddle-saddle reachability */
     double minor_ms;     /* junction numbering, DAG minor, minor matrices */
     double paths_ms;     /* iterated products, P, M21 and transpose */
@@ -319,6 +320,11 @@ typedef struct {
     /* graphs of the batch front captured / replayed by this context since it
      * was created (not reset by enabling timing) */
     int64_t graph_captures, graph_replays;
+    /* pointer jumping, M10 / M32, their transposes and the manifold labels,
+     * queued by a helper thread on a second stream of the context once the
+     * search is queued, so that they run beside the minor and the path
+     * counting (their own span; not part of total_ms's stages) */
+    double extrema_side_ms;
 } ms_timing;
 
 /* Enables (1) or disables (0) timing; enabling resets the accumulators. */

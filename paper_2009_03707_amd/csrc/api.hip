@@ -122,7 +122,7 @@ void critical_finish(ms_ctx* c, const float* f, const float* const* fptr, const 
 }
 
 // Records the context's critical-record buffers (cx_crit_*) hold now.
-uint64_t crit_record_capacity(const ms_ctx* c) {
+uint64_t crit_record_capacity(ms_ctx* c) {
     size_t a = buf_elems<uint32_t>(c, "cx_crit_id"), b = buf_elems<uint8_t>(c, "cx_crit_index");
     size_t d = buf_elems<float>(c, "cx_crit_value"), e = buf_elems<uint32_t>(c, "cx_crit_vmax");
     size_t m = a < b ? a : b;
@@ -237,6 +237,15 @@ void ms_ctx_destroy(ms_ctx* ctx) {
     for (auto& e : ctx->rank_ev) (void)hipEventDestroy(e);
     if (ctx->front_exec) (void)hipGraphExecDestroy(ctx->front_exec);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->side_stream) {
+        (void)hipStreamSynchronize(ctx->side_stream);
+        (void)hipStreamDestroy(ctx->side_stream);
+    }
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    for (auto& e : ctx->side_ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->h_side) (void)hipHostFree(ctx->h_side);
     delete ctx;
 }
 
@@ -307,6 +316,8 @@ ms_status ms_ctx_set_timing(ms_ctx* ctx, int enable) {
     ctx->rank_ms = 0;
     ctx->rank_launches = ctx->rank_entries = ctx->rank_heads = 0;
     ctx->rank_used = 0;
+    ctx->side_ms = 0;
+    ctx->side_timed = false;
     API_END
 }
 
@@ -319,6 +330,7 @@ ms_status ms_ctx_get_timing(ms_ctx* ctx, ms_timing* out) {
     out->minor_ms = ctx->acc_ms[4];
     out->paths_ms = ctx->acc_ms[5];
     out->total_ms = ctx->acc_ms[6];
+    out->extrema_side_ms = ctx->side_ms;
     out->calls = ctx->calls;
     out->allocations = ctx->allocations;
     out->workspace_bytes = ctx->ws_bytes;
@@ -405,6 +417,12 @@ static void accumulate_timing(ms_ctx* ctx) {
     float tot = 0;
     check(ctx, hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[6]), "event elapsed");
     ctx->acc_ms[6] += tot;
+    if (ctx->side_timed) {  // the main stream waited for the side work before ev[6]
+        float ms = 0;
+        check(ctx, hipEventElapsedTime(&ms, ctx->side_ev[0], ctx->side_ev[1]), "event elapsed");
+        ctx->side_ms += ms;
+        ctx->side_timed = false;
+    }
     ctx->calls++;
     for (size_t i = 0; i < ctx->rank_used; i++) {
         float ms = 0;

@@ -6,6 +6,8 @@
 #include "ctx.h"
 #include "paths.h"
 
+#include <exception>
+#include <thread>
 #include <vector>
 
 namespace msc {
@@ -93,8 +95,8 @@ uint64_t read_u64(ms_ctx* c, const uint64_t* d) { return readback(c, d, 1)[0]; }
 
 void check_err_flag(ms_ctx* c, int* d_err, const char* stage) {
     uint64_t* slot = buf<uint64_t>(c, "err_slot", 1);
-    check(c, hipMemsetAsync(slot, 0, sizeof(uint64_t), c->stream), "memset");
-    check(c, hipMemcpyAsync(slot, d_err, sizeof(int), hipMemcpyDeviceToDevice, c->stream), "copy");
+    check(c, hipMemsetAsync(slot, 0, sizeof(uint64_t), cur_stream(c)), "memset");
+    check(c, hipMemcpyAsync(slot, d_err, sizeof(int), hipMemcpyDeviceToDevice, cur_stream(c)), "copy");
     uint64_t v = read_u64(c, slot);
     if (v) fail(c, MS_ERR_INTERNAL, std::string("consistency check failed in ") + stage + " (flag " + std::to_string(v) + ")");
 }
@@ -102,7 +104,7 @@ void check_err_flag(ms_ctx* c, int* d_err, const char* stage) {
 // Row counts (u32) -> rowptr (exclusive scan, total in rowptr[n]); returns nnz.
 uint64_t counts_to_rowptr(ms_ctx* c, const uint32_t* cnt, uint64_t n, uint64_t* rowptr) {
     uint64_t* tmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(n) + 1);
-    check(c, scan_excl_u32_to_u64(cnt, rowptr, n, tmp, rowptr + n, c->stream), "scan");
+    check(c, scan_excl_u32_to_u64(cnt, rowptr, n, tmp, rowptr + n, cur_stream(c)), "scan");
     return read_u64(c, rowptr + n);
 }
 
@@ -125,7 +127,7 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const
     uint64_t nnz = (uint64_t)in.nnz;
     out = csr_buf(c, name, (uint64_t)in.ncols, (uint64_t)in.nrows, nnz);
     if (nnz == 0) {
-        check(c, hipMemsetAsync(out.rowptr, 0, sizeof(int64_t) * ((uint64_t)in.ncols + 1), c->stream), "memset");
+        check(c, hipMemsetAsync(out.rowptr, 0, sizeof(int64_t) * ((uint64_t)in.ncols + 1), cur_stream(c)), "memset");
         return;
     }
     uint32_t* rows = buf<uint32_t>(c, "tr.rows", nnz);
@@ -145,39 +147,39 @@ void transpose(ms_ctx* c, const ms_csr& in, const char* name, ms_csr& out, const
             packed = escapes = true;
         } else {
             uint64_t* d_max = buf<uint64_t>(c, "tr.max", 1);
-            check(c, launch_max_u64((const uint64_t*)in.val, nnz, d_max, c->stream), "max");
+            check(c, launch_max_u64((const uint64_t*)in.val, nnz, d_max, cur_stream(c)), "max");
             packed = read_u64(c, d_max) < (1ull << vbits);
         }
     }
     const uint32_t* keys = nullptr;
     if (packed) {
-        check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, row_map, rows, c->stream,
+        check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, row_map, rows, cur_stream(c),
                                     (const uint64_t*)in.val, vbits),
               "expand rows");
         Unpack up{vbits, out.col, (uint64_t*)out.val};
         if (escapes) {
             up.esc = buf<uint32_t>(c, "tr.esc", nnz);
             up.nesc = (unsigned long long*)buf<uint64_t>(c, "tr.nesc", 1);
-            check(c, launch_set_u64((uint64_t*)up.nesc, 0, c->stream), "escape count");
+            check(c, launch_set_u64((uint64_t*)up.nesc, 0, cur_stream(c)), "escape count");
         }
-        check(c, radix_transpose_packed_u32(in.col, rows, ka, va, kb, vb, nnz, kbits, tmp, up, &keys, c->stream),
+        check(c, radix_transpose_packed_u32(in.col, rows, ka, va, kb, vb, nnz, kbits, tmp, up, &keys, cur_stream(c)),
               "sort");
         if (escapes)
             check(c, launch_escape_fix(up.esc, up.nesc, keys, out.col, (const uint64_t*)in.rowptr, in.col,
                                        (const uint64_t*)in.val, row_map ? row_inv : nullptr, (uint64_t*)out.val,
-                                       c->stream),
+                                       cur_stream(c)),
                   "escape fix");
     } else {
         uint64_t* wa = buf<uint64_t>(c, "tr.wa", nnz);
         uint64_t* wb = buf<uint64_t>(c, "tr.wb", nnz);
-        check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, row_map, rows, c->stream),
+        check(c, launch_expand_rows((const uint64_t*)in.rowptr, (uint64_t)in.nrows, row_map, rows, cur_stream(c)),
               "expand rows");
         check(c, radix_transpose_u32(in.col, rows, (const uint64_t*)in.val, ka, va, kb, vb, wa, wb, nnz, kbits, tmp,
-                                     out.col, (uint64_t*)out.val, &keys, c->stream),
+                                     out.col, (uint64_t*)out.val, &keys, cur_stream(c)),
               "sort");
     }
     uint64_t* gtmp = buf<uint64_t>(c, "tr.gaps", key_bounds_tmp_elems(nnz, (uint64_t)in.ncols));
-    check(c, launch_key_bounds(keys, nnz, (uint64_t)in.ncols, (uint64_t*)out.rowptr, gtmp, c->stream), "bounds");
+    check(c, launch_key_bounds(keys, nnz, (uint64_t)in.ncols, (uint64_t*)out.rowptr, gtmp, cur_stream(c)), "bounds");
 }
 
 // Sort a COO by (row, col) and merge repeats; result in buffer set `name`.
@@ -196,18 +198,18 @@ Coo sort_merge(ms_ctx* c, const Coo& in, uint64_t nrows, uint64_t ncols, const c
     uint32_t* va = buf<uint32_t>(c, "sm.va", n);
     uint32_t* vb = buf<uint32_t>(c, "sm.vb", n);
     uint64_t* tmp = buf<uint64_t>(c, "sm.tmp", radix_tmp_elems(n));
-    check(c, launch_make_keys(in.row, in.col, n, cb, ka, va, c->stream), "keys");
+    check(c, launch_make_keys(in.row, in.col, n, cb, ka, va, cur_stream(c)), "keys");
     bool in_b = false;
-    check(c, radix_sort_u64(ka, va, kb, vb, n, cb + rb, tmp, &in_b, c->stream), "sort");
+    check(c, radix_sort_u64(ka, va, kb, vb, n, cb + rb, tmp, &in_b, cur_stream(c)), "sort");
     const uint64_t* keys = in_b ? kb : ka;
     const uint32_t* perm = in_b ? vb : va;
     uint32_t* heads = buf<uint32_t>(c, "sm.heads", n);
     uint64_t* pos = buf<uint64_t>(c, "sm.pos", n + 1);
-    check(c, launch_heads(keys, n, heads, c->stream), "heads");
+    check(c, launch_heads(keys, n, heads, cur_stream(c)), "heads");
     uint64_t m = counts_to_rowptr(c, heads, n, pos);
     out = coo_buf(c, name, m);
     out.n = m;
-    check(c, launch_merge_runs(keys, perm, in.val, n, pos, cb, out.row, out.col, out.val, c->stream), "merge");
+    check(c, launch_merge_runs(keys, perm, in.val, n, pos, cb, out.row, out.col, out.val, cur_stream(c)), "merge");
     return out;
 }
 
@@ -219,14 +221,14 @@ uint64_t esc_expand(ms_ctx* c, const Coo& x, const ms_csr& y, uint64_t at, Coo& 
     if (x.n > 0) {
         uint32_t* pc = buf<uint32_t>(c, "esc.pc", x.n);
         uint64_t* poff = buf<uint64_t>(c, "esc.poff", x.n + 1);
-        check(c, launch_esc_count(x.col, x.n, (const uint64_t*)y.rowptr, pc, c->stream), "esc count");
+        check(c, launch_esc_count(x.col, x.n, (const uint64_t*)y.rowptr, pc, cur_stream(c)), "esc count");
         t = counts_to_rowptr(c, pc, x.n, poff);
         prod.row = buf_keep<uint32_t>(c, "prod.row", at + t + reserve_extra, at);
         prod.col = buf_keep<uint32_t>(c, "prod.col", at + t + reserve_extra, at);
         prod.val = buf_keep<uint64_t>(c, "prod.val", at + t + reserve_extra, at);
         if (t)
             check(c, launch_esc_expand(x.row, x.col, x.val, x.n, poff, (const uint64_t*)y.rowptr, y.col, y.val,
-                                       prod.row + at, prod.col + at, prod.val + at, c->stream),
+                                       prod.row + at, prod.col + at, prod.val + at, cur_stream(c)),
                   "esc expand");
     } else {
         prod.row = buf_keep<uint32_t>(c, "prod.row", at + reserve_extra, at);
@@ -240,14 +242,14 @@ uint64_t esc_expand(ms_ctx* c, const Coo& x, const ms_csr& y, uint64_t at, Coo& 
 void coo_to_csr(ms_ctx* c, const Coo& in, uint64_t nrows, uint64_t ncols, const char* name, ms_csr& out) {
     out = csr_buf(c, name, nrows, ncols, in.n);
     uint32_t* h = buf<uint32_t>(c, "cc.hist", nrows + 1);
-    check(c, hipMemsetAsync(h, 0, sizeof(uint32_t) * (nrows + 1), c->stream), "memset");
-    check(c, launch_hist(in.row, in.n, h, c->stream), "hist");
+    check(c, hipMemsetAsync(h, 0, sizeof(uint32_t) * (nrows + 1), cur_stream(c)), "memset");
+    check(c, launch_hist(in.row, in.n, h, cur_stream(c)), "hist");
     uint64_t* stmp = buf<uint64_t>(c, "scan_tmp", scan_tmp_elems(nrows) + 1);
-    check(c, scan_excl_u32_to_u64(h, (uint64_t*)out.rowptr, nrows, stmp, (uint64_t*)out.rowptr + nrows, c->stream),
+    check(c, scan_excl_u32_to_u64(h, (uint64_t*)out.rowptr, nrows, stmp, (uint64_t*)out.rowptr + nrows, cur_stream(c)),
           "scan");
     if (in.n) {
-        check(c, hipMemcpyAsync(out.col, in.col, 4 * in.n, hipMemcpyDeviceToDevice, c->stream), "copy");
-        check(c, hipMemcpyAsync(out.val, in.val, 8 * in.n, hipMemcpyDeviceToDevice, c->stream), "copy");
+        check(c, hipMemcpyAsync(out.col, in.col, 4 * in.n, hipMemcpyDeviceToDevice, cur_stream(c)), "copy");
+        check(c, hipMemcpyAsync(out.val, in.val, 8 * in.n, hipMemcpyDeviceToDevice, cur_stream(c)), "copy");
     }
 }
 
@@ -257,7 +259,7 @@ Coo csr_as_coo(ms_ctx* c, const ms_csr& m, const char* rows_name) {
     o.row = buf<uint32_t>(c, rows_name, o.n);
     o.col = m.col;
     o.val = m.val;
-    check(c, launch_expand_rows((const uint64_t*)m.rowptr, (uint64_t)m.nrows, nullptr, o.row, c->stream),
+    check(c, launch_expand_rows((const uint64_t*)m.rowptr, (uint64_t)m.nrows, nullptr, o.row, cur_stream(c)),
           "expand rows");
     return o;
 }
@@ -267,7 +269,7 @@ Coo csr_as_coo(ms_ctx* c, const ms_csr& m, const char* rows_name) {
 // P = D + A* B*.  Products are expand-sort-compress.  Writes M21 and M21t.
 void paths_power(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, const ms_csr& D, uint64_t S1,
                  uint64_t S2, uint64_t J, ms_arcs* out) {
-    hipStream_t s = c->stream;
+    hipStream_t s = cur_stream(c);
     ms_stats& st = out->stats;
     const uint64_t nD = (uint64_t)D.nnz;
     // Each iteration adds the current frontier of 1-saddle -> junction path
@@ -325,7 +327,7 @@ void paths_power(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
 // discarded).
 bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, const ms_csr& D, uint64_t S1,
                  uint64_t S2, uint64_t J, ms_arcs* out, int* d_err) {
-    hipStream_t s = c->stream;
+    hipStream_t s = cur_stream(c);
     ms_stats& st = out->stats;
     ms_csr At, Bt, Bst, Dt;
     // minor multiplicities are at most 4: at most four paths leave a source
@@ -421,7 +423,7 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
 // 2-saddles).  No column size limit.
 void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, const ms_csr& D, uint64_t S1,
                  uint64_t S2, uint64_t J, ms_arcs* out, int* d_err) {
-    hipStream_t s = c->stream;
+    hipStream_t s = cur_stream(c);
     ms_stats& st = out->stats;
     // ---- topological numbering --------------------------------------------
     uint32_t* indeg = buf<uint32_t>(c, "pr.indeg", J + 1);
@@ -561,27 +563,14 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     st.products = (int64_t)(products + T);
     if (c->timing) c->rank_heads += st.nnz_astar + m21.nnz;
 }
-}  // namespace
-
-void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t* crit, const int64_t cnt[4],
-                  ms_arcs* out) {
-    memset(out, 0, sizeof(*out));
-    c->rank_used = 0;  // rank timing pairs of an earlier call that were not accumulated
-    hipStream_t s = c->stream;
-    const uint64_t S0 = (uint64_t)cnt[0], S1 = (uint64_t)cnt[1], S2 = (uint64_t)cnt[2], S3 = (uint64_t)cnt[3];
-    const uint32_t* s1 = crit + S0;
-    const uint32_t* s2 = crit + S0 + S1;
+// The saddle-extremum arcs: pointer jumping to the extremum every vertex and
+// every 3-cell flows to (Section 3.4), M10 and M32 (Section 3.5,
+// "Saddle-Extrema arcs"), the manifold labels and the two transposes.
+void extremum_arcs(ms_ctx* c, const Geo& g, const uint32_t* s1, const uint32_t* s2, uint64_t S0, uint64_t S1,
+                   uint64_t S2, uint64_t S3, uint32_t* Pv, uint32_t* Pc, ms_arcs* out, ms_stats& st) {
+    hipStream_t s = cur_stream(c);
     int* d_err = buf<int>(c, "cn_err", 1);
     check(c, hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
-    ms_stats& st = out->stats;
-
-    // ---- saddle-extremum arcs ------------------------------------------------
-    uint32_t* Pv = buf<uint32_t>(c, "pv", g.nv);
-    uint32_t* Pc = buf<uint32_t>(c, "pc", g.nv);
-    uint32_t* label = buf<uint32_t>(c, "cell_label", (uint64_t)6 * g.nv);  // planes of edges and quads
-    check(c, launch_pj_init(grad, g, Pv, Pc, d_err, s), "pj init");
-    check(c, launch_label(crit, cnt, grad, g, Pv, Pc, label, d_err, s), "label");
-    check_err_flag(c, d_err, "critical list labelling");
     int* d_chg = (int*)buf<uint64_t>(c, "pj_changed", 32);  // 64 flag words
     for (int which = 0; which < 2; which++) {
         uint32_t* P = which == 0 ? Pv : Pc;
@@ -625,6 +614,110 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
         transpose(c, m10, "m10t", out->m10t, nullptr, 2);
         transpose(c, m32t, "m32", out->m32, nullptr, 2);
     }
+}
+
+void ensure_side(ms_ctx* c) {
+    if (!c->side_stream) check(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking), "stream create");
+    if (!c->ev_fork) check(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "event create");
+    if (!c->ev_join) check(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "event create");
+    for (auto& e : c->side_ev)
+        if (!e) check(c, hipEventCreate(&e), "event create");
+    if (!c->h_side) {
+        check(c, hipHostMalloc((void**)&c->h_side, HOST_SCRATCH_WORDS * sizeof(uint64_t),
+                               hipHostMallocMapped | hipHostMallocCoherent),
+              "host allocation");
+        check(c, hipHostGetDevicePointer((void**)&c->h_side_dev, c->h_side, 0), "host pointer");
+    }
+}
+
+// Work of one call queued from a helper thread on the context's side stream
+// after everything the calling thread queued so far (event ev_fork), with
+// its own readback scratch, buffer names and error text.  finish() joins
+// the thread, rethrows its failure and orders the calling thread's stream
+// after the helper's work (event ev_join); the destructor joins on the
+// error paths of the calling thread.
+class SideTask {
+  public:
+    explicit SideTask(ms_ctx* c) : c_(c) {}
+    SideTask(const SideTask&) = delete;
+    SideTask& operator=(const SideTask&) = delete;
+    template <class F>
+    void start(hipStream_t s, F f) {
+        ensure_side(c_);
+        check(c_, hipEventRecord(c_->ev_fork, s), "event record");
+        c_->side_timed = c_->timing;
+        th_ = std::thread([this, f]() {
+            t_ctx = ThreadCtx{c_->side_stream, c_->h_side, c_->h_side_dev, "side.", &err_};
+            try {
+                check(c_, hipSetDevice(c_->device), "set device");
+                check(c_, hipStreamWaitEvent(c_->side_stream, c_->ev_fork, 0), "stream wait");
+                if (c_->side_timed) check(c_, hipEventRecord(c_->side_ev[0], c_->side_stream), "event record");
+                f();
+                if (c_->side_timed) check(c_, hipEventRecord(c_->side_ev[1], c_->side_stream), "event record");
+                check(c_, hipEventRecord(c_->ev_join, c_->side_stream), "event record");
+            } catch (const Fail& e) {
+                st_ = e.st;
+            } catch (const std::exception& e) {
+                st_ = MS_ERR_INTERNAL;
+                err_ = std::string("internal error: ") + e.what();
+            } catch (...) {
+                st_ = MS_ERR_INTERNAL;
+                err_ = "internal error";
+            }
+            t_ctx = ThreadCtx{};
+        });
+    }
+    void finish(hipStream_t s) {
+        th_.join();
+        if (st_ != MS_OK) {
+            (void)hipStreamSynchronize(c_->side_stream);
+            c_->err = err_;
+            throw Fail{st_};
+        }
+        check(c_, hipStreamWaitEvent(s, c_->ev_join, 0), "stream wait");
+    }
+    ~SideTask() {
+        if (th_.joinable()) {
+            th_.join();
+            (void)hipStreamSynchronize(c_->side_stream);
+        }
+    }
+
+  private:
+    ms_ctx* c_;
+    std::thread th_;
+    ms_status st_ = MS_OK;
+    std::string err_;
+};
+
+}  // namespace
+
+void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t* crit, const int64_t cnt[4],
+                  ms_arcs* out) {
+    memset(out, 0, sizeof(*out));
+    c->rank_used = 0;  // rank timing pairs of an earlier call that were not accumulated
+    hipStream_t s = cur_stream(c);
+    const uint64_t S0 = (uint64_t)cnt[0], S1 = (uint64_t)cnt[1], S2 = (uint64_t)cnt[2], S3 = (uint64_t)cnt[3];
+    const uint32_t* s1 = crit + S0;
+    const uint32_t* s2 = crit + S0 + S1;
+    int* d_err = buf<int>(c, "cn_err", 1);
+    check(c, hipMemsetAsync(d_err, 0, sizeof(int), s), "memset");
+    ms_stats& st = out->stats;
+
+    // ---- saddle-extremum arcs ------------------------------------------------
+    uint32_t* Pv = buf<uint32_t>(c, "pv", g.nv);
+    uint32_t* Pc = buf<uint32_t>(c, "pc", g.nv);
+    uint32_t* label = buf<uint32_t>(c, "cell_label", (uint64_t)6 * g.nv);  // planes of edges and quads
+    check(c, launch_pj_init(grad, g, Pv, Pc, d_err, s), "pj init");
+    check(c, launch_label(crit, cnt, grad, g, Pv, Pc, label, d_err, s), "label");
+    check_err_flag(c, d_err, "critical list labelling");
+    // The saddle-extremum arcs read only the gradient, the critical lists and
+    // the pointers set up above, and nothing after them reads what they
+    // write: once the search is queued, a helper thread queues them on the
+    // side stream, where they overlap the minor and the path counting queued
+    // by this thread (started before the search they slowed it about as much
+    // as they saved: both are bound by scattered memory traffic).
+    SideTask side(c);
 
     mark(c, 3);
     // ---- saddle-saddle reachability (frontier BFS) --------------------------
@@ -683,6 +776,7 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
     }
 
     mark(c, 4);
+    side.start(s, [&]() { extremum_arcs(c, g, s1, s2, S0, S1, S2, S3, Pv, Pc, out, st); });
     // ---- DAG minor ----------------------------------------------------------
     const uint64_t NS = S1 + J;
     uint8_t* out_t = buf<uint8_t>(c, "minor_t", 4 * NS);
@@ -727,6 +821,7 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
     check(c, launch_count_sat(out->m21t.val, (uint64_t)out->m21t.nnz, d_sat, s), "count saturated");
     out->n_saturated = (int64_t)read_u64(c, (const uint64_t*)d_sat);
     st.nnz_p = out->m21t.nnz;
+    side.finish(s);
 }
 
 }  // namespace msc

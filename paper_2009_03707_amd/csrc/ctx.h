@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -61,6 +62,16 @@ struct ms_ctx {
     hipGraphExec_t front_exec = nullptr;
     hipStream_t capture_stream = nullptr;
     int64_t front_captures = 0, front_replays = 0;
+    // a helper thread of connect_impl: its stream (default priority), pinned
+    // readback scratch and the events that order it against the main stream
+    hipStream_t side_stream = nullptr;
+    uint64_t* h_side = nullptr;
+    uint64_t* h_side_dev = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t side_ev[2] = {};  // the side work's span, when timing
+    bool side_timed = false;     // side_ev recorded in the current call
+    double side_ms = 0;
+    std::mutex buf_mu;  // the named buffers are looked up from both threads
 };
 
 namespace msc {
@@ -69,10 +80,27 @@ struct Fail {
     ms_status st;
 };
 
+// What a helper thread of a call overrides: the stream its work is queued
+// on, the pinned scratch its readbacks go through, a prefix that keeps its
+// scratch buffers apart from the calling thread's, and where its error text
+// goes.  Unset on the calling thread.
+struct ThreadCtx {
+    hipStream_t stream = nullptr;
+    uint64_t* h_small = nullptr;
+    uint64_t* h_small_dev = nullptr;
+    const char* prefix = nullptr;
+    std::string* err = nullptr;
+};
+inline thread_local ThreadCtx t_ctx;
+
+inline hipStream_t cur_stream(const ms_ctx* c) { return t_ctx.stream ? t_ctx.stream : c->stream; }
+inline std::string& err_text(ms_ctx* c) { return t_ctx.err ? *t_ctx.err : c->err; }
+inline std::string buf_key(const char* name) { return t_ctx.prefix ? std::string(t_ctx.prefix) + name : std::string(name); }
+
 // One workspace allocation through the context's allocator; null on failure.
 inline void* dev_alloc(ms_ctx* c, size_t bytes) {
     void* p = nullptr;
-    if (c->alloc_fn) return c->alloc_fn(c->alloc_user, bytes, (void*)c->stream);
+    if (c->alloc_fn) return c->alloc_fn(c->alloc_user, bytes, (void*)cur_stream(c));
     if (hipMalloc(&p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return nullptr;
@@ -84,9 +112,9 @@ inline void* dev_alloc(ms_ctx* c, size_t bytes) {
 // queued kernel still uses the memory whichever stream it was allocated on.
 inline void dev_free(ms_ctx* c, void* p, size_t bytes) {
     if (!p) return;
-    (void)hipStreamSynchronize(c->stream);
+    (void)hipStreamSynchronize(cur_stream(c));
     if (c->free_fn)
-        c->free_fn(c->alloc_user, p, bytes, (void*)c->stream);
+        c->free_fn(c->alloc_user, p, bytes, (void*)cur_stream(c));
     else
         (void)hipFree(p);
 }
@@ -96,7 +124,8 @@ template <typename T>
 T* buf(ms_ctx* c, const char* name, size_t count) {
     size_t bytes = count * sizeof(T);
     if (bytes == 0) bytes = sizeof(T);
-    ms_ctx::Buf& b = c->bufs[name];
+    std::lock_guard<std::mutex> lock(c->buf_mu);
+    ms_ctx::Buf& b = c->bufs[buf_key(name)];
     if (b.cap < bytes) {
         if (b.p) {
             dev_free(c, b.p, b.cap);
@@ -107,7 +136,7 @@ T* buf(ms_ctx* c, const char* name, size_t count) {
         size_t want = bytes + bytes / 4 + 256;
         b.p = dev_alloc(c, want);
         if (!b.p) {
-            c->err = std::string("device allocation of ") + std::to_string(want) + " bytes failed for " + name;
+            err_text(c) = std::string("device allocation of ") + std::to_string(want) + " bytes failed for " + name;
             throw Fail{MS_ERR_OOM};
         }
         b.cap = want;
@@ -119,8 +148,9 @@ T* buf(ms_ctx* c, const char* name, size_t count) {
 
 // Elements of T that buffer `name` holds now (0 if it was never allocated).
 template <typename T>
-size_t buf_elems(const ms_ctx* c, const char* name) {
-    auto it = c->bufs.find(name);
+size_t buf_elems(ms_ctx* c, const char* name) {
+    std::lock_guard<std::mutex> lock(c->buf_mu);
+    auto it = c->bufs.find(buf_key(name));
     return it == c->bufs.end() ? 0 : it->second.cap / sizeof(T);
 }
 
@@ -128,16 +158,17 @@ size_t buf_elems(const ms_ctx* c, const char* name) {
 template <typename T>
 T* buf_keep(ms_ctx* c, const char* name, size_t count, size_t used) {
     size_t bytes = (count ? count : 1) * sizeof(T);
-    ms_ctx::Buf& b = c->bufs[name];
+    std::lock_guard<std::mutex> lock(c->buf_mu);
+    ms_ctx::Buf& b = c->bufs[buf_key(name)];
     if (b.cap >= bytes) return (T*)b.p;
     size_t want = bytes + bytes / 2 + 256;
     void* p = dev_alloc(c, want);
     if (!p) {
-        c->err = std::string("device allocation of ") + std::to_string(want) + " bytes failed for " + name;
+        err_text(c) = std::string("device allocation of ") + std::to_string(want) + " bytes failed for " + name;
         throw Fail{MS_ERR_OOM};
     }
     if (b.p) {
-        if (used) (void)hipMemcpyAsync(p, b.p, used * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+        if (used) (void)hipMemcpyAsync(p, b.p, used * sizeof(T), hipMemcpyDeviceToDevice, cur_stream(c));
         dev_free(c, b.p, b.cap);
         c->ws_bytes -= (int64_t)b.cap;
     }
@@ -150,13 +181,13 @@ T* buf_keep(ms_ctx* c, const char* name, size_t count, size_t used) {
 
 inline void check(ms_ctx* c, hipError_t e, const char* what) {
     if (e != hipSuccess) {
-        c->err = std::string(what) + ": " + hipGetErrorString(e);
+        err_text(c) = std::string(what) + ": " + hipGetErrorString(e);
         throw Fail{MS_ERR_HIP};
     }
 }
 
 inline void fail(ms_ctx* c, ms_status st, const std::string& msg) {
-    c->err = msg;
+    err_text(c) = msg;
     throw Fail{st};
 }
 
@@ -167,9 +198,10 @@ hipError_t launch_publish(const uint64_t* src, uint64_t n, uint64_t* dst, hipStr
 // the scratch (coherent, device-mapped host memory).
 inline uint64_t* readback(ms_ctx* c, const uint64_t* d, size_t n) {
     if (n > HOST_SCRATCH_WORDS) fail(c, MS_ERR_INTERNAL, "readback larger than the pinned scratch");
-    check(c, launch_publish(d, n, c->h_small_dev, c->stream), "readback");
-    check(c, hipStreamSynchronize(c->stream), "stream synchronize");
-    return c->h_small;
+    uint64_t* h = t_ctx.h_small ? t_ctx.h_small : c->h_small;
+    check(c, launch_publish(d, n, t_ctx.h_small ? t_ctx.h_small_dev : c->h_small_dev, cur_stream(c)), "readback");
+    check(c, hipStreamSynchronize(cur_stream(c)), "stream synchronize");
+    return h;
 }
 
 // Records boundary event i of ms_complex on the context stream (timing only).

@@ -1,0 +1,62 @@
+"""The saddle-extremum arcs (pointer jumping, M10, M32, their transposes,
+the manifold labels) run on a second stream of the context, queued by a
+helper thread while the calling thread queues the minor and the path
+counting; the context's own stream waits for them before the call returns.
+
+* A context bound to a non-default torch stream gives, call after call, the
+  same complexes (and manifold labels) as one on the default stream.
+* With timing on, the side work's own span is reported, and enabling
+  timing again resets it."""
+import numpy as np
+import pytest
+
+from paper_2009_03707_amd import fields
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _field(seed):
+    return fields.blob_field((48, 40, 36), nblobs=6, seed=seed)
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_user_stream_matches_default_stream():
+    from gpu_util import same_complex, to_dev
+    from paper_2009_03707_amd import msc
+    _need_gpu()
+    fs = [to_dev(_field(s)) for s in range(3)]
+    ref = msc.Context()
+    want = [msc.complex_(f, ref) for f in fs]
+    ref.close()
+    user = torch.cuda.Stream()
+    with torch.cuda.stream(user):
+        ctx = msc.Context()
+        for rep in range(2):
+            for f, w in zip(fs, want):
+                got = msc.complex_(f, ctx)
+                same_complex(got, w)
+                np.testing.assert_array_equal(got.min_label.cpu().numpy(), w.min_label.cpu().numpy())
+                np.testing.assert_array_equal(got.max_label.cpu().numpy(), w.max_label.cpu().numpy())
+        ctx.close()
+
+
+def test_side_time_reported_and_reset():
+    from gpu_util import to_dev
+    from paper_2009_03707_amd import msc
+    _need_gpu()
+    f = to_dev(_field(7))
+    ctx = msc.Context()
+    ctx.set_timing(True)
+    msc.complex_(f, ctx)
+    msc.complex_(f, ctx)
+    t = ctx.timing()
+    assert t["calls"] == 2
+    assert t["extrema_side_ms"] > 0
+    ctx.set_timing(True)
+    assert ctx.timing()["extrema_side_ms"] == 0
+    ctx.close()

@@ -760,8 +760,7 @@ __global__ __launch_bounds__(BT) void k_block_start(const uint64_t* __restrict__
 // colof (every entry's column, for levels of short columns, where many
 // entries lie beyond the window) or else by binary search in off.
 //
-// The kernel is bound by the latency of dependent loads, so each step
-// issues all of a thread's independent loads before it uses any: the
+// Each step issues all of a thread's independent loads before it uses any: the
 // window's offsets and column ids, then every column's list pointers, then
 // its first predecessors' ids and multiplicities, then their A* offsets and
 // lengths (a junction has at most three predecessors; more are read one by

@@ -83,9 +83,13 @@ typedef struct ms_ctx ms_ctx;
  * on `stream` (a hipStream_t), or NULL when it cannot (the call in progress
  * then fails with MS_ERR_OOM; the context stays usable and keeps what it
  * holds).  `free` gives back a block with the size it was allocated with;
- * the library drains the context's stream before it frees anything, so the
- * block is idle.  Both receive the `user` pointer given to ms_ctx_create.
- * Either may be called from any host thread that calls into the context. */
+ * the library drains the stream the block was used on before it frees it,
+ * so the block is idle.  Both receive the `user` pointer given to
+ * ms_ctx_create.  Either may be called from any host thread that calls into
+ * the context, and, during ms_complex and ms_complex_batch, also from the
+ * call's helper thread (which queues the saddle-extremum arcs on a second
+ * stream of the context, passed as `stream`) while the calling thread is
+ * inside the library: the callbacks must be safe to call from two threads. */
 typedef void* (*ms_alloc_fn)(void* user, size_t bytes, void* stream);
 typedef void (*ms_free_fn)(void* user, void* ptr, size_t bytes, void* stream);
 

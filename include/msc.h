@@ -248,7 +248,11 @@ typedef struct {
 /* Counters of the connection phase (Section 5 reports the same kinds of
  * statistics: junction counts, matrix sizes, product iterations). */
 typedef struct {
-    int64_t pj_rounds_vertex, pj_rounds_cube; /* pointer-jumping rounds */
+    /* pointer-jumping rounds; a round updates the pointers in place, so how
+     * far it gets depends on which updates of the same round its reads
+     * already see: the count (never the result) can differ between
+     * identical calls */
+    int64_t pj_rounds_vertex, pj_rounds_cube;
     int64_t bfs_levels, reachable;            /* BFS levels, reachable 1-2 pairs */
     int64_t junctions;
     int64_t nnz_a, nnz_b, nnz_bstar, nnz_d;   /* DAG-minor matrices (Section 3.3) */
@@ -307,7 +311,7 @@ typedef struct {
     double gradient_ms;  /* gradient kernel */
     double critical_ms;  /* critical counts, scan, compaction */
     double extrema_ms;   /* pointer set-up and critical-cell labels (the rest of the
-                            saddle-extremum arcs overlaps later stages: extrema_side_ms) */
+                            saddle-extremum arcs overlaps later stages: side_ms) */
     double bfs_ms;       /* saddle-saddle reachability */
     double minor_ms;     /* junction numbering, DAG minor, minor matrices */
     double paths_ms;     /* iterated products, P, M21 and transpose */
@@ -324,11 +328,13 @@ typedef struct {
     /* graphs of the batch front captured / replayed by this context since it
      * was created (not reset by enabling timing) */
     int64_t graph_captures, graph_replays;
-    /* pointer jumping, M10 / M32, their transposes and the manifold labels,
-     * queued by a helper thread on a second stream of the context once the
-     * search is queued, so that they run beside the minor and the path
-     * counting (their own span; not part of total_ms's stages) */
-    double extrema_side_ms;
+    /* work a helper thread of the call queues on a second stream of the
+     * context, beside the stages above: pointer jumping, M10 / M32, their
+     * transposes and the manifold labels (queued once the search is), and
+     * with MS_PATHS_ENTRY the transposes of B* and D (queued once the
+     * junctions are numbered, needed by the last product); the sum of their
+     * spans */
+    double side_ms;
 } ms_timing;
 
 /* Enables (1) or disables (0) timing; enabling resets the accumulators. */

@@ -243,8 +243,7 @@ void ms_ctx_destroy(ms_ctx* ctx) {
     }
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
-    for (auto& e : ctx->side_ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto& e : ctx->side_ev) (void)hipEventDestroy(e);
     if (ctx->h_side) (void)hipHostFree(ctx->h_side);
     delete ctx;
 }
@@ -317,7 +316,7 @@ ms_status ms_ctx_set_timing(ms_ctx* ctx, int enable) {
     ctx->rank_launches = ctx->rank_entries = ctx->rank_heads = 0;
     ctx->rank_used = 0;
     ctx->side_ms = 0;
-    ctx->side_timed = false;
+    ctx->side_used = 0;
     API_END
 }
 
@@ -330,7 +329,7 @@ ms_status ms_ctx_get_timing(ms_ctx* ctx, ms_timing* out) {
     out->minor_ms = ctx->acc_ms[4];
     out->paths_ms = ctx->acc_ms[5];
     out->total_ms = ctx->acc_ms[6];
-    out->extrema_side_ms = ctx->side_ms;
+    out->side_ms = ctx->side_ms;
     out->calls = ctx->calls;
     out->allocations = ctx->allocations;
     out->workspace_bytes = ctx->ws_bytes;
@@ -417,12 +416,12 @@ static void accumulate_timing(ms_ctx* ctx) {
     float tot = 0;
     check(ctx, hipEventElapsedTime(&tot, ctx->ev[0], ctx->ev[6]), "event elapsed");
     ctx->acc_ms[6] += tot;
-    if (ctx->side_timed) {  // the main stream waited for the side work before ev[6]
+    for (size_t i = 0; i < ctx->side_used; i++) {  // the main stream waited for the side work before ev[6]
         float ms = 0;
-        check(ctx, hipEventElapsedTime(&ms, ctx->side_ev[0], ctx->side_ev[1]), "event elapsed");
+        check(ctx, hipEventElapsedTime(&ms, ctx->side_ev[2 * i], ctx->side_ev[2 * i + 1]), "event elapsed");
         ctx->side_ms += ms;
-        ctx->side_timed = false;
     }
+    ctx->side_used = 0;
     ctx->calls++;
     for (size_t i = 0; i < ctx->rank_used; i++) {
         float ms = 0;

@@ -264,6 +264,95 @@ Coo csr_as_coo(ms_ctx* c, const ms_csr& m, const char* rows_name) {
     return o;
 }
 
+void ensure_side(ms_ctx* c) {
+    if (!c->side_stream) check(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking), "stream create");
+    if (!c->ev_fork) check(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "event create");
+    if (!c->ev_join) check(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "event create");
+    if (!c->h_side) {
+        check(c, hipHostMalloc((void**)&c->h_side, HOST_SCRATCH_WORDS * sizeof(uint64_t),
+                               hipHostMallocMapped | hipHostMallocCoherent),
+              "host allocation");
+        check(c, hipHostGetDevicePointer((void**)&c->h_side_dev, c->h_side, 0), "host pointer");
+    }
+}
+
+// Work of one call queued from a helper thread on the context's side stream
+// after everything the calling thread queued so far (event ev_fork), with
+// its own readback scratch, buffer names and error text.  finish() joins
+// the thread, rethrows its failure and orders the calling thread's stream
+// after the helper's work (event ev_join); it does nothing when no work was
+// started, and a task may be started again once finished.  abandon() (and
+// the destructor) joins on the error paths of the calling thread and drains
+// the side stream, so that nothing the helper uses outlives its work.
+class SideTask {
+  public:
+    explicit SideTask(ms_ctx* c) : c_(c) {}
+    SideTask(const SideTask&) = delete;
+    SideTask& operator=(const SideTask&) = delete;
+    template <class F>
+    void start(hipStream_t s, F f) {
+        ensure_side(c_);
+        hipEvent_t t0 = nullptr, t1 = nullptr;  // the work's span, when timing
+        if (c_->timing) {
+            while (c_->side_ev.size() < 2 * (c_->side_used + 1)) {
+                hipEvent_t ev;
+                check(c_, hipEventCreate(&ev), "event create");
+                c_->side_ev.push_back(ev);
+            }
+            t0 = c_->side_ev[2 * c_->side_used];
+            t1 = c_->side_ev[2 * c_->side_used + 1];
+            c_->side_used++;
+        }
+        check(c_, hipEventRecord(c_->ev_fork, s), "event record");
+        st_ = MS_OK;
+        err_.clear();
+        th_ = std::thread([this, f, t0, t1]() {
+            t_ctx = ThreadCtx{c_->side_stream, c_->h_side, c_->h_side_dev, "side.", &err_};
+            try {
+                check(c_, hipSetDevice(c_->device), "set device");
+                check(c_, hipStreamWaitEvent(c_->side_stream, c_->ev_fork, 0), "stream wait");
+                if (t0) check(c_, hipEventRecord(t0, c_->side_stream), "event record");
+                f();
+                if (t1) check(c_, hipEventRecord(t1, c_->side_stream), "event record");
+                check(c_, hipEventRecord(c_->ev_join, c_->side_stream), "event record");
+            } catch (const Fail& e) {
+                st_ = e.st;
+            } catch (const std::exception& e) {
+                st_ = MS_ERR_INTERNAL;
+                err_ = std::string("internal error: ") + e.what();
+            } catch (...) {
+                st_ = MS_ERR_INTERNAL;
+                err_ = "internal error";
+            }
+            t_ctx = ThreadCtx{};
+        });
+    }
+    void finish(hipStream_t s) {
+        if (!th_.joinable()) return;
+        th_.join();
+        if (st_ != MS_OK) {
+            (void)hipStreamSynchronize(c_->side_stream);
+            c_->err = err_;
+            throw Fail{st_};
+        }
+        check(c_, hipStreamWaitEvent(s, c_->ev_join, 0), "stream wait");
+    }
+    void abandon() {
+        if (th_.joinable()) {
+            th_.join();
+            (void)hipStreamSynchronize(c_->side_stream);
+        }
+    }
+    ~SideTask() { abandon(); }
+
+  private:
+    ms_ctx* c_;
+    std::thread th_;
+    ms_status st_ = MS_OK;
+    std::string err_;
+};
+
+
 // Path counting as the paper iterates it (Section 3.3): A* accumulates the
 // frontier A, which is advanced by A <- A*B until the product is empty; then
 // P = D + A* B*.  Products are expand-sort-compress.  Writes M21 and M21t.
@@ -422,8 +511,12 @@ bool paths_ready(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
 // placed at their upper-bound offsets.  P is written directly as M21 (rows
 // 2-saddles).  No column size limit.
 void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, const ms_csr& D, uint64_t S1,
-                 uint64_t S2, uint64_t J, ms_arcs* out, int* d_err) {
+                 uint64_t S2, uint64_t J, ms_arcs* out, int* d_err, SideTask& side) {
     hipStream_t s = cur_stream(c);
+    struct Abandon {  // the helper's work below uses this function's locals
+        SideTask& t;
+        ~Abandon() { t.abandon(); }
+    } abandon_on_exit{side};
     ms_stats& st = out->stats;
     // ---- topological numbering --------------------------------------------
     uint32_t* indeg = buf<uint32_t>(c, "pr.indeg", J + 1);
@@ -459,15 +552,21 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
     if (lvl.back() != J) fail(c, MS_ERR_INTERNAL, "the junction graph has a cycle");
     const uint64_t nlev = lvl.size() - 1;
     check(c, launch_invert(order, J, newid, s), "invert");
+    ms_csr At, Bt, Bst, Dt;
+    // minor multiplicities are at most 4: at most four paths leave a source.
+    // B* and D are first needed by the last product (P), so the helper thread
+    // transposes them on the side stream (once the saddle-extremum arcs are
+    // done there) while the levels of A* are counted here.
+    side.finish(s);
+    side.start(s, [&]() {
+        transpose(c, Bs, "Bst", Bst, newid, 4);  // 2-saddle x junction (renumbered)
+        transpose(c, D, "Dt", Dt, nullptr, 4);   // 2-saddle x 1-saddle
+    });
     // A, B by their target junctions in the new numbering; sources relabelled after the transposes
     check(c, launch_relabel(A.col, (uint64_t)A.nnz, newid, s), "relabel");
     check(c, launch_relabel(B.col, (uint64_t)B.nnz, newid, s), "relabel");
-    ms_csr At, Bt, Bst, Dt;
-    // minor multiplicities are at most 4: at most four paths leave a source
     transpose(c, A, "At", At, nullptr, 4);     // junction x 1-saddle
     transpose(c, B, "Bt", Bt, newid, 4);       // junction x predecessor junction (sources renumbered)
-    transpose(c, Bs, "Bst", Bst, newid, 4);    // 2-saddle x junction (renumbered)
-    transpose(c, D, "Dt", Dt, nullptr, 4);     // 2-saddle x 1-saddle
     // ---- levels --------------------------------------------------------------
     const uint64_t nmax = (J > S2 ? J : S2) + 1;
     uint64_t* ub = buf<uint64_t>(c, "pr.ub", nmax + 1);
@@ -544,6 +643,7 @@ void paths_entry(ms_ctx* c, const ms_csr& A, const ms_csr& B, const ms_csr& Bs, 
         products += T;
     }
     // P columns, written as M21 (rows 2-saddles) in canonical order
+    side.finish(s);
     MergeLaunch mp{nullptr, S2, (const uint64_t*)Dt.rowptr, Dt.col, Dt.val, (const uint64_t*)Bst.rowptr, Bst.col,
                    Bst.val, aoff, alen, arow, aval, 0, 1, 1};
     uint64_t pbase;
@@ -616,86 +716,13 @@ void extremum_arcs(ms_ctx* c, const Geo& g, const uint32_t* s1, const uint32_t* 
     }
 }
 
-void ensure_side(ms_ctx* c) {
-    if (!c->side_stream) check(c, hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking), "stream create");
-    if (!c->ev_fork) check(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "event create");
-    if (!c->ev_join) check(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "event create");
-    for (auto& e : c->side_ev)
-        if (!e) check(c, hipEventCreate(&e), "event create");
-    if (!c->h_side) {
-        check(c, hipHostMalloc((void**)&c->h_side, HOST_SCRATCH_WORDS * sizeof(uint64_t),
-                               hipHostMallocMapped | hipHostMallocCoherent),
-              "host allocation");
-        check(c, hipHostGetDevicePointer((void**)&c->h_side_dev, c->h_side, 0), "host pointer");
-    }
-}
-
-// Work of one call queued from a helper thread on the context's side stream
-// after everything the calling thread queued so far (event ev_fork), with
-// its own readback scratch, buffer names and error text.  finish() joins
-// the thread, rethrows its failure and orders the calling thread's stream
-// after the helper's work (event ev_join); the destructor joins on the
-// error paths of the calling thread.
-class SideTask {
-  public:
-    explicit SideTask(ms_ctx* c) : c_(c) {}
-    SideTask(const SideTask&) = delete;
-    SideTask& operator=(const SideTask&) = delete;
-    template <class F>
-    void start(hipStream_t s, F f) {
-        ensure_side(c_);
-        check(c_, hipEventRecord(c_->ev_fork, s), "event record");
-        c_->side_timed = c_->timing;
-        th_ = std::thread([this, f]() {
-            t_ctx = ThreadCtx{c_->side_stream, c_->h_side, c_->h_side_dev, "side.", &err_};
-            try {
-                check(c_, hipSetDevice(c_->device), "set device");
-                check(c_, hipStreamWaitEvent(c_->side_stream, c_->ev_fork, 0), "stream wait");
-                if (c_->side_timed) check(c_, hipEventRecord(c_->side_ev[0], c_->side_stream), "event record");
-                f();
-                if (c_->side_timed) check(c_, hipEventRecord(c_->side_ev[1], c_->side_stream), "event record");
-                check(c_, hipEventRecord(c_->ev_join, c_->side_stream), "event record");
-            } catch (const Fail& e) {
-                st_ = e.st;
-            } catch (const std::exception& e) {
-                st_ = MS_ERR_INTERNAL;
-                err_ = std::string("internal error: ") + e.what();
-            } catch (...) {
-                st_ = MS_ERR_INTERNAL;
-                err_ = "internal error";
-            }
-            t_ctx = ThreadCtx{};
-        });
-    }
-    void finish(hipStream_t s) {
-        th_.join();
-        if (st_ != MS_OK) {
-            (void)hipStreamSynchronize(c_->side_stream);
-            c_->err = err_;
-            throw Fail{st_};
-        }
-        check(c_, hipStreamWaitEvent(s, c_->ev_join, 0), "stream wait");
-    }
-    ~SideTask() {
-        if (th_.joinable()) {
-            th_.join();
-            (void)hipStreamSynchronize(c_->side_stream);
-        }
-    }
-
-  private:
-    ms_ctx* c_;
-    std::thread th_;
-    ms_status st_ = MS_OK;
-    std::string err_;
-};
-
 }  // namespace
 
 void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t* crit, const int64_t cnt[4],
                   ms_arcs* out) {
     memset(out, 0, sizeof(*out));
     c->rank_used = 0;  // rank timing pairs of an earlier call that were not accumulated
+    c->side_used = 0;  // and side-stream spans
     hipStream_t s = cur_stream(c);
     const uint64_t S0 = (uint64_t)cnt[0], S1 = (uint64_t)cnt[1], S2 = (uint64_t)cnt[2], S3 = (uint64_t)cnt[3];
     const uint32_t* s1 = crit + S0;
@@ -812,7 +839,7 @@ void connect_impl(ms_ctx* c, const uint32_t* grad, const Geo& g, const uint32_t*
     bool done = false;
     if (c->path_schedule == MS_PATHS_READY) done = paths_ready(c, A, B, Bs, D, S1, S2, J, out, d_err);
     if (c->path_schedule == MS_PATHS_ENTRY) {
-        paths_entry(c, A, B, Bs, D, S1, S2, J, out, d_err);
+        paths_entry(c, A, B, Bs, D, S1, S2, J, out, d_err, side);
         done = true;
     }
     if (!done) paths_power(c, A, B, Bs, D, S1, S2, J, out);

@@ -68,8 +68,9 @@ struct ms_ctx {
     uint64_t* h_side = nullptr;
     uint64_t* h_side_dev = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t side_ev[2] = {};  // the side work's span, when timing
-    bool side_timed = false;     // side_ev recorded in the current call
+    // spans of the side work (event pairs) recorded in the current call, when timing
+    std::vector<hipEvent_t> side_ev;
+    size_t side_used = 0;
     double side_ms = 0;
     std::mutex buf_mu;  // the named buffers are looked up from both threads
 };

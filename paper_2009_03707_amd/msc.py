@@ -81,7 +81,7 @@ class Timing(C.Structure):
                                                                       ("rank_heads", C.c_int64),
                                                                       ("graph_captures", C.c_int64),
                                                                       ("graph_replays", C.c_int64),
-                                                                      ("extrema_side_ms", C.c_double)]
+                                                                      ("side_ms", C.c_double)]
 
 
 class Result(C.Structure):

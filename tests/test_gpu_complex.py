@@ -137,7 +137,15 @@ def test_deterministic_repeat(ctx):
     for name in ("m10", "m10t", "m21", "m21t", "m32", "m32t"):
         for x, y in zip(csr_np(getattr(a, name)), csr_np(getattr(b, name))):
             np.testing.assert_array_equal(x, y)
-    assert a.stats == b.stats
+    np.testing.assert_array_equal(a.min_label.cpu().numpy(), b.min_label.cpu().numpy())
+    np.testing.assert_array_equal(a.max_label.cpu().numpy(), b.max_label.cpu().numpy())
+    # every statistic but the pointer-jumping round counts, which depend on
+    # how far the in-place rounds see each other's updates
+    sa = {k: v for k, v in a.stats.items() if not k.startswith("pj_rounds")}
+    sb = {k: v for k, v in b.stats.items() if not k.startswith("pj_rounds")}
+    assert sa == sb
+    for k in ("pj_rounds_vertex", "pj_rounds_cube"):
+        assert 1 <= a.stats[k] <= 65 and 1 <= b.stats[k] <= 65
 
 
 def test_connect_rejects_mismatched_critical_list(ctx):

@@ -1,10 +1,12 @@
 """The saddle-extremum arcs (pointer jumping, M10, M32, their transposes,
-the manifold labels) run on a second stream of the context, queued by a
-helper thread while the calling thread queues the minor and the path
-counting; the context's own stream waits for them before the call returns.
+the manifold labels) and, with the entry schedule, the transposes of B* and
+D run on a second stream of the context, queued by a helper thread while
+the calling thread queues the minor and the path counting; the context's
+own stream waits for them where their results are needed.
 
 * A context bound to a non-default torch stream gives, call after call, the
-  same complexes (and manifold labels) as one on the default stream.
+  same complexes (and manifold labels) as one on the default stream, under
+  every path schedule.
 * With timing on, the side work's own span is reported, and enabling
   timing again resets it."""
 import numpy as np
@@ -25,10 +27,12 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
-def test_user_stream_matches_default_stream():
+@pytest.mark.parametrize("schedule", ["ready", "power", "entry"])
+def test_user_stream_matches_default_stream(schedule):
     from gpu_util import same_complex, to_dev
     from paper_2009_03707_amd import msc
     _need_gpu()
+    sched = {"ready": msc.MS_PATHS_READY, "power": msc.MS_PATHS_POWER, "entry": msc.MS_PATHS_ENTRY}[schedule]
     fs = [to_dev(_field(s)) for s in range(3)]
     ref = msc.Context()
     want = [msc.complex_(f, ref) for f in fs]
@@ -36,6 +40,7 @@ def test_user_stream_matches_default_stream():
     user = torch.cuda.Stream()
     with torch.cuda.stream(user):
         ctx = msc.Context()
+        ctx.set_path_schedule(sched)
         for rep in range(2):
             for f, w in zip(fs, want):
                 got = msc.complex_(f, ctx)
@@ -56,7 +61,7 @@ def test_side_time_reported_and_reset():
     msc.complex_(f, ctx)
     t = ctx.timing()
     assert t["calls"] == 2
-    assert t["extrema_side_ms"] > 0
+    assert t["side_ms"] > 0
     ctx.set_timing(True)
-    assert ctx.timing()["extrema_side_ms"] == 0
+    assert ctx.timing()["side_ms"] == 0
     ctx.close()

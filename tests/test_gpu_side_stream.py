@@ -65,3 +65,62 @@ def test_side_time_reported_and_reset():
     ctx.set_timing(True)
     assert ctx.timing()["side_ms"] == 0
     ctx.close()
+
+
+class SideFailingAllocator:
+    """Allocates from torch's caching allocator and tracks every live block;
+    while `refuse_side` is set it refuses every request made for a stream
+    other than `main` (the helper thread's side stream)."""
+
+    def __init__(self, main_stream):
+        from paper_2009_03707_amd import msc
+        self.main = int(main_stream or 0)
+        self.refuse_side = True
+        self.refused = 0
+        self.live = {}
+        self.fns = (msc.ALLOC_FN(self._alloc), msc.FREE_FN(self._free))
+
+    def _alloc(self, user, nbytes, stream):
+        if self.refuse_side and int(stream or 0) != self.main:
+            self.refused += 1
+            return None
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), 0, int(stream or 0))
+        self.live[p] = int(nbytes)
+        return p
+
+    def _free(self, user, ptr, nbytes, stream):
+        assert self.live.pop(int(ptr)) == int(nbytes)
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+
+@pytest.mark.parametrize("schedule", ["ready", "entry"])
+def test_side_failure_is_reported_and_recovered(schedule):
+    """An allocation refused on the helper thread fails the call with
+    MS_ERR_OOM and its text, leaks nothing, and the same context then gives
+    the same complex as a context that never failed."""
+    from gpu_util import same_complex, to_dev
+    from paper_2009_03707_amd import msc
+    _need_gpu()
+    sched = {"ready": msc.MS_PATHS_READY, "entry": msc.MS_PATHS_ENTRY}[schedule]
+    f = to_dev(_field(11))
+    ref = msc.Context()
+    ref.set_path_schedule(sched)
+    want = msc.complex_(f, ref)
+    ref.close()
+    a = SideFailingAllocator(torch.cuda.current_stream().cuda_stream)
+    ctx = msc.Context(allocator=a.fns)
+    ctx.set_path_schedule(sched)
+    ctx.set_timing(True)
+    with pytest.raises(msc.MscError) as e:
+        msc.complex_(f, ctx)
+    assert e.value.status == msc.MS_ERR_OOM
+    assert "allocation" in str(e.value)
+    assert a.refused >= 1
+    assert ctx.timing()["workspace_bytes"] == sum(a.live.values())
+    a.refuse_side = False
+    got = msc.complex_(f, ctx)
+    same_complex(got, want)
+    np.testing.assert_array_equal(got.min_label.cpu().numpy(), want.min_label.cpu().numpy())
+    np.testing.assert_array_equal(got.max_label.cpu().numpy(), want.max_label.cpu().numpy())
+    ctx.close()
+    assert a.live == {}

@@ -283,7 +283,12 @@ typedef struct {
 
 /* 1-skeleton (Sections 3.1-3.5): saddle-extremum arcs by pointer jumping;
  * saddle-saddle arcs by frontier BFS, junction nodes, DAG minor and iterated
- * sparse integer products.
+ * sparse integer products.  The call starts one host thread of its own,
+ * which queues the saddle-extremum arcs (and, with MS_PATHS_ENTRY, two
+ * transposes the last product needs) on a second stream of the context,
+ * created on first use with the default priority; the context's stream
+ * waits for that work before the results are used, and the thread has ended
+ * when the call returns.  Calls on one context must not overlap in time.
  *   d_grad       : device gradient words.
  *   d_crit_id    : device, the critical cell ids sorted by (index, id), as
  *                  written by ms_critical (sum(h_count) entries).

@@ -124,3 +124,27 @@ def test_side_failure_is_reported_and_recovered(schedule):
     np.testing.assert_array_equal(got.max_label.cpu().numpy(), want.max_label.cpu().numpy())
     ctx.close()
     assert a.live == {}
+
+
+def test_release_between_calls():
+    """ms_ctx_release frees the whole workspace, the helper thread's buffers
+    included; the next calls reallocate it and give the same complex, and the
+    workspace then equals what one call needs from scratch."""
+    from gpu_util import same_complex, to_dev
+    from paper_2009_03707_amd import msc
+    _need_gpu()
+    f = to_dev(_field(5))
+    ctx = msc.Context()
+    ctx.set_path_schedule(msc.MS_PATHS_ENTRY)
+    ctx.set_timing(True)
+    want = msc.complex_(f, ctx)
+    ws = ctx.timing()["workspace_bytes"]
+    assert ws > 0
+    ctx.release()
+    assert ctx.timing()["workspace_bytes"] == 0
+    for _ in range(2):
+        got = msc.complex_(f, ctx)
+        same_complex(got, want)
+        np.testing.assert_array_equal(got.min_label.cpu().numpy(), want.min_label.cpu().numpy())
+    assert ctx.timing()["workspace_bytes"] == ws
+    ctx.close()

@@ -39,3 +39,34 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(msc, "_LIB", None)
     with pytest.raises(RuntimeError):
         msc.lib()
+
+
+def header_struct(name):
+    """(field, C type) in declaration order of `typedef struct { ... } name;`
+    in the header, for structs of scalar fields."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", text)
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, rest = decl.split(None, 1)
+        fields += [(n.strip(), ctype) for n in rest.split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("cname,pyname", [("ms_stats", "Stats"), ("ms_timing", "Timing")])
+def test_binding_structs_match_the_header(cname, pyname):
+    """The ctypes mirrors of the header's result structs list the same fields
+    in the same order with the same widths (a missing or moved field would
+    shift every later one)."""
+    from paper_2009_03707_amd import msc
+    want = header_struct(cname)
+    got = getattr(msc, pyname)._fields_
+    assert [n for n, _ in got] == [n for n, _ in want]
+    ctypes_of = {"double": ctypes.c_double, "int64_t": ctypes.c_int64, "uint64_t": ctypes.c_uint64,
+                 "int32_t": ctypes.c_int32, "uint32_t": ctypes.c_uint32}
+    for (n, t), (_, ct) in zip(got, want):
+        assert ctypes.sizeof(t) == ctypes.sizeof(ctypes_of[ct]), n

@@ -237,6 +237,30 @@ typedef struct {
 ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab,
                                        uint32_t* h_grad, const ms_crit64* out, int64_t h_count[4]);
 
+/* Out-of-core ascending 3-manifolds of the minima and descending
+ * 3-manifolds of the maxima (Section 3.4: the destination extremum of every
+ * vertex and every cube; Section 1.1: parcels computed apart and stitched),
+ * for a field held in HOST memory, with the same slabs and limits as
+ * ms_gradient_critical_chunked.  Each slab follows the (0,1) and (2,3)
+ * gradient paths of its exact rows by pointer jumping on the device; a path
+ * that crosses into another slab ends there with the cell it continues
+ * from, and the host then resolves those cells across the slabs' first and
+ * last rows (the paths never revisit a cell, so every chain ends).  The
+ * labels equal the min_label / max_label of ms_complex on the whole field,
+ * widened to 64 bits:
+ *   h_min_label : host, nx*ny*nz uint64: rank of the minimum the (0,1)
+ *                 path from vertex v reaches, or NULL (not written);
+ *   h_max_label : host, nx*ny*nz uint64: rank of the maximum reached from
+ *                 the cube with lowest corner v, MS_LABEL_EXIT64 when there is
+ *                 no such cube or its path leaves the grid, or NULL;
+ *   h_count     : host, critical cells per index (the ranks' ranges).
+ * Errors: as ms_gradient_critical_chunked (no MS_ERR_CAPACITY);
+ * MS_ERR_INTERNAL if a path between slabs does not end.  Synchronises the
+ * context's stream; uses the host's threads for the stitching. */
+#define MS_LABEL_EXIT64 0xFFFFFFFFFFFFFFFFull
+ms_status ms_manifolds_chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab,
+                               uint64_t* h_min_label, uint64_t* h_max_label, int64_t h_count[4]);
+
 /* A CSR matrix in device memory, context-owned. */
 typedef struct {
     int64_t nrows, ncols, nnz;

@@ -23,6 +23,7 @@
 // keeps (one chunk per slab); once all slabs are done, host threads gather
 // the chunks into the index-major output.
 #include <algorithm>
+#include <atomic>
 #include <memory>
 #include <thread>
 #include <string.h>
@@ -43,6 +44,7 @@ hipError_t launch_crit_scatter(const float* f0, const float* const* fptr, const 
                                hipStream_t s, uint64_t cap = ~0ull);
 Geo single(const Grid& g);
 void flag_clear(ms_ctx* c, int* d_err);
+hipError_t launch_pj_round(uint32_t* P, uint32_t n, int* changed, hipStream_t s);
 
 namespace {
 
@@ -53,6 +55,160 @@ __global__ void k_widen(const uint32_t* __restrict__ id, const uint32_t* __restr
     if (i >= n) return;
     id64[i] = 8 * vbase + id[i];
     vmax64[i] = vbase + vmax[i];
+}
+
+// ---- manifold labels of an out-of-core field (Section 3.4), stitched ----
+//
+// Within a slab's exact rows [z0, z1), the vertex and cube pointers of the
+// in-HBM path are built from the words (slab-local ids, < 2^29); a pointer
+// that crosses z0 or z1 into another slab ends its chain instead, as a root
+// that records where it leaves: ROOT_FLAG | OOC_EXIT | (local id of the
+// last cell in the slab).  Pointer jumping then gives every cell either its
+// extremum (ROOT_FLAG | rank in the slab) or the cell through which its path
+// leaves the slab, and the resolve kernel turns that into a 64-bit label:
+// the global rank of the extremum, or OOC_PENDING | the global id of the
+// cell in the neighbouring slab the path continues in.  Those cells lie in
+// the first or last row of a slab, so the host stitches the slabs by first
+// resolving the pending labels of those boundary rows among themselves (a
+// (0,1) or (2,3) path never returns to a cell, so every chain ends), then
+// every other pending label with one lookup.
+constexpr uint32_t OOC_EXIT = 0x40000000u;  // with ROOT_FLAG: the path leaves the slab here
+constexpr uint32_t OOC_LOCAL = 0x1FFFFFFFu;  // slab-local vertex ids are < 2^29
+constexpr uint64_t OOC_PENDING = 1ull << 62;
+constexpr uint64_t OOC_NONE = ~0ull;        // no cube, or its path leaves the grid
+
+// The successor of vertex v (local, rows [0, gi.n[2]) of the slab, global
+// rows z0 + local) and of the cube with lowest corner v.
+__global__ void k_ooc_ptr(const uint32_t* __restrict__ grad, Grid gi, uint64_t nzg, uint64_t z0,
+                          uint32_t* __restrict__ Pv, uint32_t* __restrict__ Pc, int* __restrict__ err) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= gi.nv) return;
+    const uint32_t v = (uint32_t)i;
+    uint32_t c[3];
+    gi.coords(v, c);
+    const uint64_t zg = z0 + c[2];
+    const uint32_t w = grad[v];
+    const uint32_t n0 = w & 15u;
+    uint32_t pv = ROOT_FLAG;  // a minimum: its rank comes from the critical list
+    if (n0 >= 1 && n0 <= 6) {
+        const uint32_t a = (n0 - 1u) >> 1;
+        const bool neg = ((n0 - 1u) & 1u) != 0;
+        const bool inside = a < 2 ? (neg ? c[a] >= 1 : c[a] + 1 < gi.n[a]) : (neg ? zg >= 1 : zg + 1 < nzg);
+        if (!inside)
+            atomicOr(err, 1);
+        else if (a == 2 && (neg ? c[2] == 0 : c[2] + 1 == gi.n[2]))
+            pv = ROOT_FLAG | OOC_EXIT | v;
+        else
+            pv = neg ? v - gi.stride[a] : v + gi.stride[a];
+    } else if (n0 < NB_CRIT) {
+        atomicOr(err, 1);
+    }
+    Pv[v] = pv;
+    const uint32_t n7 = (w >> 28) & 15u;
+    uint32_t pc = EXIT_LABEL;
+    if (n7 >= NB_CRIT) {
+        pc = ROOT_FLAG;  // a maximum
+    } else if (n7 >= 1 && n7 <= 6) {
+        const uint32_t a = (n7 - 1u) >> 1;
+        const bool neg = ((n7 - 1u) & 1u) != 0;
+        const bool inside = a < 2 ? (neg ? c[a] >= 1 : c[a] + 2 < gi.n[a]) : (neg ? zg >= 1 : zg + 2 < nzg);
+        if (inside) {
+            if (a == 2 && (neg ? c[2] == 0 : c[2] + 1 == gi.n[2]))
+                pc = ROOT_FLAG | OOC_EXIT | v;
+            else
+                pc = neg ? v - gi.stride[a] : v + gi.stride[a];
+        }
+    } else if (n7 != NB_NONE) {
+        atomicOr(err, 1);
+    }
+    Pc[v] = pc;
+}
+
+// Roots of the slab's minima and maxima: their ranks among the slab's
+// critical cells of that index (the list is sorted by (index, id)).
+__global__ void k_ooc_roots(const uint32_t* __restrict__ id, uint64_t c0, uint64_t s3, uint64_t c3,
+                            uint32_t* __restrict__ Pv, uint32_t* __restrict__ Pc) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < c0) Pv[id[i] >> 3] = ROOT_FLAG | (uint32_t)i;
+    if (i < c3) Pc[id[s3 + i] >> 3] = ROOT_FLAG | (uint32_t)i;
+}
+
+__device__ inline uint64_t ooc_label(uint32_t p, uint32_t nib, uint64_t base, uint64_t vbase, uint64_t nxy) {
+    if (p == EXIT_LABEL) return OOC_NONE;
+    if (p & OOC_EXIT) {  // the path continues in the slab below (code 6: -z) or above (code 5: +z)
+        const uint64_t r = vbase + (p & OOC_LOCAL);
+        return OOC_PENDING | (nib == 6u ? r - nxy : r + nxy);
+    }
+    return base + (p & ~ROOT_FLAG);
+}
+
+__global__ void k_ooc_resolve(const uint32_t* __restrict__ Pv, const uint32_t* __restrict__ Pc,
+                              const uint32_t* __restrict__ grad, uint64_t nv, uint64_t vbase, uint64_t nxy,
+                              uint64_t min_base, uint64_t max_base, uint64_t* __restrict__ lmin,
+                              uint64_t* __restrict__ lmax) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nv) return;
+    const uint32_t a = Pv[i], b = Pc[i];
+    // an exit root names its own cell, whose word gives the direction
+    const uint32_t wa = (a & ROOT_FLAG) && (a & OOC_EXIT) ? grad[a & OOC_LOCAL] : 0u;
+    const uint32_t wb = b != EXIT_LABEL && (b & OOC_EXIT) ? grad[b & OOC_LOCAL] : 0u;
+    lmin[i] = ooc_label(a, wa & 15u, min_base, vbase, nxy);
+    lmax[i] = ooc_label(b, wb >> 28, max_base, vbase, nxy);
+}
+
+// Resolves the pending labels of L (host, nv entries): first those in the
+// boundary rows listed (chains among those rows, followed to their end),
+// then every other one from its target, which lies in such a row.  Returns
+// false if a chain does not end or leaves the range (a gradient that is
+// not acyclic; never the case for the words computed here).
+bool stitch(uint64_t* L, uint64_t nv, uint64_t nxy, const std::vector<int64_t>& rows) {
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const uint64_t limit = (uint64_t)rows.size() * nxy + 1;
+    std::atomic<bool> ok{true};
+    auto pending = [](uint64_t x) { return (x >> 62) == 1; };
+    auto run = [&](uint64_t n, auto&& body) {
+        std::vector<std::thread> th;
+        const uint64_t per = (n + hw - 1) / hw;
+        for (unsigned t = 0; t < hw; t++) {
+            const uint64_t a = t * per, b = std::min(n, a + per);
+            if (a >= b) break;
+            th.emplace_back([&, a, b] { body(a, b); });
+        }
+        for (auto& x : th) x.join();
+    };
+    // boundary rows: a chain's labels are either still pending (and lead on)
+    // or final, so threads may read each other's stores in any order
+    run((uint64_t)rows.size() * nxy, [&](uint64_t a, uint64_t b) {
+        for (uint64_t j = a; j < b && ok.load(std::memory_order_relaxed); j++) {
+            const uint64_t v = (uint64_t)rows[j / nxy] * nxy + j % nxy;
+            uint64_t x = __atomic_load_n(&L[v], __ATOMIC_RELAXED);
+            uint64_t steps = 0;
+            while (pending(x)) {
+                const uint64_t t = x & (OOC_PENDING - 1);
+                if (t >= nv || ++steps > limit) {
+                    ok = false;
+                    break;
+                }
+                x = __atomic_load_n(&L[t], __ATOMIC_RELAXED);
+            }
+            if (!pending(x)) __atomic_store_n(&L[v], x, __ATOMIC_RELAXED);
+        }
+    });
+    if (!ok) return false;
+    run(nv, [&](uint64_t a, uint64_t b) {
+        for (uint64_t v = a; v < b; v++) {
+            const uint64_t x = L[v];
+            if (!pending(x)) continue;
+            const uint64_t t = x & (OOC_PENDING - 1);
+            const uint64_t y = t < nv ? L[t] : x;
+            if (pending(y)) {
+                ok = false;
+                return;
+            }
+            L[v] = y;
+        }
+    });
+    return ok;
 }
 
 // memcpy split over host threads
@@ -129,11 +285,16 @@ struct Stream {
 
 using namespace msc;
 
-extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab,
-                                                  uint32_t* h_grad, const ms_crit64* out, int64_t h_count[4]) {
+namespace {
+
+// One pass over the slabs: gradient words (h_grad), critical records (out)
+// and manifold labels (h_min, h_max), each when its pointer is not null.
+ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uint32_t* h_grad, const ms_crit64* out,
+                  int64_t h_count[4], uint64_t* h_min, uint64_t* h_max) {
     if (!ctx) return MS_ERR_INVALID_ARG;
     try {
         if (!h_f || !h_count) fail(ctx, MS_ERR_INVALID_ARG, "null field or count pointer");
+        const bool labels = h_min || h_max;
         if (dims.nx < 1 || dims.ny < 1 || dims.nz < 1 || slab < 1) fail(ctx, MS_ERR_INVALID_ARG, "dims and slab must be >= 1");
         const int64_t nx = dims.nx, ny = dims.ny, nz = dims.nz;
         if (nx > (1 << 29) || ny > (1 << 29) || nx * ny > ((int64_t)1 << 29))
@@ -179,6 +340,10 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
 
         const int64_t nslab = (nz + slab - 1) / slab;
         std::vector<Chunk> chunks((size_t)nslab);
+        uint64_t min_base = 0, max_base = 0;  // minima / maxima in earlier slabs
+        int* d_lerr = labels ? buf<int>(ctx, "ooc.lerr", 64) : nullptr;
+        int* d_chg = labels ? buf<int>(ctx, "ooc.chg", 64) : nullptr;
+        if (labels) check(ctx, hipMemsetAsync(d_lerr, 0, 2 * sizeof(int), cs), "memset");
         RecordArena arena{ctx};
         auto rows_of = [&](int64_t i, int64_t& z0, int64_t& z1, int64_t& zs, int64_t& ze) {
             z0 = i * slab;
@@ -244,20 +409,57 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
             uint32_t* d_vmax = buf<uint32_t>(ctx, "ooc.vmax", (size_t)n);
             uint64_t* d_id64 = buf<uint64_t>(ctx, "ooc.id64", (size_t)n);
             uint64_t* d_vmax64 = buf<uint64_t>(ctx, "ooc.vmax64", (size_t)n);
-            if (n > 0) {
+            if (n > 0 && (out || labels))
                 check(ctx, launch_crit_scatter(d_f[b] + off, nullptr, d_grad + off, single(gi), tmp, d_id, d_index,
                                                d_value, d_vmax, cs),
                       "critical scatter launch");
+            if (n > 0 && out) {
                 hipLaunchKernelGGL(k_widen, dim3(grid_blocks((uint64_t)n, 256)), dim3(256), 0, cs, (const uint32_t*)d_id,
                                    (const uint32_t*)d_vmax, (uint64_t)n, (uint64_t)z0 * (uint64_t)nxy, d_id64, d_vmax64);
                 check(ctx, hipGetLastError(), "widen launch");
             }
             check(ctx, hipEventRecord(ev_done[b].e, cs), "event record");  // d_f[b] may be refilled
+            if (labels) {
+                const uint64_t nvi = gi.nv, vbase = (uint64_t)z0 * (uint64_t)nxy;
+                uint32_t* Pv = buf<uint32_t>(ctx, "ooc.pv", (size_t)nvi);
+                uint32_t* Pc = buf<uint32_t>(ctx, "ooc.pc", (size_t)nvi);
+                uint64_t* lmin = buf<uint64_t>(ctx, "ooc.lmin", (size_t)nvi);
+                uint64_t* lmax = buf<uint64_t>(ctx, "ooc.lmax", (size_t)nvi);
+                hipLaunchKernelGGL(k_ooc_ptr, dim3(grid_blocks(nvi, 256)), dim3(256), 0, cs,
+                                   (const uint32_t*)(d_grad + off), gi, (uint64_t)nz, (uint64_t)z0, Pv, Pc, d_lerr);
+                check(ctx, hipGetLastError(), "pointer launch");
+                const uint64_t c0 = (uint64_t)ch.cnt[0], c3 = (uint64_t)ch.cnt[3];
+                if (c0 + c3 > 0) {
+                    hipLaunchKernelGGL(k_ooc_roots, dim3(grid_blocks(std::max(c0, c3), 256)), dim3(256), 0, cs,
+                                       (const uint32_t*)d_id, c0, (uint64_t)(n - ch.cnt[3]), c3, Pv, Pc);
+                    check(ctx, hipGetLastError(), "roots launch");
+                }
+                for (uint32_t* P : {Pv, Pc})
+                    for (int rounds = 0;; rounds++) {
+                        if (rounds > 64) fail(ctx, MS_ERR_INTERNAL, "pointer jumping did not converge");
+                        check(ctx, hipMemsetAsync(d_chg, 0, 64 * sizeof(int), cs), "memset");
+                        check(ctx, launch_pj_round(P, (uint32_t)nvi, d_chg, cs), "pointer jumping launch");
+                        const uint64_t* h = readback(ctx, (const uint64_t*)d_chg, 32);
+                        bool any = false;
+                        for (int q = 0; q < 32; q++) any = any || h[q] != 0;
+                        if (!any) break;
+                    }
+                hipLaunchKernelGGL(k_ooc_resolve, dim3(grid_blocks(nvi, 256)), dim3(256), 0, cs, (const uint32_t*)Pv,
+                                   (const uint32_t*)Pc, (const uint32_t*)(d_grad + off), nvi, vbase, (uint64_t)nxy,
+                                   min_base, max_base, lmin, lmax);
+                check(ctx, hipGetLastError(), "resolve launch");
+                if (h_min)
+                    check(ctx, hipMemcpyAsync(h_min + vbase, lmin, 8 * nvi, hipMemcpyDeviceToHost, cs), "copy to host");
+                if (h_max)
+                    check(ctx, hipMemcpyAsync(h_max + vbase, lmax, 8 * nvi, hipMemcpyDeviceToHost, cs), "copy to host");
+                min_base += c0;
+                max_base += c3;
+            }
             if (h_grad)
                 check(ctx, hipMemcpyAsync(h_grad + z0 * nxy, d_grad + off, (size_t)((z1 - z0) * nxy) * sizeof(uint32_t),
                                           hipMemcpyDeviceToHost, cs),
                       "copy to host");
-            if (n > 0) {
+            if (n > 0 && out) {
                 uint64_t* hid = (uint64_t*)arena.take(8 * (size_t)n);
                 uint64_t* hvm = (uint64_t*)arena.take(8 * (size_t)n);
                 float* hval = (float*)arena.take(4 * (size_t)n);
@@ -272,6 +474,20 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
         }
         check(ctx, hipStreamSynchronize(xs.s), "stream synchronize");
         if (nonfinite) fail(ctx, MS_ERR_NONFINITE, "the field contains NaN or infinite values");
+        if (labels) {
+            const uint64_t* h = readback(ctx, (const uint64_t*)d_lerr, 1);
+            if ((int)*h) fail(ctx, MS_ERR_INTERNAL, "inconsistent gradient words");
+            std::vector<int64_t> rows;  // first and last row of every slab
+            for (int64_t i = 0; i < nslab; i++) {
+                int64_t z0, z1, zs, ze;
+                rows_of(i, z0, z1, zs, ze);
+                rows.push_back(z0);
+                if (z1 - 1 > z0) rows.push_back(z1 - 1);
+            }
+            for (uint64_t* L : {h_min, h_max})
+                if (L && !stitch(L, (uint64_t)(nxy * nz), (uint64_t)nxy, rows))
+                    fail(ctx, MS_ERR_INTERNAL, "a path between slabs does not end");
+        }
         int64_t total = 0;
         for (int k = 0; k < 4; k++) {
             h_count[k] = 0;
@@ -321,4 +537,16 @@ extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f,
         return MS_ERR_INTERNAL;
     }
     return MS_OK;
+}
+
+}  // namespace
+
+extern "C" ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab,
+                                                  uint32_t* h_grad, const ms_crit64* out, int64_t h_count[4]) {
+    return chunked(ctx, h_f, dims, slab, h_grad, out, h_count, nullptr, nullptr);
+}
+
+extern "C" ms_status ms_manifolds_chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab,
+                                          uint64_t* h_min_label, uint64_t* h_max_label, int64_t h_count[4]) {
+    return chunked(ctx, h_f, dims, slab, nullptr, nullptr, h_count, h_min_label, h_max_label);
 }

@@ -24,7 +24,9 @@ EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_err
             "ms_ctx_set_option", "ms_complex_batch", "ms_ctx_release", "ms_critical_noalloc",
             "ms_graph_build", "ms_graph_build_host", "ms_graph_destroy", "ms_graph_num_nodes", "ms_graph_last_error",
             "ms_graph_node", "ms_graph_find", "ms_graph_arcs", "ms_graph_counts", "ms_graph_simplify",
-            "ms_graph_num_cancellations", "ms_graph_cancellations", "ms_gradient_critical_chunked"]
+            "ms_graph_num_cancellations", "ms_graph_cancellations", "ms_gradient_critical_chunked",
+            "ms_manifolds_chunked"]
+LABEL_EXIT64 = 0xFFFFFFFFFFFFFFFF
 MS_DOWN, MS_UP = 0, 1
 MS_SIMPLIFY_SERIAL, MS_SIMPLIFY_SUBGRID = 0, 1
 
@@ -146,6 +148,7 @@ def lib():
         L.ms_complex_batch.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(Dims), C.POINTER(Result)]
         L.ms_ctx_release.argtypes = [vp]
         L.ms_gradient_critical_chunked.argtypes = [vp, vp, Dims, i64, vp, C.POINTER(Crit64), C.POINTER(i64)]
+        L.ms_manifolds_chunked.argtypes = [vp, vp, Dims, i64, vp, vp, C.POINTER(i64)]
         L.ms_graph_build.argtypes = [vp, C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
         L.ms_graph_build_host.argtypes = [C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
         L.ms_graph_destroy.argtypes = [vp]
@@ -331,6 +334,23 @@ class Context:
         self._raise(st, "ms_gradient_critical_chunked")
         n = int(sum(cnt))
         return (grad,) + tuple(a[:n] for a in arrs) + (list(cnt),)
+
+    def manifolds_chunked(self, f, slab: int, want_min: bool = True, want_max: bool = True):
+        """ms_manifolds_chunked on a host numpy float32 field (nz, ny, nx):
+        returns (min_label uint64 (nz, ny, nx) or None, max_label uint64
+        (nz, ny, nx) or None, counts)."""
+        import numpy as np
+        f = np.ascontiguousarray(f, dtype=np.float32)
+        nz, ny, nx = f.shape
+        self._sync_stream()
+        cnt = (C.c_int64 * 4)()
+        lo = np.empty(f.shape, np.uint64) if want_min else None
+        hi = np.empty(f.shape, np.uint64) if want_max else None
+        st = lib().ms_manifolds_chunked(self._h, f.ctypes.data, Dims(nx, ny, nz), int(slab),
+                                        lo.ctypes.data if want_min else None, hi.ctypes.data if want_max else None,
+                                        cnt)
+        self._raise(st, "ms_manifolds_chunked")
+        return lo, hi, list(cnt)
 
     def connect(self, grad: torch.Tensor, dims, crit_id: torch.Tensor, counts) -> "Arcs":
         self._sync_stream()

@@ -27,6 +27,7 @@ ms_manifolds_chunked (labels stitched across slabs, Section 3.4):
 import numpy as np
 import pytest
 
+from forest import EXIT64, check_forest, widen_exit
 from oracle import oracle as O
 from paper_2009_03707_amd import fields
 
@@ -134,12 +135,6 @@ def test_errors(ctx):
     assert st == msc.MS_ERR_CAPACITY and sum(cnt) > 0
 
 
-def _wide(lab):
-    out = lab.astype(np.uint64)
-    out[lab == 0xFFFFFFFF] = np.uint64(0xFFFFFFFFFFFFFFFF)
-    return out
-
-
 @pytest.mark.parametrize("kind,dims,seed", CASES)
 def test_labels_equal_oracle(ctx, kind, dims, seed):
     f = _field(kind, dims, seed)
@@ -151,10 +146,10 @@ def test_labels_equal_oracle(ctx, kind, dims, seed):
         lo, hi, cnt = ctx.manifolds_chunked(f, slab)
         assert cnt == ref.count.tolist(), slab
         np.testing.assert_array_equal(lo, lo_ref.astype(np.uint64), err_msg=f"min labels, slab {slab}")
-        np.testing.assert_array_equal(hi, _wide(hi_ref), err_msg=f"max labels, slab {slab}")
+        np.testing.assert_array_equal(hi, widen_exit(hi_ref), err_msg=f"max labels, slab {slab}")
     lo, hi, _ = ctx.manifolds_chunked(f, 2, want_min=False)
     assert lo is None
-    np.testing.assert_array_equal(hi, _wide(hi_ref))
+    np.testing.assert_array_equal(hi, widen_exit(hi_ref))
 
 
 def test_labels_equal_in_hbm_512(ctx):
@@ -168,49 +163,7 @@ def test_labels_equal_in_hbm_512(ctx):
     del got
     lo, hi, cnt = ctx.manifolds_chunked(f, 100)
     np.testing.assert_array_equal(lo, want_lo.astype(np.uint64))
-    np.testing.assert_array_equal(hi, _wide(want_hi))
-
-
-def _check_forest(grad, lab, roots, nibble, cube, z0, z1, exit_label=None):
-    """Labels of rows [z0, z1) of `lab` (nz, ny, nx) against their
-    successors' along the (0,1) paths (nibble 0, vertices) or (2,3) paths
-    (nibble 7, cubes; a neighbouring cube must exist, so a step leaves room
-    for two vertices); roots are the extrema's vertices (flat ids)."""
-    nz, ny, nx = lab.shape
-    room = 2 if cube else 1
-    code = ((grad[z0:z1] >> np.uint32(4 * nibble)) & np.uint32(15)).astype(np.uint8)
-    got = lab[z0:z1]
-    assert not (code == 0).any()
-    if cube:
-        assert (got[code == 7] == exit_label).all()
-    else:
-        assert not (code == 7).any()
-    for axis in range(3):
-        n, d = (nx, ny, nz)[axis], 2 - axis  # numpy dimension of the axis
-        for neg in (False, True):
-            c = 2 * axis + 1 + int(neg)
-            lo, hi = (1, n) if neg else (0, n - room)  # cells whose successor exists
-            sh = -1 if neg else 1
-            if axis == 2:
-                a, b = max(z0, lo), min(z1, hi)
-                if a < b:
-                    assert ((code[a - z0:b - z0] != c) | (lab[a:b] == lab[a + sh:b + sh])).all(), (axis, neg)
-                out = [z for z in range(z0, z1) if not lo <= z < hi]
-                sel = [z - z0 for z in out]
-                cs, gs = code[sel], got[sel]
-            else:
-                if lo < hi:
-                    src = [slice(None)] * 3
-                    dst = [slice(None)] * 3
-                    src[d], dst[d] = slice(lo, hi), slice(lo + sh, hi + sh)
-                    assert ((code[tuple(src)] != c) | (got[tuple(src)] == got[tuple(dst)])).all(), (axis, neg)
-                idx = [i for i in range(n) if not lo <= i < hi]
-                cs, gs = np.take(code, idx, axis=d), np.take(got, idx, axis=d)
-            if cube:  # the path leaves the grid
-                assert (gs[cs == c] == exit_label).all()
-            else:
-                assert not (cs == c).any()
-    assert (code >= 8).sum() == ((roots >= z0 * nx * ny) & (roots < z1 * nx * ny)).sum()
+    np.testing.assert_array_equal(hi, widen_exit(want_hi))
 
 
 def test_labels_beyond_32bit_cell_ids(ctx):
@@ -224,6 +177,8 @@ def test_labels_beyond_32bit_cell_ids(ctx):
     grad, cid, idx, _, _, cnt = ctx.gradient_critical_chunked(f, 120)
     lo, hi, cnt2 = ctx.manifolds_chunked(f, 120)
     assert cnt2 == cnt
+    from paper_2009_03707_amd import msc
+    assert msc.LABEL_EXIT64 == int(EXIT64)
     print("[chunked] labels done", flush=True)
     off = np.cumsum([0] + cnt)
     vmin = (cid[off[0]:off[1]] >> np.uint64(3)).astype(np.int64)
@@ -233,13 +188,9 @@ def test_labels_beyond_32bit_cell_ids(ctx):
     np.testing.assert_array_equal(lo.reshape(-1)[vmin], np.arange(len(vmin), dtype=np.uint64))
     np.testing.assert_array_equal(hi.reshape(-1)[vmax], np.arange(len(vmax), dtype=np.uint64))
     assert int(lo.max()) < cnt[0]
-    assert int(hi[hi != np.uint64(msc_exit())].max()) < cnt[3]
+    assert int(hi[hi != EXIT64].max()) < cnt[3]
     for z0 in range(0, nz, 50):  # every row, across the slab boundaries too
         z1 = min(nz, z0 + 50)
-        _check_forest(grad, lo, vmin, 0, False, z0, z1)
-        _check_forest(grad, hi, vmax, 7, True, z0, z1, np.uint64(msc_exit()))
+        check_forest(grad, lo, vmin, 0, False, z0, z1)
+        check_forest(grad, hi, vmax, 7, True, z0, z1, EXIT64)
 
-
-def msc_exit():
-    from paper_2009_03707_amd import msc
-    return msc.LABEL_EXIT64

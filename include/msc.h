@@ -106,7 +106,7 @@ ms_status ms_ctx_set_stream(ms_ctx* ctx, void* stream);
 /* Text describing the last non-OK status returned on this context. */
 const char* ms_last_error(const ms_ctx* ctx);
 /* Frees the context's workspace -- its device buffers and the pinned host
- * memory of ms_gradient_critical_chunked (slab staging and records; all are
+ * memory of the out-of-core calls (slab staging, records and labels; all are
  * reallocated on demand by the next call); invalidates every context-owned
  * output.  Synchronises the stream. */
 ms_status ms_ctx_release(ms_ctx* ctx);
@@ -256,7 +256,9 @@ ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f, ms_dims di
  *   h_count     : host, critical cells per index (the ranks' ranges).
  * Errors: as ms_gradient_critical_chunked (no MS_ERR_CAPACITY);
  * MS_ERR_INTERNAL if a path between slabs does not end.  Synchronises the
- * context's stream; uses the host's threads for the stitching. */
+ * context's stream; uses the host's threads for the stitching.  The
+ * labels come back through pinned memory (16 bytes per vertex of two
+ * slabs) that the context keeps for later calls. */
 #define MS_LABEL_EXIT64 0xFFFFFFFFFFFFFFFFull
 ms_status ms_manifolds_chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab,
                                uint64_t* h_min_label, uint64_t* h_max_label, int64_t h_count[4]);

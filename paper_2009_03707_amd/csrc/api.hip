@@ -231,6 +231,8 @@ void ms_ctx_destroy(ms_ctx* ctx) {
     if (ctx->h_small) (void)hipHostFree(ctx->h_small);
     for (void* p : ctx->h_stage)
         if (p) (void)hipHostFree(p);
+    for (void* p : ctx->h_lab)
+        if (p) (void)hipHostFree(p);
     for (auto& b : ctx->h_recs) (void)hipHostFree(b.first);
     for (auto& e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
@@ -259,6 +261,11 @@ ms_status ms_ctx_release(ms_ctx* ctx) {
         p = nullptr;
     }
     ctx->h_stage_bytes = 0;
+    for (void*& p : ctx->h_lab) {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+    }
+    ctx->h_lab_bytes = 0;
     for (auto& b : ctx->h_recs) (void)hipHostFree(b.first);
     ctx->h_recs.clear();
     return MS_OK;

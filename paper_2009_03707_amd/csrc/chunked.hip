@@ -24,6 +24,7 @@
 // the chunks into the index-major output.
 #include <algorithm>
 #include <atomic>
+#include <functional>
 #include <memory>
 #include <thread>
 #include <string.h>
@@ -266,6 +267,21 @@ struct RecordArena {
     }
 };
 
+// A host copy started once its source is ready (start) and waited for
+// before the source is reused or the call returns (join, also on errors).
+struct Copier {
+    std::function<void()> pending;
+    std::thread t;
+    void start() {
+        if (pending) t = std::thread(std::move(pending));
+        pending = nullptr;
+    }
+    void join() {
+        if (t.joinable()) t.join();
+    }
+    ~Copier() { join(); }
+};
+
 struct Ev {
     hipEvent_t e = nullptr;
     ~Ev() {
@@ -342,6 +358,26 @@ ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uin
         std::vector<Chunk> chunks((size_t)nslab);
         uint64_t min_base = 0, max_base = 0;  // minima / maxima in earlier slabs
         int* d_lerr = labels ? buf<int>(ctx, "ooc.lerr", 64) : nullptr;
+        // labels come back through two pinned buffers (one slab's two label
+        // arrays each); host threads copy a slab's labels into the caller's
+        // arrays while the GPU works on the next slab
+        Copier lab_copy[2];
+        const size_t lab_bytes = 16 * (size_t)(slab * nxy);
+        if (labels && ctx->h_lab_bytes < lab_bytes) {
+            check(ctx, hipStreamSynchronize(cs), "stream synchronize");
+            for (void*& p : ctx->h_lab) {
+                if (p) (void)hipHostFree(p);
+                p = nullptr;
+            }
+            ctx->h_lab_bytes = 0;
+            for (void*& p : ctx->h_lab)
+                if (hipHostMalloc(&p, lab_bytes, hipHostMallocDefault) != hipSuccess) {
+                    (void)hipGetLastError();
+                    p = nullptr;
+                    fail(ctx, MS_ERR_OOM, "pinned label staging allocation failed");
+                }
+            ctx->h_lab_bytes = lab_bytes;
+        }
         int* d_chg = labels ? buf<int>(ctx, "ooc.chg", 64) : nullptr;
         if (labels) check(ctx, hipMemsetAsync(d_lerr, 0, 2 * sizeof(int), cs), "memset");
         RecordArena arena{ctx};
@@ -448,10 +484,17 @@ ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uin
                                    (const uint32_t*)Pc, (const uint32_t*)(d_grad + off), nvi, vbase, (uint64_t)nxy,
                                    min_base, max_base, lmin, lmax);
                 check(ctx, hipGetLastError(), "resolve launch");
+                lab_copy[b].join();  // staging b is free again
+                uint64_t* st_min = (uint64_t*)ctx->h_lab[b];
+                uint64_t* st_max = st_min + nvi;
                 if (h_min)
-                    check(ctx, hipMemcpyAsync(h_min + vbase, lmin, 8 * nvi, hipMemcpyDeviceToHost, cs), "copy to host");
+                    check(ctx, hipMemcpyAsync(st_min, lmin, 8 * nvi, hipMemcpyDeviceToHost, cs), "copy to host");
                 if (h_max)
-                    check(ctx, hipMemcpyAsync(h_max + vbase, lmax, 8 * nvi, hipMemcpyDeviceToHost, cs), "copy to host");
+                    check(ctx, hipMemcpyAsync(st_max, lmax, 8 * nvi, hipMemcpyDeviceToHost, cs), "copy to host");
+                lab_copy[b].pending = [=] {
+                    if (h_min) par_copy(h_min + vbase, st_min, 8 * nvi);
+                    if (h_max) par_copy(h_max + vbase, st_max, 8 * nvi);
+                };
                 min_base += c0;
                 max_base += c3;
             }
@@ -471,8 +514,10 @@ ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uin
                 check(ctx, hipMemcpyAsync(hval, d_value, 4 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
             }
             check(ctx, hipStreamSynchronize(cs), "stream synchronize");
+            if (labels) lab_copy[b].start();
         }
         check(ctx, hipStreamSynchronize(xs.s), "stream synchronize");
+        for (Copier& cp : lab_copy) cp.join();
         if (nonfinite) fail(ctx, MS_ERR_NONFINITE, "the field contains NaN or infinite values");
         if (labels) {
             const uint64_t* h = readback(ctx, (const uint64_t*)d_lerr, 1);

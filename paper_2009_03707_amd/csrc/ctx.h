@@ -33,6 +33,8 @@ struct ms_ctx {
     std::map<std::string, Buf> bufs;
     void* h_stage[2] = {nullptr, nullptr};  // pinned staging of the out-of-core field slabs
     size_t h_stage_bytes = 0;
+    void* h_lab[2] = {nullptr, nullptr};  // pinned staging of the out-of-core slabs' labels
+    size_t h_lab_bytes = 0;
     std::vector<std::pair<void*, size_t>> h_recs;  // pinned blocks holding the out-of-core slabs' records
     uint64_t* h_small = nullptr;  // pinned, coherent host scratch for small readbacks
     uint64_t* h_small_dev = nullptr;  // the same memory as the device addresses it

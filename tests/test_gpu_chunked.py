@@ -152,6 +152,19 @@ def test_labels_equal_oracle(ctx, kind, dims, seed):
     np.testing.assert_array_equal(hi, widen_exit(hi_ref))
 
 
+def test_labels_after_release_and_regrowth(ctx):
+    """Label staging that grows (a taller slab), or is freed between calls
+    (ms_ctx_release), gives the same labels."""
+    f = fields.grf_field((30, 24, 20), seed=4)
+    ref_g = O.gradient(f)
+    lo_ref, hi_ref = O.manifolds(f, ref_g, O.critical(f, ref_g))
+    for slab in (2, 9, 3):
+        lo, hi, _ = ctx.manifolds_chunked(f, slab)
+        np.testing.assert_array_equal(lo, lo_ref.astype(np.uint64))
+        np.testing.assert_array_equal(hi, widen_exit(hi_ref))
+        ctx.release()
+
+
 def test_labels_equal_in_hbm_512(ctx):
     from gpu_util import to_dev
     from paper_2009_03707_amd import msc

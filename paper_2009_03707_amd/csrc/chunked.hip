@@ -358,12 +358,14 @@ ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uin
         std::vector<Chunk> chunks((size_t)nslab);
         uint64_t min_base = 0, max_base = 0;  // minima / maxima in earlier slabs
         int* d_lerr = labels ? buf<int>(ctx, "ooc.lerr", 64) : nullptr;
-        // labels come back through two pinned buffers (one slab's two label
-        // arrays each); host threads copy a slab's labels into the caller's
-        // arrays while the GPU works on the next slab
+        // labels and gradient words come back through two pinned buffers
+        // (one slab's outputs each: minima labels, maxima labels, words);
+        // host threads copy a slab's outputs into the caller's arrays while
+        // the GPU works on the next slab
         Copier lab_copy[2];
-        const size_t lab_bytes = 16 * (size_t)(slab * nxy);
-        if (labels && ctx->h_lab_bytes < lab_bytes) {
+        const bool staged = labels || h_grad;
+        const size_t lab_bytes = (labels ? 16 : 0) * (size_t)(slab * nxy) + (h_grad ? 4 : 0) * (size_t)(slab * nxy);
+        if (staged && ctx->h_lab_bytes < lab_bytes) {
             check(ctx, hipStreamSynchronize(cs), "stream synchronize");
             for (void*& p : ctx->h_lab) {
                 if (p) (void)hipHostFree(p);
@@ -374,7 +376,7 @@ ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uin
                 if (hipHostMalloc(&p, lab_bytes, hipHostMallocDefault) != hipSuccess) {
                     (void)hipGetLastError();
                     p = nullptr;
-                    fail(ctx, MS_ERR_OOM, "pinned label staging allocation failed");
+                    fail(ctx, MS_ERR_OOM, "pinned output staging allocation failed");
                 }
             ctx->h_lab_bytes = lab_bytes;
         }
@@ -455,6 +457,11 @@ ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uin
                 check(ctx, hipGetLastError(), "widen launch");
             }
             check(ctx, hipEventRecord(ev_done[b].e, cs), "event record");  // d_f[b] may be refilled
+            lab_copy[b].join();  // output staging b is free again
+            const size_t ns = (size_t)((z1 - z0) * nxy);
+            uint64_t* st_min = (uint64_t*)ctx->h_lab[b];  // [minima labels | maxima labels | words]
+            uint64_t* st_max = labels ? st_min + ns : st_min;
+            uint32_t* st_grad = (uint32_t*)(labels ? st_max + ns : st_min);
             if (labels) {
                 const uint64_t nvi = gi.nv, vbase = (uint64_t)z0 * (uint64_t)nxy;
                 uint32_t* Pv = buf<uint32_t>(ctx, "ooc.pv", (size_t)nvi);
@@ -484,24 +491,23 @@ ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uin
                                    (const uint32_t*)Pc, (const uint32_t*)(d_grad + off), nvi, vbase, (uint64_t)nxy,
                                    min_base, max_base, lmin, lmax);
                 check(ctx, hipGetLastError(), "resolve launch");
-                lab_copy[b].join();  // staging b is free again
-                uint64_t* st_min = (uint64_t*)ctx->h_lab[b];
-                uint64_t* st_max = st_min + nvi;
                 if (h_min)
                     check(ctx, hipMemcpyAsync(st_min, lmin, 8 * nvi, hipMemcpyDeviceToHost, cs), "copy to host");
                 if (h_max)
                     check(ctx, hipMemcpyAsync(st_max, lmax, 8 * nvi, hipMemcpyDeviceToHost, cs), "copy to host");
-                lab_copy[b].pending = [=] {
-                    if (h_min) par_copy(h_min + vbase, st_min, 8 * nvi);
-                    if (h_max) par_copy(h_max + vbase, st_max, 8 * nvi);
-                };
                 min_base += c0;
                 max_base += c3;
             }
             if (h_grad)
-                check(ctx, hipMemcpyAsync(h_grad + z0 * nxy, d_grad + off, (size_t)((z1 - z0) * nxy) * sizeof(uint32_t),
-                                          hipMemcpyDeviceToHost, cs),
-                      "copy to host");
+                check(ctx, hipMemcpyAsync(st_grad, d_grad + off, 4 * ns, hipMemcpyDeviceToHost, cs), "copy to host");
+            if (staged) {
+                const size_t vbase = (size_t)(z0 * nxy);
+                lab_copy[b].pending = [=] {
+                    if (h_min) par_copy(h_min + vbase, st_min, 8 * ns);
+                    if (h_max) par_copy(h_max + vbase, st_max, 8 * ns);
+                    if (h_grad) par_copy(h_grad + vbase, st_grad, 4 * ns);
+                };
+            }
             if (n > 0 && out) {
                 uint64_t* hid = (uint64_t*)arena.take(8 * (size_t)n);
                 uint64_t* hvm = (uint64_t*)arena.take(8 * (size_t)n);
@@ -514,7 +520,7 @@ ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uin
                 check(ctx, hipMemcpyAsync(hval, d_value, 4 * (size_t)n, hipMemcpyDeviceToHost, cs), "copy to host");
             }
             check(ctx, hipStreamSynchronize(cs), "stream synchronize");
-            if (labels) lab_copy[b].start();
+            lab_copy[b].start();
         }
         check(ctx, hipStreamSynchronize(xs.s), "stream synchronize");
         for (Copier& cp : lab_copy) cp.join();

@@ -177,7 +177,8 @@ def transfer_bench(ctx, f, torch, msc, reps=3):
 def out_of_core_bench(ctx, f, torch, msc, slab=64, reps=2):
     """ms_gradient_critical_chunked on the benchmark field held in host
     memory, streamed in z-slabs (copies of the next slab overlap the current
-    slab's kernels); whole-job rate including the host-to-device traffic."""
+    slab's kernels); whole-job rate including the host-to-device traffic.
+    Then ms_manifolds_chunked on the same field and slabs."""
     import numpy as np
     f = np.ascontiguousarray(f)
     ctx.gradient_critical_chunked(f, slab, want_grad=False)  # warm
@@ -185,9 +186,21 @@ def out_of_core_bench(ctx, f, torch, msc, slab=64, reps=2):
     for _ in range(reps):
         _, cid, idx, val, vmax, cnt = ctx.gradient_critical_chunked(f, slab, want_grad=False)
     ms = (time.perf_counter() - t0) / reps * 1e3
+    del cid, idx, val, vmax
+    # the manifold labels of the same field, stitched across the slabs
+    ctx.manifolds_chunked(f, slab)  # warm (pinned label staging)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lo, hi, cnt_l = ctx.manifolds_chunked(f, slab)
+        del lo, hi
+    ms_l = (time.perf_counter() - t0) / reps * 1e3
+    if cnt_l != cnt:
+        raise SystemExit(f"out-of-core label counts {cnt_l} differ from {cnt}")
     return {"slab_rows": slab, "ms_per_call": round(ms, 2), "mvox_s": round(f.size / ms / 1e3, 2),
             "h2d_gbs": round(4 * f.size * (slab + 3) / slab / (ms / 1e3) / 1e9, 2), "critical_counts": cnt,
-            "note": "host field in, critical list out (64-bit ids); counts equal the in-HBM run's"}
+            "labels_ms_per_call": round(ms_l, 2), "labels_mvox_s": round(f.size / ms_l / 1e3, 2),
+            "note": "host field in, critical list out (64-bit ids); counts equal the in-HBM run's; labels: "
+                    "ms_manifolds_chunked, both 64-bit label arrays out (16 bytes per vertex)"}
 
 
 def graph_bench(torch, msc, nthreads=16):

@@ -253,7 +253,8 @@ ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f, ms_dims di
  *   h_max_label : host, nx*ny*nz uint64: rank of the maximum reached from
  *                 the cube with lowest corner v, MS_LABEL_EXIT64 when there is
  *                 no such cube or its path leaves the grid, or NULL;
- *   h_count     : host, critical cells per index (the ranks' ranges).
+ *   h_count     : host, critical cells per index (the ranks' ranges);
+ *                 with both label pointers NULL only these are computed.
  * Errors: as ms_gradient_critical_chunked (no MS_ERR_CAPACITY);
  * MS_ERR_INTERNAL if a path between slabs does not end.  Synchronises the
  * context's stream; uses the host's threads for the stitching.  The

@@ -10,7 +10,8 @@
   prod_axes (m + M t) (m = 1D minima, M = interior 1D maxima; pinned against
   the oracle in tests/test_oracle_pins.py), its ids strictly increase, and
   each value is the field at the recorded highest vertex.
-* Non-finite input and too small an output are reported.
+* Non-finite input and too small an output are reported (and invalid
+  arguments and non-finite input to the label call).
 
 ms_manifolds_chunked (labels stitched across slabs, Section 3.4):
 
@@ -133,6 +134,24 @@ def test_errors(ctx):
     out = msc.Crit64(None, None, None, None, 0)
     st = lib.ms_gradient_critical_chunked(ctx._h, f.ctypes.data, msc.Dims(10, 9, 8), 3, None, C.byref(out), cnt)
     assert st == msc.MS_ERR_CAPACITY and sum(cnt) > 0
+    with pytest.raises(msc.MscError) as e:
+        ctx.manifolds_chunked(bad, 2)
+    assert e.value.status == msc.MS_ERR_NONFINITE
+    lo = np.empty(f.shape, np.uint64)
+    assert lib.ms_manifolds_chunked(ctx._h, f.ctypes.data, msc.Dims(10, 9, 0), 3, lo.ctypes.data, None,
+                                    cnt) == msc.MS_ERR_INVALID_ARG
+    assert lib.ms_manifolds_chunked(ctx._h, None, msc.Dims(10, 9, 8), 3, lo.ctypes.data, None,
+                                    cnt) == msc.MS_ERR_INVALID_ARG
+    # no label output: counts only
+    cnt2 = (C.c_int64 * 4)()
+    assert lib.ms_manifolds_chunked(ctx._h, f.ctypes.data, msc.Dims(10, 9, 8), 3, None, None, cnt2) == msc.MS_OK
+    assert list(cnt2) == O.critical(f, O.gradient(f)).count.tolist()
+    # the context still works after the errors
+    lo, hi, _ = ctx.manifolds_chunked(f, 3)
+    ref_g = O.gradient(f)
+    want_lo, want_hi = O.manifolds(f, ref_g, O.critical(f, ref_g))
+    np.testing.assert_array_equal(lo, want_lo.astype(np.uint64))
+    np.testing.assert_array_equal(hi, widen_exit(want_hi))
 
 
 @pytest.mark.parametrize("kind,dims,seed", CASES)

@@ -364,7 +364,7 @@ ms_status chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab, uin
         // the GPU works on the next slab
         Copier lab_copy[2];
         const bool staged = labels || h_grad;
-        const size_t lab_bytes = (labels ? 16 : 0) * (size_t)(slab * nxy) + (h_grad ? 4 : 0) * (size_t)(slab * nxy);
+        const size_t lab_bytes = (size_t)((labels ? 16 : 0) + (h_grad ? 4 : 0)) * (size_t)(slab * nxy);
         if (staged && ctx->h_lab_bytes < lab_bytes) {
             check(ctx, hipStreamSynchronize(cs), "stream synchronize");
             for (void*& p : ctx->h_lab) {

@@ -264,6 +264,42 @@ ms_status ms_gradient_critical_chunked(ms_ctx* ctx, const float* h_f, ms_dims di
 ms_status ms_manifolds_chunked(ms_ctx* ctx, const float* h_f, ms_dims dims, int64_t slab,
                                uint64_t* h_min_label, uint64_t* h_max_label, int64_t h_count[4]);
 
+/* A CSR matrix in host memory, caller-owned (out-of-core results). */
+typedef struct {
+    int64_t* rowptr;   /* nrows + 1 */
+    uint64_t* col;     /* capacity entries */
+    uint64_t* val;     /* capacity entries */
+    int64_t capacity;  /* entries available in col and val */
+    int64_t nnz;       /* out: entries of the matrix */
+} ms_csr64_host;
+
+/* Saddle-extremum arcs of an out-of-core field (Section 3.5, "Saddle-Extrema
+ * arcs"; Section 3.4: the arcs of a saddle end where the gradient paths from
+ * its two faces or cofaces go) from the labels of ms_manifolds_chunked and
+ * the saddles of ms_gradient_critical_chunked, on the host (the labels of
+ * such a field live in host memory):
+ *   M10  : row r = the 1-saddle s1_id[r]: the minima of its two vertices;
+ *   M32^T: row r = the 2-saddle s2_id[r]: the maxima of its two cubes
+ *          (a cube that does not exist or whose path leaves the grid gives
+ *          no entry);
+ * columns ascending, value 2 when both reach the same extremum, else 1 --
+ * the m10 and m32t of ms_complex on the whole field, with 64-bit columns.
+ *   dims        : the field's dims (limits as ms_gradient_critical_chunked).
+ *   h_min_label, h_max_label : host, nx*ny*nz labels (ms_manifolds_chunked).
+ *   s1_id, s2_id: host, the 1-saddle and 2-saddle cell ids (64-bit, as in
+ *                 ms_crit64), S1 and S2 of them, in rank order.
+ *   m10, m32t   : caller-owned outputs, or NULL (not computed, and its label
+ *                 array may be NULL); rowptr holds S + 1 entries, and a
+ *                 capacity of 2 S always suffices.
+ * No device work and no context: uses the host's threads.  Errors:
+ * MS_ERR_INVALID_ARG (null pointer where an output is asked for, an id that
+ * is not a cell of the right dimension in the grid, a minimum label that is
+ * the exit label), MS_ERR_TOO_LARGE, MS_ERR_CAPACITY (nnz written, entries
+ * not), MS_ERR_OOM. */
+ms_status ms_extremum_arcs_host(ms_dims dims, const uint64_t* h_min_label, const uint64_t* h_max_label,
+                                const uint64_t* s1_id, int64_t S1, const uint64_t* s2_id, int64_t S2,
+                                ms_csr64_host* m10, ms_csr64_host* m32t);
+
 /* A CSR matrix in device memory, context-owned. */
 typedef struct {
     int64_t nrows, ncols, nnz;

@@ -601,3 +601,121 @@ extern "C" ms_status ms_manifolds_chunked(ms_ctx* ctx, const float* h_f, ms_dims
                                           uint64_t* h_min_label, uint64_t* h_max_label, int64_t h_count[4]) {
     return chunked(ctx, h_f, dims, slab, nullptr, nullptr, h_count, h_min_label, h_max_label);
 }
+
+// Saddle-extremum arcs from the stitched labels (host): a 1-saddle's row of
+// M10 holds the minima of its two vertices, a 2-saddle's row of M32^T the
+// maxima of its two cubes (paths that leave the grid dropped); an arc
+// reached twice has multiplicity 2.  Two passes over the saddles (row
+// lengths, then entries) split over host threads.
+namespace {
+
+struct SaddleRow {
+    uint64_t c[2];
+    int n;  // distinct columns (0..2); c[0] < c[1]
+    uint64_t v0;  // multiplicity of c[0] when n == 1
+};
+
+bool arcs_host(ms_dims d, const uint64_t* lab, const uint64_t* ids, int64_t S, bool cubes, ms_csr64_host* out) {
+    const uint64_t nx = (uint64_t)d.nx, ny = (uint64_t)d.ny, nz = (uint64_t)d.nz, nxy = nx * ny, nv = nxy * nz;
+    const uint64_t n[3] = {nx, ny, nz}, stride[3] = {1, nx, nxy};
+    auto row = [&](int64_t r, SaddleRow& o) -> bool {
+        const uint64_t id = ids[r], v = id >> 3;
+        const uint32_t k = (uint32_t)(id & 7u);
+        if (v >= nv || __builtin_popcount(k) != (cubes ? 2 : 1)) return false;
+        const uint64_t c[3] = {v % nx, (v / nx) % ny, v / nxy};
+        for (int a = 0; a < 3; a++)
+            if (((k >> a) & 1u) && c[a] + 1 >= n[a]) return false;  // the cell must exist
+        uint64_t l[2];
+        int m = 0;
+        if (!cubes) {
+            const int a = __builtin_ctz(k);
+            l[0] = lab[v];
+            l[1] = lab[v + stride[a]];
+            if (l[0] == MS_LABEL_EXIT64 || l[1] == MS_LABEL_EXIT64) return false;
+            m = 2;
+        } else {
+            const int j = k == 3u ? 2 : (k == 5u ? 1 : 0);  // the quad's normal axis
+            const uint64_t e[2] = {c[j] + 1 < n[j] ? lab[v] : MS_LABEL_EXIT64,
+                                   c[j] >= 1 ? lab[v - stride[j]] : MS_LABEL_EXIT64};
+            for (uint64_t x : e)
+                if (x != MS_LABEL_EXIT64) l[m++] = x;
+        }
+        if (m == 2 && l[0] == l[1]) {
+            o.n = 1;
+            o.c[0] = l[0];
+            o.v0 = 2;
+        } else {
+            o.n = m;
+            o.v0 = 1;
+            o.c[0] = m == 2 ? std::min(l[0], l[1]) : l[0];
+            o.c[1] = m == 2 ? std::max(l[0], l[1]) : 0;
+        }
+        return true;
+    };
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::atomic<bool> ok{true};
+    auto run = [&](auto&& body) {
+        std::vector<std::thread> th;
+        const int64_t per = (S + hw - 1) / hw;
+        for (unsigned t = 0; t < hw; t++) {
+            const int64_t a = t * per, b = std::min<int64_t>(S, a + per);
+            if (a >= b) break;
+            th.emplace_back([&, a, b] { body(a, b); });
+        }
+        for (auto& x : th) x.join();
+    };
+    out->rowptr[0] = 0;
+    run([&](int64_t a, int64_t b) {
+        SaddleRow o;
+        for (int64_t r = a; r < b; r++) {
+            if (!row(r, o)) {
+                ok = false;
+                return;
+            }
+            out->rowptr[r + 1] = o.n;
+        }
+    });
+    if (!ok) return false;
+    for (int64_t r = 0; r < S; r++) out->rowptr[r + 1] += out->rowptr[r];
+    out->nnz = out->rowptr[S];
+    if (out->nnz > out->capacity) return true;  // the caller sees nnz > capacity
+    run([&](int64_t a, int64_t b) {
+        SaddleRow o;
+        for (int64_t r = a; r < b; r++) {
+            row(r, o);
+            const int64_t p = out->rowptr[r];
+            for (int i = 0; i < o.n; i++) {
+                out->col[p + i] = o.c[i];
+                out->val[p + i] = o.v0;
+            }
+        }
+    });
+    return true;
+}
+
+}  // namespace
+
+extern "C" ms_status ms_extremum_arcs_host(ms_dims dims, const uint64_t* h_min_label, const uint64_t* h_max_label,
+                                           const uint64_t* s1_id, int64_t S1, const uint64_t* s2_id, int64_t S2,
+                                           ms_csr64_host* m10, ms_csr64_host* m32t) {
+    if (dims.nx < 1 || dims.ny < 1 || dims.nz < 1 || S1 < 0 || S2 < 0) return MS_ERR_INVALID_ARG;
+    if (dims.nx > (1 << 29) || dims.ny > (1 << 29) || dims.nx * dims.ny > ((int64_t)1 << 29) ||
+        dims.nz > ((int64_t)1 << 40) / (dims.nx * dims.ny))
+        return MS_ERR_TOO_LARGE;
+    try {
+        for (int which = 0; which < 2; which++) {
+            ms_csr64_host* o = which == 0 ? m10 : m32t;
+            if (!o) continue;
+            const uint64_t* lab = which == 0 ? h_min_label : h_max_label;
+            const uint64_t* ids = which == 0 ? s1_id : s2_id;
+            const int64_t S = which == 0 ? S1 : S2;
+            if (!lab || !o->rowptr || (S > 0 && !ids) || o->capacity < 0 || (o->capacity > 0 && (!o->col || !o->val)))
+                return MS_ERR_INVALID_ARG;
+            if (!arcs_host(dims, lab, ids, S, which == 1, o)) return MS_ERR_INVALID_ARG;
+        }
+        if ((m10 && m10->nnz > m10->capacity) || (m32t && m32t->nnz > m32t->capacity)) return MS_ERR_CAPACITY;
+    } catch (const std::exception&) {
+        return MS_ERR_OOM;
+    }
+    return MS_OK;
+}

@@ -25,7 +25,7 @@ EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_err
             "ms_graph_build", "ms_graph_build_host", "ms_graph_destroy", "ms_graph_num_nodes", "ms_graph_last_error",
             "ms_graph_node", "ms_graph_find", "ms_graph_arcs", "ms_graph_counts", "ms_graph_simplify",
             "ms_graph_num_cancellations", "ms_graph_cancellations", "ms_gradient_critical_chunked",
-            "ms_manifolds_chunked"]
+            "ms_manifolds_chunked", "ms_extremum_arcs_host"]
 LABEL_EXIT64 = 0xFFFFFFFFFFFFFFFF
 MS_DOWN, MS_UP = 0, 1
 MS_SIMPLIFY_SERIAL, MS_SIMPLIFY_SUBGRID = 0, 1
@@ -58,6 +58,11 @@ class Csr(C.Structure):
 class Crit64(C.Structure):
     _fields_ = [("id", C.c_void_p), ("index", C.c_void_p), ("value", C.c_void_p), ("vmax", C.c_void_p),
                 ("capacity", C.c_int64)]
+
+
+class Csr64Host(C.Structure):
+    _fields_ = [("rowptr", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p), ("capacity", C.c_int64),
+                ("nnz", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -149,6 +154,8 @@ def lib():
         L.ms_ctx_release.argtypes = [vp]
         L.ms_gradient_critical_chunked.argtypes = [vp, vp, Dims, i64, vp, C.POINTER(Crit64), C.POINTER(i64)]
         L.ms_manifolds_chunked.argtypes = [vp, vp, Dims, i64, vp, vp, C.POINTER(i64)]
+        L.ms_extremum_arcs_host.argtypes = [Dims, vp, vp, vp, i64, vp, i64, C.POINTER(Csr64Host),
+                                            C.POINTER(Csr64Host)]
         L.ms_graph_build.argtypes = [vp, C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
         L.ms_graph_build_host.argtypes = [C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
         L.ms_graph_destroy.argtypes = [vp]
@@ -172,6 +179,33 @@ def lib():
 
 
 _hip = None
+
+
+def extremum_arcs_host(dims, min_label, max_label, s1_id, s2_id):
+    """ms_extremum_arcs_host: (M10, M32^T) of a field from its 64-bit labels
+    (host numpy, e.g. Context.manifolds_chunked) and its 1- and 2-saddle
+    ids (host numpy uint64, e.g. from Context.gradient_critical_chunked);
+    each matrix as (rowptr int64, col uint64, val uint64).  dims = (nx, ny,
+    nz)."""
+    import numpy as np
+    out = []
+    mats = []
+    keep = []
+    for ids, lab in ((s1_id, min_label), (s2_id, max_label)):
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        lab = np.ascontiguousarray(lab, dtype=np.uint64)
+        cap = max(2 * len(ids), 1)
+        arrs = (np.zeros(len(ids) + 1, np.int64), np.empty(cap, np.uint64), np.empty(cap, np.uint64))
+        keep.append((ids, lab))
+        mats.append(Csr64Host(arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data, cap, 0))
+        out.append(arrs)
+    (i1, l1), (i2, l2) = keep
+    st = lib().ms_extremum_arcs_host(Dims(*[int(x) for x in dims]), l1.ctypes.data, l2.ctypes.data,
+                                     i1.ctypes.data, len(i1), i2.ctypes.data, len(i2), C.byref(mats[0]),
+                                     C.byref(mats[1]))
+    if st != MS_OK:
+        raise MscError(st, "ms_extremum_arcs_host")
+    return tuple((rp, col[:m.nnz], val[:m.nnz]) for (rp, col, val), m in zip(out, mats))
 
 
 def _hip_rt():

@@ -17,8 +17,9 @@ ms_manifolds_chunked (labels stitched across slabs, Section 3.4):
 
 * The same small fields and slab heights: both labels equal the oracle's
   (widened to 64 bits, its exit label to all ones) word for word.
-* The 512^3 blobs field in slabs of 100 rows: the labels equal those of
-  ms_complex on the whole field in HBM.
+* The 512^3 blobs field in slabs of 100 rows: the labels, and the
+  saddle-extremum arcs ms_extremum_arcs_host assembles from them, equal
+  those of ms_complex on the whole field in HBM.
 * The 1024 x 1024 x 600 field above (beyond 32-bit cell ids, so no in-HBM
   run and no oracle run to compare with): the labels form the forest the
   gradient defines -- every minimum and maximum labels itself with its rank,
@@ -185,6 +186,8 @@ def test_labels_after_release_and_regrowth(ctx):
 
 
 def test_labels_equal_in_hbm_512(ctx):
+    """Labels and, from them, the saddle-extremum arcs (ms_extremum_arcs_host
+    on the out-of-core saddles) equal those of the in-HBM run."""
     from gpu_util import to_dev
     from paper_2009_03707_amd import msc
     f = fields.blob_field((512, 512, 512), nblobs=64, seed=0)
@@ -192,10 +195,20 @@ def test_labels_equal_in_hbm_512(ctx):
     got = msc.complex_(to_dev(f), ctx)
     want_lo = got.min_label.cpu().numpy().view(np.uint32).reshape(f.shape)
     want_hi = got.max_label.cpu().numpy().view(np.uint32).reshape(f.shape)
+    want = [(m.rowptr.cpu().numpy(), m.col.cpu().numpy().view(np.uint32), m.val.cpu().numpy().view(np.uint64))
+            for m in (got.m10, got.m32t)]
     del got
     lo, hi, cnt = ctx.manifolds_chunked(f, 100)
     np.testing.assert_array_equal(lo, want_lo.astype(np.uint64))
     np.testing.assert_array_equal(hi, widen_exit(want_hi))
+    _, cid, _, _, _, cnt2 = ctx.gradient_critical_chunked(f, 100, want_grad=False)
+    assert cnt2 == cnt
+    off = np.cumsum([0] + cnt)
+    arcs = msc.extremum_arcs_host(f.shape[::-1], lo, hi, cid[off[1]:off[2]], cid[off[2]:off[3]])
+    for (rp, col, val), (w_rp, w_col, w_val) in zip(arcs, want):
+        np.testing.assert_array_equal(rp, w_rp)
+        np.testing.assert_array_equal(col, w_col.astype(np.uint64))
+        np.testing.assert_array_equal(val, w_val)
 
 
 def test_labels_beyond_32bit_cell_ids(ctx):
@@ -215,6 +228,16 @@ def test_labels_beyond_32bit_cell_ids(ctx):
     off = np.cumsum([0] + cnt)
     vmin = (cid[off[0]:off[1]] >> np.uint64(3)).astype(np.int64)
     vmax = (cid[off[3]:off[4]] >> np.uint64(3)).astype(np.int64)
+    # saddle-extremum arcs: every 1-saddle reaches minima twice, a 2-saddle
+    # maxima at most twice, columns ascending within a row
+    from paper_2009_03707_amd import msc
+    (rp1, c1, v1), (rp2, c2, v2) = msc.extremum_arcs_host((nx, ny, nz), lo, hi, cid[off[1]:off[2]],
+                                                          cid[off[2]:off[3]])
+    assert (np.add.reduceat(v1, rp1[:-1]) == 2).all() and int(c1.max()) < cnt[0]
+    assert (np.diff(rp2) <= 2).all() and (c2 < np.uint64(cnt[3])).all()
+    for rp, c in ((rp1, c1), (rp2, c2)):
+        two = np.flatnonzero(np.diff(rp) == 2)
+        assert (c[rp[two]] < c[rp[two] + 1]).all()
     del cid, idx
     # roots: each extremum labels itself with its rank
     np.testing.assert_array_equal(lo.reshape(-1)[vmin], np.arange(len(vmin), dtype=np.uint64))

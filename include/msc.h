@@ -300,6 +300,18 @@ ms_status ms_extremum_arcs_host(ms_dims dims, const uint64_t* h_min_label, const
                                 const uint64_t* s1_id, int64_t S1, const uint64_t* s2_id, int64_t S2,
                                 ms_csr64_host* m10, ms_csr64_host* m32t);
 
+/* Transpose of a host CSR (e.g. M10 -> M10^T = minimum x 1-saddle, M32^T ->
+ * M32 = maximum x 2-saddle, as ms_complex gives them), by a counting sort
+ * on the host: out row c lists the input rows holding column c, ascending,
+ * with their values.
+ *   in    : nrows + 1 rowptr entries (rowptr[0] = 0, non-decreasing),
+ *           columns < ncols.
+ *   out   : caller-owned; rowptr holds ncols + 1 entries; capacity >=
+ *           in's nnz (out->nnz is written first).
+ * Errors: MS_ERR_INVALID_ARG (null pointers, a malformed input),
+ * MS_ERR_CAPACITY, MS_ERR_OOM. */
+ms_status ms_csr64_transpose_host(const ms_csr64_host* in, int64_t nrows, int64_t ncols, ms_csr64_host* out);
+
 /* A CSR matrix in device memory, context-owned. */
 typedef struct {
     int64_t nrows, ncols, nnz;

@@ -719,3 +719,35 @@ extern "C" ms_status ms_extremum_arcs_host(ms_dims dims, const uint64_t* h_min_l
     }
     return MS_OK;
 }
+
+extern "C" ms_status ms_csr64_transpose_host(const ms_csr64_host* in, int64_t nrows, int64_t ncols,
+                                             ms_csr64_host* out) {
+    if (!in || !out || nrows < 0 || ncols < 0 || !in->rowptr || !out->rowptr) return MS_ERR_INVALID_ARG;
+    const int64_t nnz = in->rowptr[nrows];
+    if (in->rowptr[0] != 0 || nnz < 0 || (nnz > 0 && (!in->col || !in->val))) return MS_ERR_INVALID_ARG;
+    for (int64_t r = 0; r < nrows; r++)
+        if (in->rowptr[r + 1] < in->rowptr[r]) return MS_ERR_INVALID_ARG;
+    for (int64_t p = 0; p < nnz; p++)
+        if (in->col[p] >= (uint64_t)ncols) return MS_ERR_INVALID_ARG;
+    out->nnz = nnz;
+    if (nnz > out->capacity) return MS_ERR_CAPACITY;
+    if (nnz > 0 && (!out->col || !out->val)) return MS_ERR_INVALID_ARG;
+    // counting sort by column; rows are visited in order, so each output row
+    // lists its columns (the input rows) ascending
+    int64_t* rp = out->rowptr;
+    std::fill(rp, rp + ncols + 1, (int64_t)0);
+    for (int64_t p = 0; p < nnz; p++) rp[in->col[p] + 1]++;
+    for (int64_t c = 0; c < ncols; c++) rp[c + 1] += rp[c];
+    try {
+        std::vector<int64_t> next(rp, rp + ncols);
+        for (int64_t r = 0; r < nrows; r++)
+            for (int64_t p = in->rowptr[r]; p < in->rowptr[r + 1]; p++) {
+                const int64_t q = next[in->col[p]]++;
+                out->col[q] = (uint64_t)r;
+                out->val[q] = in->val[p];
+            }
+    } catch (const std::exception&) {
+        return MS_ERR_OOM;
+    }
+    return MS_OK;
+}

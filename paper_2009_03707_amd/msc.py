@@ -25,7 +25,7 @@ EXPORTED = ["ms_ctx_create", "ms_ctx_destroy", "ms_ctx_set_stream", "ms_last_err
             "ms_graph_build", "ms_graph_build_host", "ms_graph_destroy", "ms_graph_num_nodes", "ms_graph_last_error",
             "ms_graph_node", "ms_graph_find", "ms_graph_arcs", "ms_graph_counts", "ms_graph_simplify",
             "ms_graph_num_cancellations", "ms_graph_cancellations", "ms_gradient_critical_chunked",
-            "ms_manifolds_chunked", "ms_extremum_arcs_host"]
+            "ms_manifolds_chunked", "ms_extremum_arcs_host", "ms_csr64_transpose_host"]
 LABEL_EXIT64 = 0xFFFFFFFFFFFFFFFF
 MS_DOWN, MS_UP = 0, 1
 MS_SIMPLIFY_SERIAL, MS_SIMPLIFY_SUBGRID = 0, 1
@@ -156,6 +156,7 @@ def lib():
         L.ms_manifolds_chunked.argtypes = [vp, vp, Dims, i64, vp, vp, C.POINTER(i64)]
         L.ms_extremum_arcs_host.argtypes = [Dims, vp, vp, vp, i64, vp, i64, C.POINTER(Csr64Host),
                                             C.POINTER(Csr64Host)]
+        L.ms_csr64_transpose_host.argtypes = [C.POINTER(Csr64Host), i64, i64, C.POINTER(Csr64Host)]
         L.ms_graph_build.argtypes = [vp, C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
         L.ms_graph_build_host.argtypes = [C.POINTER(Result), Dims, C.c_int, C.POINTER(vp)]
         L.ms_graph_destroy.argtypes = [vp]
@@ -206,6 +207,22 @@ def extremum_arcs_host(dims, min_label, max_label, s1_id, s2_id):
     if st != MS_OK:
         raise MscError(st, "ms_extremum_arcs_host")
     return tuple((rp, col[:m.nnz], val[:m.nnz]) for (rp, col, val), m in zip(out, mats))
+
+
+def csr64_transpose_host(csr, ncols: int):
+    """ms_csr64_transpose_host of a host CSR (rowptr int64, col uint64, val
+    uint64) with `ncols` columns; returns the transpose in the same form."""
+    import numpy as np
+    rp, col, val = (np.ascontiguousarray(csr[0], np.int64), np.ascontiguousarray(csr[1], np.uint64),
+                    np.ascontiguousarray(csr[2], np.uint64))
+    nnz = int(rp[-1])
+    out = (np.zeros(int(ncols) + 1, np.int64), np.empty(max(nnz, 1), np.uint64), np.empty(max(nnz, 1), np.uint64))
+    src = Csr64Host(rp.ctypes.data, col.ctypes.data, val.ctypes.data, len(col), nnz)
+    dst = Csr64Host(out[0].ctypes.data, out[1].ctypes.data, out[2].ctypes.data, max(nnz, 1), 0)
+    st = lib().ms_csr64_transpose_host(C.byref(src), len(rp) - 1, int(ncols), C.byref(dst))
+    if st != MS_OK:
+        raise MscError(st, "ms_csr64_transpose_host")
+    return out[0], out[1][:nnz], out[2][:nnz]
 
 
 def _hip_rt():

@@ -2,7 +2,9 @@
 Section 3.5 "Saddle-Extrema arcs", assembled on the host from stitched
 labels) runs without a GPU: from the oracle's labels and saddles it must
 give the oracle's M10 and the transpose of its M32 entry for entry, and it
-must reject ids and labels that are not those of a field of the given dims."""
+must reject ids and labels that are not those of a field of the given dims.
+ms_csr64_transpose_host turns them into M10^T and M32, equal to the
+oracle's."""
 import numpy as np
 import pytest
 
@@ -63,6 +65,44 @@ def test_equals_oracle(msc, kind, dims, seed):
     np.testing.assert_array_equal(rp2, w_rp)
     np.testing.assert_array_equal(c2, w_c)
     np.testing.assert_array_equal(v2, w_v)
+
+
+@pytest.mark.parametrize("kind,dims,seed", FIELDS)
+def test_transposes_equal_oracle(msc, kind, dims, seed):
+    """M10^T and M32 by ms_csr64_transpose_host: the oracle's M10 transposed
+    and its M32 as they are."""
+    f = _field(kind, dims, seed)
+    ref, d, lo, hi, s1, s2 = _inputs(f)
+    m10, m32t = msc.extremum_arcs_host(d, lo, hi, s1, s2)
+    cnt = ref.crit.count.tolist()
+    for got, want in ((msc.csr64_transpose_host(m10, cnt[0]), _csr_t(ref.m10)),
+                      (msc.csr64_transpose_host(m32t, cnt[3]), ref.m32.csr())):
+        for g, w in zip(got, want):
+            np.testing.assert_array_equal(g, w.astype(g.dtype))
+
+
+def test_transpose_errors(msc):
+    import ctypes as C
+    lib = msc.lib()
+    rp = np.array([0, 2, 3], np.int64)
+    col = np.array([0, 4, 1], np.uint64)
+    val = np.array([1, 1, 2], np.uint64)
+    # column 4 beyond ncols = 3
+    with pytest.raises(msc.MscError):
+        msc.csr64_transpose_host((rp, col, val), 3)
+    rp_t, col_t, val_t = msc.csr64_transpose_host((rp, col, val), 5)
+    np.testing.assert_array_equal(rp_t, [0, 1, 2, 2, 2, 3])
+    np.testing.assert_array_equal(col_t, [0, 1, 0])
+    np.testing.assert_array_equal(val_t, [1, 2, 1])
+    bad_rp = np.array([0, 2, 1], np.int64)
+    with pytest.raises(msc.MscError):
+        msc.csr64_transpose_host((bad_rp, col, val), 5)
+    out_rp = np.zeros(6, np.int64)
+    one = np.empty(1, np.uint64)
+    src = msc.Csr64Host(rp.ctypes.data, col.ctypes.data, val.ctypes.data, 3, 3)
+    dst = msc.Csr64Host(out_rp.ctypes.data, one.ctypes.data, one.ctypes.data, 1, 0)
+    assert lib.ms_csr64_transpose_host(C.byref(src), 2, 5, C.byref(dst)) == msc.MS_ERR_CAPACITY and dst.nnz == 3
+    assert lib.ms_csr64_transpose_host(None, 2, 5, C.byref(dst)) == msc.MS_ERR_INVALID_ARG
 
 
 def test_errors(msc):

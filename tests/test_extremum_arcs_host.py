@@ -143,3 +143,20 @@ def test_errors(msc):
                                      C.byref(m10), None) == msc.MS_ERR_INVALID_ARG
     assert lib.ms_extremum_arcs_host(msc.Dims(0, 1, 1), None, None, None, 0, None, 0, None,
                                      None) == msc.MS_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_small_fields(msc, seed):
+    """Small fields of random dims (1..12 per axis), with ties from 0..2
+    quantisation levels: all four matrices equal the oracle's."""
+    rng = np.random.default_rng(7000 + seed)
+    dims = tuple(int(x) for x in rng.integers(1, 13, size=3))
+    f = fields.random_field(dims, seed=seed, levels=seed % 3)
+    ref, d, lo, hi, s1, s2 = _inputs(f)
+    m10, m32t = msc.extremum_arcs_host(d, lo, hi, s1, s2)
+    cnt = ref.crit.count.tolist()
+    pairs = [(m10, ref.m10.csr()), (m32t, _csr_t(ref.m32)), (msc.csr64_transpose_host(m10, cnt[0]), _csr_t(ref.m10)),
+             (msc.csr64_transpose_host(m32t, cnt[3]), ref.m32.csr())]
+    for got, want in pairs:
+        for g, w in zip(got, want):
+            np.testing.assert_array_equal(g, w.astype(g.dtype))

@@ -732,20 +732,82 @@ extern "C" ms_status ms_csr64_transpose_host(const ms_csr64_host* in, int64_t nr
     out->nnz = nnz;
     if (nnz > out->capacity) return MS_ERR_CAPACITY;
     if (nnz > 0 && (!out->col || !out->val)) return MS_ERR_INVALID_ARG;
-    // counting sort by column; rows are visited in order, so each output row
-    // lists its columns (the input rows) ascending
+    // A counting sort by column in two levels, so that no pass scatters over
+    // all columns at once: the entries go to buckets of adjacent columns
+    // (threads over equal shares of the entries, each keeping row order),
+    // then each bucket is sorted by column on its own (threads over
+    // buckets).  Both levels are stable, so each output row lists its
+    // columns (the input rows) ascending.
     int64_t* rp = out->rowptr;
-    std::fill(rp, rp + ncols + 1, (int64_t)0);
-    for (int64_t p = 0; p < nnz; p++) rp[in->col[p] + 1]++;
-    for (int64_t c = 0; c < ncols; c++) rp[c + 1] += rp[c];
+    if (ncols == 0) {
+        rp[0] = 0;
+        return MS_OK;
+    }
     try {
-        std::vector<int64_t> next(rp, rp + ncols);
-        for (int64_t r = 0; r < nrows; r++)
-            for (int64_t p = in->rowptr[r]; p < in->rowptr[r + 1]; p++) {
-                const int64_t q = next[in->col[p]]++;
-                out->col[q] = (uint64_t)r;
-                out->val[q] = in->val[p];
+        const int64_t T = std::max<int64_t>(1, std::min<int64_t>(std::min(16u, std::max(1u,
+                                                 std::thread::hardware_concurrency())), nnz / 65536 + 1));
+        const int64_t width = std::max<int64_t>(1, (ncols + 4095) / 4096);  // columns per bucket
+        const int64_t nb = (ncols + width - 1) / width;
+        std::vector<int64_t> rlo(T + 1);  // thread t takes rows [rlo[t], rlo[t+1])
+        for (int64_t t = 0; t <= T; t++)
+            rlo[t] = std::upper_bound(in->rowptr, in->rowptr + nrows + 1, t * nnz / T) - in->rowptr - 1;
+        rlo[0] = 0;
+        rlo[T] = nrows;
+        std::vector<int64_t> cnt((size_t)(T * nb), 0);
+        auto par = [&](int64_t n, auto&& body) {
+            std::vector<std::thread> th;
+            for (int64_t t = 0; t < std::min(n, T); t++)
+                th.emplace_back([&, t] {
+                    for (int64_t i = t; i < n; i += T) body(i);
+                });
+            for (auto& x : th) x.join();
+        };
+        par(T, [&](int64_t t) {
+            int64_t* c = &cnt[(size_t)(t * nb)];
+            for (int64_t p = in->rowptr[rlo[t]]; p < in->rowptr[rlo[t + 1]]; p++) c[in->col[p] / width]++;
+        });
+        std::vector<int64_t> bstart((size_t)nb + 1);
+        int64_t run = 0;
+        for (int64_t q = 0; q < nb; q++) {
+            bstart[(size_t)q] = run;
+            for (int64_t t = 0; t < T; t++) {
+                const int64_t v = cnt[(size_t)(t * nb + q)];
+                cnt[(size_t)(t * nb + q)] = run;
+                run += v;
             }
+        }
+        bstart[(size_t)nb] = run;
+        // not zeroed: the scatter below writes every entry (and faults the pages in on its threads)
+        std::unique_ptr<int64_t[]> trow(new int64_t[(size_t)nnz]);
+        std::unique_ptr<uint64_t[]> tcol(new uint64_t[(size_t)nnz]), tval(new uint64_t[(size_t)nnz]);
+        par(T, [&](int64_t t) {
+            int64_t* o = &cnt[(size_t)(t * nb)];
+            for (int64_t r = rlo[t]; r < rlo[t + 1]; r++)
+                for (int64_t p = in->rowptr[r]; p < in->rowptr[r + 1]; p++) {
+                    const int64_t q = o[in->col[p] / width]++;
+                    trow[(size_t)q] = r;
+                    tcol[(size_t)q] = in->col[p];
+                    tval[(size_t)q] = in->val[p];
+                }
+        });
+        par(nb, [&](int64_t q) {
+            const int64_t c0 = q * width, c1 = std::min(ncols, c0 + width);
+            std::vector<int64_t> next((size_t)(c1 - c0), 0);
+            for (int64_t p = bstart[(size_t)q]; p < bstart[(size_t)q + 1]; p++) next[(size_t)(tcol[(size_t)p] - c0)]++;
+            int64_t at = bstart[(size_t)q];
+            for (int64_t c = c0; c < c1; c++) {
+                rp[c] = at;
+                const int64_t v = next[(size_t)(c - c0)];
+                next[(size_t)(c - c0)] = at;
+                at += v;
+            }
+            for (int64_t p = bstart[(size_t)q]; p < bstart[(size_t)q + 1]; p++) {
+                const int64_t d = next[(size_t)(tcol[(size_t)p] - c0)]++;
+                out->col[d] = (uint64_t)trow[(size_t)p];
+                out->val[d] = tval[(size_t)p];
+            }
+        });
+        rp[ncols] = nnz;
     } catch (const std::exception&) {
         return MS_ERR_OOM;
     }
